@@ -1,0 +1,255 @@
+"""FP64 CPU oracle of the MAFOD hot path -- TEST INFRASTRUCTURE ONLY.
+
+A plain, slow, double-precision reference written from the paper
+(multi-scale anisotropic fourth-order diffusion, FED integration). It is
+what the GPU library is checked against and must never be on the product
+path: only tests/, ``__graft_entry__.smoke()`` and the ``cpu_baseline``
+leg of ``bench.py`` may import it. It shares no code with
+``paper_1611_06906_amd`` and does not import it.
+
+The arithmetic lives in ``mf4d_oracle.c`` (built with gcc, -O2,
+-ffp-contract=off, OpenMP over pixel rows); this module only marshals
+numpy arrays through ctypes.
+
+Parity pins: every function here is pinned by tests/test_oracle_*.py
+against closed forms, invariants, brute force on tiny inputs or library
+routines (numpy.linalg, numpy.convolve). No function is "parity unpinned".
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mf4d_oracle.c")
+_LIB = os.path.join(_HERE, "libmf4d_oracle.so")
+
+RIDGE, VALLEY, BOTH = 0, 1, 2
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no GPU involved)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fopenmp",
+               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib = ctypes.CDLL(_LIB)
+        _declare(_lib)
+    return _lib
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+
+
+def _declare(L):
+    L.ref_fed_n.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_double]
+    L.ref_fed_n.restype = ctypes.c_int
+    L.ref_fed_taus.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp]
+    L.ref_kappa_order.argtypes = [ctypes.c_int, _dp, ctypes.c_double, _ip, _dp]
+    L.ref_kappa_order.restype = ctypes.c_int
+    L.ref_fed_schedule.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _ip]
+    L.ref_fed_schedule.restype = ctypes.c_int
+    L.ref_gauss_taps.argtypes = [ctypes.c_double, _dp]
+    L.ref_gauss_taps.restype = ctypes.c_int
+    L.ref_gauss_radius.argtypes = [ctypes.c_double]
+    L.ref_gauss_radius.restype = ctypes.c_int
+    L.ref_blur.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp]
+    L.ref_derivatives.argtypes = [_dp, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp, _dp]
+    L.ref_scale_select.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
+                                   ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                   _u8p, _dp, _dp, _dp, _dp]
+    L.ref_scale_select.restype = ctypes.c_int
+    L.ref_tensor.argtypes = [_dp, ctypes.c_int, ctypes.c_int, _u8p, ctypes.c_int, _dp,
+                             ctypes.c_double, _dp]
+    L.ref_tensor.restype = ctypes.c_int
+    L.ref_dtensor_px.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_int, _dp, _dp, _dp]
+    L.ref_dtensor.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp]
+    L.ref_apply_P.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_int, _dp]
+    L.ref_explicit_step.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double]
+    L.ref_fed_cycle.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int]
+    L.ref_filter.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_int,
+                             ctypes.c_int, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                             ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                             ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                             _u8p, _dp, _dp, _dp]
+    L.ref_filter.restype = ctypes.c_int
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _null(t):
+    return ctypes.cast(None, t)
+
+
+# ---------------------------------------------------------------- schedule
+def fed_n(T, M, tau_max=0.05):
+    """Eq. (22)."""
+    return lib().ref_fed_n(float(T), int(M), float(tau_max))
+
+
+def fed_taus(n, T, M):
+    """Eq. (23), natural order."""
+    out = np.zeros(n)
+    lib().ref_fed_taus(int(n), float(T), int(M), _d(out))
+    return out
+
+
+def kappa_order(tau, tau_max=0.05):
+    tau = _f64(tau)
+    n = len(tau)
+    perm = np.zeros(n, np.int32)
+    ordered = np.zeros(n)
+    k = lib().ref_kappa_order(n, _d(tau), float(tau_max), perm.ctypes.data_as(_ip), _d(ordered))
+    return k, perm, ordered
+
+
+def fed_schedule(n, tau_max=0.05):
+    """Ordered steps of one cycle for given n. Returns (ordered, perm, kappa)."""
+    perm = np.zeros(n, np.int32)
+    ordered = np.zeros(n)
+    k = lib().ref_fed_schedule(int(n), float(tau_max), _d(ordered), perm.ctypes.data_as(_ip))
+    return ordered, perm, k
+
+
+# ---------------------------------------------------------------- scale space
+def gauss_taps(sigma):
+    r = lib().ref_gauss_radius(float(sigma))
+    g = np.zeros(2 * r + 1)
+    lib().ref_gauss_taps(float(sigma), _d(g))
+    return g
+
+
+def blur(u, sigma):
+    u = _f64(u)
+    H, W = u.shape
+    out = np.zeros_like(u)
+    lib().ref_blur(_d(u), H, W, float(sigma), _d(out))
+    return out
+
+
+def derivatives(v):
+    """(ux, uy, uxx, uxy, uyy) of an already smoothed image."""
+    v = _f64(v)
+    H, W = v.shape
+    outs = [np.zeros_like(v) for _ in range(5)]
+    lib().ref_derivatives(_d(v), H, W, *[_d(o) for o in outs])
+    return tuple(outs)
+
+
+def scale_select(u, sigmas, mode, beta=0.5, c=-1.0):
+    """Returns dict(idx, V, S, vmax, c)."""
+    u = _f64(u)
+    H, W = u.shape
+    sig = _f64(np.asarray(sigmas, dtype=np.float32))  # scales as the GPU receives them
+    ns = len(sig)
+    idx = np.zeros((H, W), np.uint8)
+    V = np.zeros((ns, H, W))
+    S = np.zeros((ns, H, W))
+    vmax = np.zeros((H, W))
+    cc = np.zeros(1)
+    lib().ref_scale_select(_d(u), H, W, ns, _d(sig), int(mode), float(beta), float(c),
+                           idx.ctypes.data_as(_u8p), _d(V), _d(S), _d(vmax), _d(cc))
+    return dict(idx=idx, V=V, S=S, vmax=vmax, c=float(cc[0]))
+
+
+def tensor(u, idx, sigmas, rho=0.5):
+    """H_rho planes (3, H, W) = (a, b, d)."""
+    u = _f64(u)
+    H, W = u.shape
+    sig = _f64(np.asarray(sigmas, dtype=np.float32))
+    idx = np.ascontiguousarray(idx, dtype=np.uint8)
+    out = np.zeros((3, H, W))
+    lib().ref_tensor(_d(u), H, W, idx.ctypes.data_as(_u8p), len(sig), _d(sig), float(rho), _d(out))
+    return out
+
+
+def dtensor_px(a, b, d, lam, mode):
+    D = np.zeros(16)
+    e = np.zeros(4)
+    mu = np.zeros(4)
+    lib().ref_dtensor_px(float(a), float(b), float(d), float(lam), int(mode), _d(D), _d(e), _d(mu))
+    return D.reshape(4, 4), e, mu
+
+
+def dtensor(hrho, lam, mode):
+    hrho = _f64(hrho)
+    _, H, W = hrho.shape
+    out = np.zeros((H, W, 16))
+    lib().ref_dtensor(_d(hrho), H, W, float(lam), int(mode), _d(out))
+    return out
+
+
+def apply_P(u, D):
+    u = _f64(u)
+    D = _f64(D)
+    H, W = u.shape
+    r = np.zeros_like(u)
+    lib().ref_apply_P(_d(u), _d(D), H, W, _d(r))
+    return r
+
+
+def explicit_step(u, D, tau):
+    u = _f64(u).copy()
+    H, W = u.shape
+    lib().ref_explicit_step(_d(u), _d(_f64(D)), H, W, float(tau))
+    return u
+
+
+def fed_cycle(u, D, ordered_tau):
+    u = _f64(u).copy()
+    H, W = u.shape
+    t = _f64(ordered_tau)
+    lib().ref_fed_cycle(_d(u), _d(_f64(D)), H, W, _d(t), len(t))
+    return u
+
+
+def filter(u, sigmas, mode, lam=0.005, rho=0.5, beta=0.5, c=-1.0, cycles=1, substeps=10,
+           stop_time=0.0, tau_max=0.05, reselect=1, record=False):
+    """The whole filter. Returns u_out, or (u_out, records) if record."""
+    u = _f64(u)
+    H, W = u.shape
+    sig = _f64(np.asarray(sigmas, dtype=np.float32))
+    out = np.zeros_like(u)
+    lam32 = float(np.float32(lam))
+    if record:
+        idx_rec = np.zeros((cycles, H, W), np.uint8)
+        c_rec = np.zeros(max(cycles, 1))
+        hrho_rec = np.zeros((cycles, 3, H, W))
+        u_rec = np.zeros((cycles, H, W))
+        args = (idx_rec.ctypes.data_as(_u8p), _d(c_rec), _d(hrho_rec), _d(u_rec))
+    else:
+        args = (_null(_u8p), _null(_dp), _null(_dp), _null(_dp))
+    n = lib().ref_filter(_d(u), _d(out), H, W, len(sig), _d(sig), int(mode), lam32,
+                         float(np.float32(rho)), float(np.float32(beta)), float(np.float32(c)),
+                         int(cycles), int(substeps), float(stop_time), float(tau_max), int(reselect),
+                         *args)
+    if n < 0:
+        raise ValueError("invalid schedule")
+    if record:
+        return out, dict(idx=idx_rec, c=c_rec[:cycles], hrho=hrho_rec, u=u_rec, n=n)
+    return out
