@@ -1,0 +1,185 @@
+/*
+ * mf4d -- multi-scale anisotropic fourth-order diffusion (MAFOD) on MI355X.
+ *
+ * C ABI of the GPU library libmf4d.so (HIP, gfx950). The library computes the
+ * hot path of the MAFOD ridge/valley filter: a per-pixel Gaussian scale chosen
+ * by Frangi vesselness, the normalised integrated Hessian at that scale, and
+ * Fast Explicit Diffusion (FED) cycles of the fourth-order anisotropic PDE.
+ * Section, equation and table numbers refer to the paper (arXiv:1611.06906).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Images are contiguous row-major float32 [H][W] in DEVICE memory, x = column
+ *    (the paper's index i), y = row (index j), pixel spacing 1. The caller owns
+ *    all buffers; the library never allocates or frees caller memory and keeps
+ *    no device memory of its own. Scratch space comes from a caller-provided
+ *    device workspace of at least mf4d_workspace_bytes() bytes.
+ *  - mf4d_params, its sigmas array and all double* schedule arrays are HOST
+ *    memory; they are read during the call only.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Device work is enqueued asynchronously on it; results are ready when the
+ *    stream is synchronised. Calls on different streams must use different
+ *    workspaces and outputs.
+ *  - Every function returns an int status (MF4D_OK = 0 or a negative code).
+ *    Arguments are validated on the host before anything is enqueued; on an
+ *    error nothing is enqueued. No exceptions cross the ABI.
+ *  - The library is stateless, hence thread-safe for distinct streams and
+ *    workspaces.
+ */
+#ifndef MF4D_H
+#define MF4D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MF4D_OK 0
+#define MF4D_EINVAL (-1)   /* invalid argument (checked before any launch)   */
+#define MF4D_ENOMEM (-2)   /* workspace smaller than mf4d_workspace_bytes()  */
+#define MF4D_EHIP (-3)     /* a HIP launch or runtime call failed            */
+
+/* Crease type to enhance (Sec. 3.2, text after Eq. (7); Sec. 3.3 Eq. (9)). */
+#define MF4D_RIDGE 0       /* mu_i = 1 where nu_i >= 0; V = 0 where nu~_2 > 0 */
+#define MF4D_VALLEY 1      /* mu_i = 1 where nu_i <= 0; V = 0 where nu~_2 < 0 */
+#define MF4D_BOTH 2        /* no mask, no sign test (the paper's default)    */
+
+#define MF4D_MAX_SCALES 16
+#define MF4D_MAX_RADIUS 64 /* Gaussian radius max(1, ceil(3 sigma)) limit   */
+#define MF4D_MAX_SUBSTEPS 1024
+
+/* Filter parameters, in the paper's notation.
+ *   nscales, sigmas  scale set {sigma_min..sigma_max} of Sec. 3.3; host array,
+ *                    strictly ascending, > 0, radius ceil(3 sigma) <= 64.
+ *   mode             MF4D_RIDGE / MF4D_VALLEY / MF4D_BOTH.
+ *   lambda           Perona-Malik contrast parameter of Eq. (7); > 0, +inf
+ *                    allowed (linear isotropic fourth-order diffusion).
+ *   rho              integration scale of Eq. (6); >= 0 (0: no integration).
+ *                    The paper uses 0.5.
+ *   beta, c          Frangi parameters of Eq. (9); beta > 0 (paper: 0.5);
+ *                    c <= 0 selects the paper's c = max(S)/2, taken over all
+ *                    scales and pixels of the image; c > 0 is used as given.
+ *   cycles           number of FED cycles M >= 0 (Eq. (21)).
+ *   substeps         n >= 1 substeps per cycle (then T/M = tau_max (n^2+n)/3),
+ *                    or 0 to derive n from stop_time by Eq. (22).
+ *   stop_time        diffusion stopping time T (used when substeps == 0).
+ *   tau_max          stable explicit step, 0 < tau_max <= 1/17 (Eq. (20)).
+ *   reselect_each_cycle  1: scales re-selected on u^k every cycle; 0: once on
+ *                    u^0 (the Hessian is still re-formed from u^k each cycle).
+ *   theta, postprocess   vessel threshold and scale-image postprocessing of
+ *                    Sec. 3.3; postprocessing is not part of this library and
+ *                    postprocess must be 0. theta is unused.
+ */
+typedef struct mf4d_params {
+    int nscales;
+    const float *sigmas;
+    int mode;
+    float lambda;
+    float rho;
+    float beta;
+    float c;
+    int cycles;
+    int substeps;
+    double stop_time;
+    double tau_max;
+    int reselect_each_cycle;
+    float theta;
+    int postprocess;
+} mf4d_params;
+
+/* Human-readable text for a status code. Never NULL. */
+const char *mf4d_status_string(int status);
+
+/* Fills *p with the paper's defaults (rho = beta = 0.5, c automatic,
+ * tau_max = 0.05, lambda = 0.005, BOTH, reselect each cycle) for the given
+ * scale set. Returns MF4D_EINVAL if p is NULL. */
+int mf4d_params_default(mf4d_params *p, int nscales, const float *sigmas);
+
+/* ------------------------------------------------------------------ host */
+
+/* FED steps of one cycle, Sec. 3.5 Eq. (23), for n given substeps and
+ * T/M = tau_max (n^2+n)/3, i.e. tau_i = tau_max / (2 cos^2(pi (2i+1)/(4n+2))),
+ * written to taus_out[0..n-1] (host) in the order they are applied: position j
+ * holds tau_{pi(j)} with pi(j) = (kappa j) mod n, kappa the value in [1, n-1]
+ * coprime to n that minimises the largest partial-product amplification of
+ * the cycle (the paper names kappa-cycle reordering without defining it; this
+ * rule is the library's reading). perm_out (nullable) receives pi.
+ * Returns kappa (>= 1), or MF4D_EINVAL (n outside [1, MF4D_MAX_SUBSTEPS],
+ * tau_max outside (0, 1/17], NULL taus_out). */
+int mf4d_fed_schedule(int n, double tau_max, double *taus_out, int *perm_out);
+
+/* Substeps per cycle from the stopping time, Eq. (22). Returns n >= 1 or
+ * MF4D_EINVAL (T <= 0, M < 1, bad tau_max, or n > MF4D_MAX_SUBSTEPS). */
+int mf4d_fed_substeps(double stop_time, int cycles, double tau_max);
+
+/* Ordered steps for the schedule mf4d_filter will use with these params
+ * (Eq. (22) and Eq. (23) when substeps == 0). Writes *n_out; taus_out
+ * (nullable) must hold MF4D_MAX_SUBSTEPS doubles. Returns MF4D_OK or
+ * MF4D_EINVAL. */
+int mf4d_fed_plan(const mf4d_params *p, int *n_out, double *taus_out);
+
+/* Bytes of device workspace needed by mf4d_scale_select, mf4d_tensor and
+ * mf4d_filter for an H x W image and these params (0 if invalid). */
+size_t mf4d_workspace_bytes(int H, int W, const mf4d_params *p);
+
+/* ---------------------------------------------------------------- device */
+
+/* Scale selection, Sec. 3.3 Eq. (9). For every scale sigma_s the Hessian of
+ * u_sigma = u * G_sigma (sampled Gaussian, radius max(1, ceil(3 sigma)),
+ * symmetric extension at the border, central differences as in Sec. 3.4) is
+ * scale-normalised by sigma^2; S, R_B and the vesselness V_s follow Eq. (9)
+ * with c = max over all scales and pixels of S / 2 (or params->c when > 0).
+ *   u        device, float32 [H][W], read only.
+ *   idx_out  device, uint8 [H][W]: smallest s with V_s = max_t V_t.
+ *   vmax_out device, float32 [H][W] (nullable): max_t V_t.
+ *   c_out    device, one float32 (nullable): the c used.
+ *   ws       device workspace of ws_bytes >= mf4d_workspace_bytes(H, W, p).
+ * Errors: MF4D_EINVAL (bad sizes/params/NULL), MF4D_ENOMEM, MF4D_EHIP. */
+int mf4d_scale_select(const float *u, int H, int W, const mf4d_params *p,
+                      uint8_t *idx_out, float *vmax_out, float *c_out,
+                      void *ws, size_t ws_bytes, void *stream);
+
+/* Normalised, integrated Hessian, Eq. (6): for each pixel,
+ * N = H(u_sigma) / sqrt(1 + |grad u_sigma|) at the pixel's scale idx[x,y],
+ * then H_rho = G_rho * N per component (symmetric extension).
+ *   u         device float32 [H][W]; idx device uint8 [H][W], values < nscales
+ *             (larger values are clamped to nscales - 1).
+ *   hrho_out  device float32 [3][H][W]: planes (a, b, d) = (xx, xy, yy).
+ *   dparams_out (nullable) device float32 [3][H][W]: the fourth-order tensor of
+ *             Eqs. (7), (8) in the compact form acting on a symmetric H as
+ *             T_xx = (m+al) h_xx + be h_xy, T_xy = m h_xy + be (h_xx+h_yy)/2,
+ *             T_yy = (m-al) h_yy + be h_xy; planes (m, al, be), where
+ *             m = (mu_1+mu_2)/2 and (al, be) = (mu_1-mu_2)/2 (cos 2t, sin 2t)
+ *             for the angle t of the first eigenvector of H_rho.
+ * Errors as mf4d_scale_select. */
+int mf4d_tensor(const float *u, int H, int W, const uint8_t *idx, const mf4d_params *p,
+                float *hrho_out, float *dparams_out,
+                void *ws, size_t ws_bytes, void *stream);
+
+/* One FED cycle, Eq. (21): n explicit steps u <- (I - tau P) u with
+ * P = L^T D L frozen for the cycle (Sec. 3.4: Hajiaboli stencils, rows of L
+ * only at interior pixels, D from H_rho by Eqs. (7), (8), lambda and mode
+ * from p). taus (host, n doubles) are applied in the given order, each cast
+ * to float32.
+ *   u      device float32 [H][W], in/out: the result always lands here.
+ *   u_tmp  device float32 [H][W] scratch (must not alias u).
+ *   hrho   device float32 [3][H][W] from mf4d_tensor.
+ * Errors: MF4D_EINVAL, MF4D_EHIP. */
+int mf4d_fed_cycle(float *u, float *u_tmp, int H, int W, const float *hrho,
+                   const mf4d_params *p, const double *taus, int n, void *stream);
+
+/* The whole filter: M cycles of scale selection (Sec. 3.3), normalised
+ * Hessian (Eq. (6)) and an FED cycle (Eq. (21)) with the schedule of
+ * mf4d_fed_plan.
+ *   u_in   device float32 [H][W], read only.
+ *   u_out  device float32 [H][W]; may alias u_in.
+ * Errors: MF4D_EINVAL, MF4D_ENOMEM, MF4D_EHIP. */
+int mf4d_filter(const float *u_in, float *u_out, int H, int W, const mf4d_params *p,
+                void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MF4D_H */

@@ -1,0 +1,429 @@
+// C ABI of libmf4d: validation, FED schedule, workspace layout and the
+// orchestration of the scale sweep, tensor and FED kernels on one stream.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "mf4d_internal.h"
+
+using namespace mf4d;
+
+namespace {
+
+constexpr double kTauLimit = 1.0 / 17.0;   // Eq. (20) at unit pixel spacing
+
+int radius_of(double sigma)
+{
+    int r = (int)std::ceil(3.0 * sigma);
+    return r < 1 ? 1 : r;
+}
+
+// Sampled Gaussian of radius max(1, ceil(3 sigma)) normalised to unit sum
+// (computed in double), and its central first and second differences.
+void make_taps(double sigma, Taps *t)
+{
+    const int r = radius_of(sigma);
+    std::vector<double> g(r + 3, 0.0);
+    double sum = 0.0;
+    for (int j = -r; j <= r; ++j) sum += std::exp(-(double)j * j / (2.0 * sigma * sigma));
+    for (int j = 0; j <= r; ++j) g[j] = std::exp(-(double)j * j / (2.0 * sigma * sigma)) / sum;
+    std::memset(t, 0, sizeof(*t));
+    t->r = r;
+    for (int i = 0; i <= r; ++i) t->g[i] = (float)g[i];
+    for (int i = 1; i <= r + 1; ++i) {
+        const double gm = g[i - 1], gp = g[i + 1];
+        t->d1[i] = (float)(0.5 * (gm - gp));
+        t->d2[i] = (float)(gm - 2.0 * g[i] + gp);
+    }
+}
+
+void make_rho_taps(double rho, RhoTaps *t)
+{
+    std::memset(t, 0, sizeof(*t));
+    if (!(rho > 0.0)) {
+        t->r = 0;
+        t->g[0] = 1.f;
+        return;
+    }
+    const int r = radius_of(rho);
+    double sum = 0.0;
+    for (int j = -r; j <= r; ++j) sum += std::exp(-(double)j * j / (2.0 * rho * rho));
+    t->r = r;
+    for (int j = 0; j <= r; ++j) t->g[j] = (float)(std::exp(-(double)j * j / (2.0 * rho * rho)) / sum);
+}
+
+bool valid_tau_max(double tau_max) { return tau_max > 0.0 && tau_max <= kTauLimit; }
+
+int validate(int H, int W, const mf4d_params *p)
+{
+    if (!p || H < 3 || W < 3 || (long long)H * (long long)W >= (1LL << 31)) return MF4D_EINVAL;
+    if (p->nscales < 1 || p->nscales > MF4D_MAX_SCALES || !p->sigmas) return MF4D_EINVAL;
+    for (int s = 0; s < p->nscales; ++s) {
+        const float v = p->sigmas[s];
+        if (!(v > 0.f) || !std::isfinite(v) || radius_of(v) > MF4D_MAX_RADIUS) return MF4D_EINVAL;
+        if (s > 0 && !(v > p->sigmas[s - 1])) return MF4D_EINVAL;
+    }
+    if (p->mode < MF4D_RIDGE || p->mode > MF4D_BOTH) return MF4D_EINVAL;
+    if (!(p->lambda > 0.f)) return MF4D_EINVAL;   // +inf allowed, NaN rejected
+    if (!(p->lambda * p->lambda > 0.f)) return MF4D_EINVAL;   // 1/lambda^2 must be finite
+    if (!(p->rho >= 0.f) || !std::isfinite(p->rho) || (p->rho > 0.f && radius_of(p->rho) > kMaxRhoR))
+        return MF4D_EINVAL;
+    if (!(p->beta > 0.f) || !std::isfinite(p->beta)) return MF4D_EINVAL;
+    if (!std::isfinite(p->c)) return MF4D_EINVAL;
+    if (p->cycles < 0) return MF4D_EINVAL;
+    if (!valid_tau_max(p->tau_max)) return MF4D_EINVAL;
+    if (p->substeps < 0 || p->substeps > MF4D_MAX_SUBSTEPS) return MF4D_EINVAL;
+    if (p->substeps == 0 && p->cycles > 0 && !(p->stop_time > 0.0 && std::isfinite(p->stop_time)))
+        return MF4D_EINVAL;
+    if (p->reselect_each_cycle != 0 && p->reselect_each_cycle != 1) return MF4D_EINVAL;
+    if (p->postprocess != 0) return MF4D_EINVAL;
+    return MF4D_OK;
+}
+
+// Largest |partial product| of (1 - tau z) over z in {2q/(Q tau_max)}, q = 0..Q,
+// over all prefixes and all suffixes of the ordered steps.
+double partial_amplification(const std::vector<double> &ord, double tau_max)
+{
+    const int Q = 8192;
+    const int n = (int)ord.size();
+    double worst = 0.0;
+    for (int q = 0; q <= Q; ++q) {
+        const double z = 2.0 * (double)q / ((double)Q * tau_max);
+        double acc = 1.0;
+        for (int j = 0; j < n; ++j) {
+            acc *= (1.0 - ord[j] * z);
+            worst = std::fmax(worst, std::fabs(acc));
+        }
+        acc = 1.0;
+        for (int j = n - 1; j >= 0; --j) {
+            acc *= (1.0 - ord[j] * z);
+            worst = std::fmax(worst, std::fabs(acc));
+        }
+    }
+    return worst;
+}
+
+int gcd(int a, int b) { return b ? gcd(b, a % b) : a; }
+
+// Orders the natural (ascending) steps as tau[(kappa j) mod n], with kappa the
+// coprime multiplier of least partial amplification (ties -> smaller kappa).
+int order_steps(const std::vector<double> &natural, double tau_max, double *out, int *perm)
+{
+    const int n = (int)natural.size();
+    int kappa = 1;
+    if (n > 2) {
+        double best = INFINITY;
+        std::vector<double> trial(n);
+        for (int k = 1; k < n; ++k) {
+            if (gcd(k, n) != 1) continue;
+            for (int j = 0; j < n; ++j) trial[j] = natural[(int)(((long long)k * j) % n)];
+            const double amp = partial_amplification(trial, tau_max);
+            if (amp < best * (1.0 - 1e-12)) {
+                best = amp;
+                kappa = k;
+            }
+        }
+    }
+    for (int j = 0; j < n; ++j) {
+        const int pj = (int)(((long long)kappa * j) % n);
+        if (perm) perm[j] = pj;
+        out[j] = natural[pj];
+    }
+    return kappa;
+}
+
+// Eq. (23) with cycle length T/M.
+std::vector<double> natural_steps(int n, double T_over_M)
+{
+    std::vector<double> tau(n);
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < n; ++i) {
+        const double c = std::cos(pi * (double)(2 * i + 1) / (double)(4 * n + 2));
+        tau[i] = 3.0 * T_over_M / (2.0 * ((double)n * n + n) * c * c);
+    }
+    return tau;
+}
+
+struct Workspace {
+    float *hA, *hB, *hC;     // horizontal pass, one scale at a time
+    float *S, *A, *N;        // per-scale planes
+    uint8_t *idx;
+    float *hrho;
+    float *utmp;
+    unsigned *smax;
+};
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t layout(int H, int W, int ns, Workspace *w, char *base)
+{
+    const size_t m = (size_t)H * W;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    Workspace t;
+    t.hA = (float *)take(m * 4);
+    t.hB = (float *)take(m * 4);
+    t.hC = (float *)take(m * 4);
+    t.S = (float *)take(m * 4 * ns);
+    t.A = (float *)take(m * 4 * ns);
+    t.N = (float *)take(m * 12 * ns);
+    t.idx = (uint8_t *)take(m);
+    t.hrho = (float *)take(m * 12);
+    t.utmp = (float *)take(m * 4);
+    t.smax = (unsigned *)take(256);
+    if (w) *w = t;
+    return off;
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? MF4D_OK : MF4D_EHIP; }
+
+#define CHECK_HIP(expr)                              \
+    do {                                             \
+        hipError_t e_ = (expr);                      \
+        if (e_ != hipSuccess) return MF4D_EHIP;      \
+    } while (0)
+
+// Scale sweep over all scales: S and blob planes (when want_sa), N planes
+// (when want_n) and the image-wide maximum of S.
+int run_sweep(const float *u, int H, int W, const mf4d_params *p, const Workspace &w,
+              bool want_n, hipStream_t s)
+{
+    const size_t m = (size_t)H * W;
+    CHECK_HIP(launch_fill_u32(w.smax, 0u, 1, s));
+    Taps t;
+    for (int k = 0; k < p->nscales; ++k) {
+        make_taps(p->sigmas[k], &t);
+        CHECK_HIP(launch_hpass(u, w.hA, w.hB, w.hC, H, W, t, s));
+        ScalePlanes planes{w.S + k * m, w.A + k * m, want_n ? w.N + 3 * k * m : nullptr};
+        CHECK_HIP(launch_vpass(w.hA, w.hB, w.hC, H, W, t, p->sigmas[k], p->mode, p->beta, planes,
+                               w.smax, s));
+    }
+    return MF4D_OK;
+}
+
+SelectArgs select_args(const mf4d_params *p, const Workspace &w)
+{
+    SelectArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.S = w.S;
+    a.A = w.A;
+    a.N = w.N;
+    a.ns = p->nscales;
+    a.smax_bits = w.smax;
+    a.c_param = p->c;
+    a.mode = p->mode;
+    a.inv_lam2 = 1.f / (p->lambda * p->lambda);
+    make_rho_taps(p->rho, &a.rho);
+    return a;
+}
+
+int plan(const mf4d_params *p, int *n_out, std::vector<double> &ordered)
+{
+    int n = p->substeps;
+    double TM;
+    if (n > 0) {
+        TM = p->tau_max * ((double)n * n + n) / 3.0;
+    } else {
+        if (p->cycles < 1 || !(p->stop_time > 0.0)) return MF4D_EINVAL;
+        n = mf4d_fed_substeps(p->stop_time, p->cycles, p->tau_max);
+        if (n < 1) return MF4D_EINVAL;
+        TM = p->stop_time / p->cycles;
+    }
+    ordered.assign(n, 0.0);
+    order_steps(natural_steps(n, TM), p->tau_max, ordered.data(), nullptr);
+    *n_out = n;
+    return MF4D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mf4d_status_string(int status)
+{
+    switch (status) {
+    case MF4D_OK: return "ok";
+    case MF4D_EINVAL: return "invalid argument";
+    case MF4D_ENOMEM: return "workspace too small";
+    case MF4D_EHIP: return "HIP runtime or launch error";
+    default: return "unknown status";
+    }
+}
+
+int mf4d_params_default(mf4d_params *p, int nscales, const float *sigmas)
+{
+    if (!p) return MF4D_EINVAL;
+    std::memset(p, 0, sizeof(*p));
+    p->nscales = nscales;
+    p->sigmas = sigmas;
+    p->mode = MF4D_BOTH;
+    p->lambda = 0.005f;
+    p->rho = 0.5f;
+    p->beta = 0.5f;
+    p->c = -1.f;
+    p->cycles = 1;
+    p->substeps = 10;
+    p->stop_time = 0.0;
+    p->tau_max = 0.05;
+    p->reselect_each_cycle = 1;
+    p->theta = 0.f;
+    p->postprocess = 0;
+    return MF4D_OK;
+}
+
+int mf4d_fed_schedule(int n, double tau_max, double *taus_out, int *perm_out)
+{
+    if (n < 1 || n > MF4D_MAX_SUBSTEPS || !valid_tau_max(tau_max) || !taus_out) return MF4D_EINVAL;
+    const double TM = tau_max * ((double)n * n + n) / 3.0;
+    return order_steps(natural_steps(n, TM), tau_max, taus_out, perm_out);
+}
+
+int mf4d_fed_substeps(double stop_time, int cycles, double tau_max)
+{
+    if (!(stop_time > 0.0) || !std::isfinite(stop_time) || cycles < 1 || !valid_tau_max(tau_max))
+        return MF4D_EINVAL;
+    const double v = -0.5 + 0.5 * std::sqrt(1.0 + 12.0 * stop_time / ((double)cycles * tau_max));
+    const double n = std::ceil(v);
+    if (n < 1.0 || n > MF4D_MAX_SUBSTEPS) return MF4D_EINVAL;
+    return (int)n;
+}
+
+int mf4d_fed_plan(const mf4d_params *p, int *n_out, double *taus_out)
+{
+    if (!p || !n_out || !valid_tau_max(p->tau_max)) return MF4D_EINVAL;
+    std::vector<double> ord;
+    int n = 0;
+    int st = plan(p, &n, ord);
+    if (st != MF4D_OK) return st;
+    *n_out = n;
+    if (taus_out) std::memcpy(taus_out, ord.data(), sizeof(double) * n);
+    return MF4D_OK;
+}
+
+size_t mf4d_workspace_bytes(int H, int W, const mf4d_params *p)
+{
+    if (validate(H, W, p) != MF4D_OK) return 0;
+    return layout(H, W, p->nscales, nullptr, nullptr);
+}
+
+int mf4d_scale_select(const float *u, int H, int W, const mf4d_params *p, uint8_t *idx_out,
+                      float *vmax_out, float *c_out, void *ws, size_t ws_bytes, void *stream)
+{
+    int st = validate(H, W, p);
+    if (st != MF4D_OK) return st;
+    if (!u || !idx_out || !ws) return MF4D_EINVAL;
+    if (ws_bytes < layout(H, W, p->nscales, nullptr, nullptr)) return MF4D_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace w;
+    layout(H, W, p->nscales, &w, (char *)ws);
+    st = run_sweep(u, H, W, p, w, false, s);
+    if (st != MF4D_OK) return st;
+    SelectArgs a = select_args(p, w);
+    a.idx_out = idx_out;
+    a.vmax_out = vmax_out;
+    a.c_out = c_out;
+    return hip_status(launch_select(a, H, W, s));
+}
+
+int mf4d_tensor(const float *u, int H, int W, const uint8_t *idx, const mf4d_params *p,
+                float *hrho_out, float *dparams_out, void *ws, size_t ws_bytes, void *stream)
+{
+    int st = validate(H, W, p);
+    if (st != MF4D_OK) return st;
+    if (!u || !idx || !hrho_out || !ws) return MF4D_EINVAL;
+    if (ws_bytes < layout(H, W, p->nscales, nullptr, nullptr)) return MF4D_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace w;
+    layout(H, W, p->nscales, &w, (char *)ws);
+    st = run_sweep(u, H, W, p, w, true, s);
+    if (st != MF4D_OK) return st;
+    SelectArgs a = select_args(p, w);
+    a.idx_in = idx;
+    a.hrho = hrho_out;
+    CHECK_HIP(launch_select(a, H, W, s));
+    if (dparams_out) CHECK_HIP(launch_dparams(hrho_out, dparams_out, H, W, p->mode, a.inv_lam2, s));
+    return MF4D_OK;
+}
+
+int mf4d_fed_cycle(float *u, float *u_tmp, int H, int W, const float *hrho, const mf4d_params *p,
+                   const double *taus, int n, void *stream)
+{
+    int st = validate(H, W, p);
+    if (st != MF4D_OK) return st;
+    if (!u || !u_tmp || u == u_tmp || !hrho || !taus || n < 1 || n > MF4D_MAX_SUBSTEPS)
+        return MF4D_EINVAL;
+    for (int i = 0; i < n; ++i)
+        if (!(taus[i] > 0.0) || !std::isfinite(taus[i])) return MF4D_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const float inv_lam2 = 1.f / (p->lambda * p->lambda);
+    float *src = u, *dst = u_tmp;
+    for (int i = 0; i < n; ++i) {
+        CHECK_HIP(launch_fed_substep(src, dst, hrho, H, W, (float)taus[i], p->mode, inv_lam2, s));
+        float *t = src;
+        src = dst;
+        dst = t;
+    }
+    if (src != u) CHECK_HIP(launch_copy_f32(src, u, (size_t)H * W, s));
+    return MF4D_OK;
+}
+
+int mf4d_filter(const float *u_in, float *u_out, int H, int W, const mf4d_params *p, void *ws,
+                size_t ws_bytes, void *stream)
+{
+    int st = validate(H, W, p);
+    if (st != MF4D_OK) return st;
+    if (!u_in || !u_out || !ws) return MF4D_EINVAL;
+    if (ws_bytes < layout(H, W, p->nscales, nullptr, nullptr)) return MF4D_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t m = (size_t)H * W;
+    if (p->cycles == 0) {
+        if (u_in != u_out) CHECK_HIP(launch_copy_f32(u_in, u_out, m, s));
+        return MF4D_OK;
+    }
+    std::vector<double> ordered;
+    int n = 0;
+    st = plan(p, &n, ordered);
+    if (st != MF4D_OK) return st;
+    std::vector<float> tau32(n);
+    for (int i = 0; i < n; ++i) tau32[i] = (float)ordered[i];
+
+    Workspace w;
+    layout(H, W, p->nscales, &w, (char *)ws);
+    // substep j writes `first` when j is even and `second` when j is odd, so
+    // that the last of the M n substeps writes u_out
+    const long long total = (long long)p->cycles * n;
+    float *first = (total % 2 == 1) ? u_out : w.utmp;
+    float *second = (total % 2 == 1) ? w.utmp : u_out;
+    const float *src = u_in;
+    if ((const float *)first == u_in) {
+        // in-place call whose first substep would overwrite its own input
+        CHECK_HIP(launch_copy_f32(u_in, w.utmp, m, s));
+        src = w.utmp;
+        first = u_out;
+        second = w.utmp;
+    }
+    SelectArgs a = select_args(p, w);
+    long long j = 0;
+    for (int k = 0; k < p->cycles; ++k) {
+        const bool reselect = (k == 0) || p->reselect_each_cycle;
+        st = run_sweep(src, H, W, p, w, true, s);
+        if (st != MF4D_OK) return st;
+        SelectArgs ak = a;
+        ak.hrho = w.hrho;
+        if (reselect) ak.idx_out = w.idx;
+        else ak.idx_in = w.idx;
+        CHECK_HIP(launch_select(ak, H, W, s));
+        for (int i = 0; i < n; ++i, ++j) {
+            float *dst = (j % 2 == 0) ? first : second;
+            CHECK_HIP(launch_fed_substep(src, dst, w.hrho, H, W, tau32[i], p->mode, a.inv_lam2, s));
+            src = dst;
+        }
+    }
+    return MF4D_OK;
+}
+
+}  // extern "C"

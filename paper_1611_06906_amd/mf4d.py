@@ -1,0 +1,255 @@
+"""Python binding of libmf4d (include/mf4d.h): argument marshalling only.
+
+Every step of the filter runs in the HIP library; this module checks tensor
+shapes, dtypes and devices, passes raw device pointers and the current HIP
+stream through ctypes, and turns non-zero status codes into exceptions.
+PyTorch provides device memory and streams. There is no CPU fallback: if the
+library has not been built, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # imported first so that libmf4d binds to torch's HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmf4d.so")
+
+MF4D_OK, MF4D_EINVAL, MF4D_ENOMEM, MF4D_EHIP = 0, -1, -2, -3
+MF4D_RIDGE, MF4D_VALLEY, MF4D_BOTH = 0, 1, 2
+MF4D_MAX_SCALES, MF4D_MAX_RADIUS, MF4D_MAX_SUBSTEPS = 16, 64, 1024
+
+# every symbol include/mf4d.h declares
+EXPORTS = ["mf4d_status_string", "mf4d_params_default", "mf4d_fed_schedule",
+           "mf4d_fed_substeps", "mf4d_fed_plan", "mf4d_workspace_bytes",
+           "mf4d_scale_select", "mf4d_tensor", "mf4d_fed_cycle", "mf4d_filter"]
+
+
+class MF4DError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+
+
+class mf4d_params(ctypes.Structure):
+    _fields_ = [
+        ("nscales", ctypes.c_int),
+        ("sigmas", ctypes.POINTER(ctypes.c_float)),
+        ("mode", ctypes.c_int),
+        ("lambda_", ctypes.c_float),
+        ("rho", ctypes.c_float),
+        ("beta", ctypes.c_float),
+        ("c", ctypes.c_float),
+        ("cycles", ctypes.c_int),
+        ("substeps", ctypes.c_int),
+        ("stop_time", ctypes.c_double),
+        ("tau_max", ctypes.c_double),
+        ("reselect_each_cycle", ctypes.c_int),
+        ("theta", ctypes.c_float),
+        ("postprocess", ctypes.c_int),
+    ]
+
+
+class Params:
+    """Filter parameters (paper notation); owns the host sigma array."""
+
+    def __init__(self, sigmas, mode=MF4D_BOTH, lam=0.005, rho=0.5, beta=0.5, c=-1.0,
+                 cycles=1, substeps=10, stop_time=0.0, tau_max=0.05, reselect_each_cycle=1,
+                 theta=0.0, postprocess=0):
+        self.sigmas = np.ascontiguousarray(np.asarray(sigmas, dtype=np.float32))
+        self.mode, self.lam, self.rho, self.beta, self.c = mode, lam, rho, beta, c
+        self.cycles, self.substeps, self.stop_time, self.tau_max = cycles, substeps, stop_time, tau_max
+        self.reselect_each_cycle, self.theta, self.postprocess = reselect_each_cycle, theta, postprocess
+
+    @classmethod
+    def from_workload(cls, w, **kw):
+        d = dict(mode=w.mode, lam=w.lam, rho=w.rho, beta=w.beta, cycles=w.cycles,
+                 substeps=w.substeps, tau_max=w.tau_max)
+        d.update(kw)
+        return cls(w.sigmas, **d)
+
+    def struct(self) -> mf4d_params:
+        p = mf4d_params()
+        p.nscales = len(self.sigmas)
+        p.sigmas = self.sigmas.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        p.mode = int(self.mode)
+        p.lambda_ = float(self.lam)
+        p.rho = float(self.rho)
+        p.beta = float(self.beta)
+        p.c = float(self.c)
+        p.cycles = int(self.cycles)
+        p.substeps = int(self.substeps)
+        p.stop_time = float(self.stop_time)
+        p.tau_max = float(self.tau_max)
+        p.reselect_each_cycle = int(self.reselect_each_cycle)
+        p.theta = float(self.theta)
+        p.postprocess = int(self.postprocess)
+        return p
+
+
+_lib = None
+
+
+def lib():
+    """Load libmf4d.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        vp, sz, i, d = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_double
+        L.mf4d_status_string.argtypes = [i]
+        L.mf4d_status_string.restype = ctypes.c_char_p
+        L.mf4d_params_default.argtypes = [P(mf4d_params), i, P(ctypes.c_float)]
+        L.mf4d_params_default.restype = i
+        L.mf4d_fed_schedule.argtypes = [i, d, P(d), P(i)]
+        L.mf4d_fed_schedule.restype = i
+        L.mf4d_fed_substeps.argtypes = [d, i, d]
+        L.mf4d_fed_substeps.restype = i
+        L.mf4d_fed_plan.argtypes = [P(mf4d_params), P(i), P(d)]
+        L.mf4d_fed_plan.restype = i
+        L.mf4d_workspace_bytes.argtypes = [i, i, P(mf4d_params)]
+        L.mf4d_workspace_bytes.restype = sz
+        L.mf4d_scale_select.argtypes = [vp, i, i, P(mf4d_params), vp, vp, vp, vp, sz, vp]
+        L.mf4d_scale_select.restype = i
+        L.mf4d_tensor.argtypes = [vp, i, i, vp, P(mf4d_params), vp, vp, vp, sz, vp]
+        L.mf4d_tensor.restype = i
+        L.mf4d_fed_cycle.argtypes = [vp, vp, i, i, vp, P(mf4d_params), P(d), i, vp]
+        L.mf4d_fed_cycle.restype = i
+        L.mf4d_filter.argtypes = [vp, vp, i, i, P(mf4d_params), vp, sz, vp]
+        L.mf4d_filter.restype = i
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().mf4d_status_string(int(status)).decode()
+
+
+def _check(st, where):
+    if st != MF4D_OK:
+        raise MF4DError(st, where)
+
+
+def _dev(t, dtype, shape=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA/HIP torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _hw(u):
+    if u.dim() != 2:
+        raise ValueError("image must be 2-D [H, W]")
+    return int(u.shape[0]), int(u.shape[1])
+
+
+# ------------------------------------------------------------------ host calls
+def mf4d_fed_schedule(n: int, tau_max: float = 0.05):
+    """Ordered FED steps of one cycle; returns (taus, perm, kappa)."""
+    taus = np.zeros(max(int(n), 1))
+    perm = np.zeros(max(int(n), 1), np.int32)
+    k = lib().mf4d_fed_schedule(int(n), float(tau_max),
+                                taus.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                perm.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    if k < 1:
+        raise MF4DError(k, "mf4d_fed_schedule")
+    return taus[:n], perm[:n], k
+
+
+def mf4d_fed_substeps(stop_time: float, cycles: int, tau_max: float = 0.05) -> int:
+    n = lib().mf4d_fed_substeps(float(stop_time), int(cycles), float(tau_max))
+    if n < 1:
+        raise MF4DError(n, "mf4d_fed_substeps")
+    return n
+
+
+def mf4d_fed_plan(params: Params):
+    st = params.struct()
+    n = ctypes.c_int(0)
+    taus = np.zeros(MF4D_MAX_SUBSTEPS)
+    _check(lib().mf4d_fed_plan(ctypes.byref(st), ctypes.byref(n),
+                               taus.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "mf4d_fed_plan")
+    return n.value, taus[:n.value].copy()
+
+
+def mf4d_workspace_bytes(H: int, W: int, params: Params) -> int:
+    st = params.struct()
+    return int(lib().mf4d_workspace_bytes(int(H), int(W), ctypes.byref(st)))
+
+
+def workspace(H: int, W: int, params: Params, device="cuda"):
+    nb = mf4d_workspace_bytes(H, W, params)
+    if nb == 0:
+        raise MF4DError(MF4D_EINVAL, "mf4d_workspace_bytes")
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+# ---------------------------------------------------------------- device calls
+def mf4d_scale_select(u, params: Params, idx_out, vmax_out=None, c_out=None, ws=None, stream=None):
+    H, W = _hw(_dev(u, torch.float32, name="u"))
+    _dev(idx_out, torch.uint8, (H, W), "idx_out")
+    _dev(vmax_out, torch.float32, (H, W), "vmax_out")
+    _dev(c_out, torch.float32, (1,), "c_out")
+    if ws is None:
+        ws = workspace(H, W, params, u.device)
+    _dev(ws, torch.uint8, name="ws")
+    st = params.struct()
+    _check(lib().mf4d_scale_select(_ptr(u), H, W, ctypes.byref(st), _ptr(idx_out), _ptr(vmax_out),
+                                   _ptr(c_out), _ptr(ws), ws.numel(), _stream(stream)),
+           "mf4d_scale_select")
+
+
+def mf4d_tensor(u, idx, params: Params, hrho_out, dparams_out=None, ws=None, stream=None):
+    H, W = _hw(_dev(u, torch.float32, name="u"))
+    _dev(idx, torch.uint8, (H, W), "idx")
+    _dev(hrho_out, torch.float32, (3, H, W), "hrho_out")
+    _dev(dparams_out, torch.float32, (3, H, W), "dparams_out")
+    if ws is None:
+        ws = workspace(H, W, params, u.device)
+    _dev(ws, torch.uint8, name="ws")
+    st = params.struct()
+    _check(lib().mf4d_tensor(_ptr(u), H, W, _ptr(idx), ctypes.byref(st), _ptr(hrho_out),
+                             _ptr(dparams_out), _ptr(ws), ws.numel(), _stream(stream)), "mf4d_tensor")
+
+
+def mf4d_fed_cycle(u, u_tmp, hrho, params: Params, taus, stream=None):
+    H, W = _hw(_dev(u, torch.float32, name="u"))
+    _dev(u_tmp, torch.float32, (H, W), "u_tmp")
+    _dev(hrho, torch.float32, (3, H, W), "hrho")
+    t = np.ascontiguousarray(np.asarray(taus, dtype=np.float64))
+    st = params.struct()
+    _check(lib().mf4d_fed_cycle(_ptr(u), _ptr(u_tmp), H, W, _ptr(hrho), ctypes.byref(st),
+                                t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(t),
+                                _stream(stream)), "mf4d_fed_cycle")
+
+
+def mf4d_filter(u_in, u_out, params: Params, ws=None, stream=None):
+    H, W = _hw(_dev(u_in, torch.float32, name="u_in"))
+    _dev(u_out, torch.float32, (H, W), "u_out")
+    if ws is None:
+        ws = workspace(H, W, params, u_in.device)
+    _dev(ws, torch.uint8, name="ws")
+    st = params.struct()
+    _check(lib().mf4d_filter(_ptr(u_in), _ptr(u_out), H, W, ctypes.byref(st), _ptr(ws), ws.numel(),
+                             _stream(stream)), "mf4d_filter")

@@ -1,0 +1,108 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads and
+exports every symbol include/mf4d.h declares, the host FED schedule equals
+the oracle's, and invalid arguments are rejected before any launch."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+
+
+@pytest.fixture(scope="module")
+def m():
+    from paper_1611_06906_amd import mf4d
+    mf4d.lib()
+    return mf4d
+
+
+def test_header_symbols_exported(m):
+    hdr = open(os.path.join(ROOT, "include", "mf4d.h")).read()
+    declared = set(re.findall(r"\b(mf4d_[a-z_]+)\s*\(", hdr))
+    assert declared == set(m.EXPORTS)
+    for name in declared:
+        assert hasattr(m.lib(), name), name
+
+
+def test_status_strings(m):
+    for st in (0, -1, -2, -3, 7):
+        assert len(m.status_string(st)) > 0
+
+
+def test_schedule_equals_oracle_bitwise(m, oracle_lib):
+    for n in range(1, 65):
+        taus, perm, k = m.mf4d_fed_schedule(n, 0.05)
+        o_taus, o_perm, o_k = oracle_lib.fed_schedule(n, 0.05)
+        assert k == o_k and np.array_equal(perm, o_perm), n
+        assert np.array_equal(taus, o_taus), n
+    for tmax in (1.0 / 17.0, 0.03):
+        taus, _, _ = m.mf4d_fed_schedule(20, tmax)
+        assert np.array_equal(taus, oracle_lib.fed_schedule(20, tmax)[0])
+
+
+def test_substeps_and_plan_equal_oracle(m, oracle_lib):
+    for T, M in [(500.0, 10000), (20.0, 1000), (12.0, 2), (5.0, 1), (80.0, 20), (7.3, 3)]:
+        assert m.mf4d_fed_substeps(T, M, 0.05) == oracle_lib.fed_n(T, M, 0.05)
+    p = m.Params([1.0, 2.0], cycles=2, substeps=0, stop_time=12.0)
+    n, taus = m.mf4d_fed_plan(p)
+    assert n == 19
+    nat = oracle_lib.fed_taus(n, 12.0, 2)
+    _, _, ordered = oracle_lib.kappa_order(nat, 0.05)
+    assert np.array_equal(taus, ordered)
+    assert math.isclose(taus.sum(), 6.0, rel_tol=1e-13)
+
+
+def _raw_filter(m, H, W, p):
+    st = p.struct()
+    return m.lib().mf4d_filter(None, None, H, W, ctypes.byref(st), None, 0, None)
+
+
+def test_validation_rejects_before_launch(m):
+    good = dict(sigmas=[1.0, 2.0], mode=0, cycles=1, substeps=5)
+    P = lambda **kw: m.Params(**{**good, **kw})
+    assert m.mf4d_workspace_bytes(64, 64, P()) > 0
+    bad = [
+        (2, 64, P()), (64, 2, P()), (1 << 16, 1 << 15, P()),
+        (64, 64, P(sigmas=[])), (64, 64, P(sigmas=[2.0, 1.0])), (64, 64, P(sigmas=[1.0, 1.0])),
+        (64, 64, P(sigmas=[0.0, 1.0])), (64, 64, P(sigmas=[30.0])), (64, 64, P(sigmas=list(range(1, 18)))),
+        (64, 64, P(mode=3)), (64, 64, P(lam=0.0)), (64, 64, P(lam=float("nan"))),
+        (64, 64, P(rho=-1.0)), (64, 64, P(rho=5.0)), (64, 64, P(beta=0.0)),
+        (64, 64, P(c=float("inf"))), (64, 64, P(cycles=-1)), (64, 64, P(tau_max=0.06)),
+        (64, 64, P(tau_max=0.0)), (64, 64, P(substeps=0, stop_time=0.0)),
+        (64, 64, P(substeps=2000)), (64, 64, P(reselect_each_cycle=2)), (64, 64, P(postprocess=1)),
+    ]
+    for H, W, p in bad:
+        assert m.mf4d_workspace_bytes(H, W, p) == 0
+        assert _raw_filter(m, H, W, p) == m.MF4D_EINVAL
+    # valid parameters but missing buffers are rejected too
+    assert _raw_filter(m, 64, 64, P()) == m.MF4D_EINVAL
+    # lambda = +inf (linear isotropic) and rho = 0 are valid
+    assert m.mf4d_workspace_bytes(64, 64, P(lam=math.inf, rho=0.0)) > 0
+    # workspace too small
+    st = P().struct()
+    nb = m.mf4d_workspace_bytes(64, 64, P())
+    assert m.lib().mf4d_filter(ctypes.c_void_p(16), ctypes.c_void_p(16), 64, 64, ctypes.byref(st),
+                               ctypes.c_void_p(16), nb - 1, None) == m.MF4D_ENOMEM
+    with pytest.raises(m.MF4DError):
+        m.mf4d_fed_schedule(0)
+    with pytest.raises(m.MF4DError):
+        m.mf4d_fed_schedule(10, 0.07)
+
+
+def test_workspace_scales_with_image_and_scales(m):
+    p1 = m.Params([1.0, 2.0])
+    p2 = m.Params([1.0, 2.0, 3.0, 4.0])
+    a = m.mf4d_workspace_bytes(256, 256, p1)
+    assert m.mf4d_workspace_bytes(512, 512, p1) > 3.9 * a
+    assert m.mf4d_workspace_bytes(256, 256, p2) > a
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_1611_06906_amd import mf4d
+    monkeypatch.setattr(mf4d, "_lib", None)
+    monkeypatch.setattr(mf4d, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError):
+        mf4d.lib()
