@@ -103,6 +103,11 @@ def main():
                 "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None,
                 "us_per_launch": ms_substep * 1e3, "bytes_per_px": SUBSTEP_BYTES_PER_PX}
 
+    # one single-step cycle: a substep plus the plain copy of H*W floats back
+    # into u (4 B read + 4 B write per pixel), the reference for HBM counters
+    mf4d.mf4d_fed_cycle(uc, ut, hrho, p, taus[:1])
+    torch.cuda.synchronize()
+
     stages = None
     if not args.no_stages:
         sel_ms = time_stream(torch, lambda: mf4d.mf4d_scale_select(u_in, p, idx, None, None, ws), 3)

@@ -170,6 +170,18 @@ int mf4d_tensor(const float *u, int H, int W, const uint8_t *idx, const mf4d_par
 int mf4d_fed_cycle(float *u, float *u_tmp, int H, int W, const float *hrho,
                    const mf4d_params *p, const double *taus, int n, void *stream);
 
+/* n FED substeps as mf4d_fed_cycle, but from the compact tensor planes
+ * (dparams_out of mf4d_tensor) computed once for the cycle, so no substep
+ * repeats the eigen-decomposition; the values are identical to those of
+ * mf4d_fed_cycle given the H_rho the planes were built from.
+ *   dparams          device float32 [3][H][W] planes (m, al, be).
+ *   steps_per_launch 1..4: consecutive substeps per pass over the image
+ *                    (intermediate images stay on chip), dividing the HBM
+ *                    traffic per substep by steps_per_launch; same values.
+ * Errors: MF4D_EINVAL, MF4D_EHIP. */
+int mf4d_fed_cycle_tensor(float *u, float *u_tmp, int H, int W, const float *dparams,
+                          const double *taus, int n, int steps_per_launch, void *stream);
+
 /* The whole filter: M cycles of scale selection (Sec. 3.3), normalised
  * Hessian (Eq. (6)) and an FED cycle (Eq. (21)) with the schedule of
  * mf4d_fed_plan.

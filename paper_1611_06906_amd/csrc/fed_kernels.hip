@@ -1,77 +1,47 @@
-// Fused FED substep (Sec. 3.4, Sec. 3.5 Eq. (21)):
-//   u_out = u_in - tau * L^T D L u_in
-// with the per-pixel fourth-order tensor D of Eqs. (7), (8) rebuilt in
-// registers from the normalised, integrated Hessian H_rho = [[a, b], [b, d]].
+// FED substeps (Sec. 3.4, Sec. 3.5 Eq. (21)):  u <- u - tau L^T D L u.
 //
 // Rows of L exist only at interior pixels (natural boundary condition), so
-// T = D L u is zero outside 1 <= x <= W-2, 1 <= y <= H-2, and L^T reaches
-// the border pixels through the transposed stencils.
+// T = D L u is zero outside 1 <= x <= W-2, 1 <= y <= H-2 and L^T reaches the
+// border pixels through the transposed stencils:
+//   L_xx, L_yy: [1 -2 1] along x / y;  L_xy = L_yx: (+1 at (-1,-1), (1,1);
+//   -1 at (-1,1), (1,-1)) / 4, so  r = L^T T = D2x T_xx + 2 Dxy T_xy + D2y T_yy.
 //
-// Tensor in compact form. With mu_1, mu_2 the diffusivities of the two
-// eigenvalues nu_1 >= nu_2 of H_rho, mu_3 = (mu_1 + mu_2) / 2 and mu_4 = 0,
-// D acts on a symmetric Hessian h as
-//   T_xx = (m + al) h_xx + be h_xy
-//   T_xy = T_yx = m h_xy + be (h_xx + h_yy) / 2
-//   T_yy = (m - al) h_yy + be h_xy
-// where m = (mu_1 + mu_2) / 2 and (al, be) = (mu_1 - mu_2) / 2 * (cos 2t, sin 2t)
-// for the angle t of the first eigenvector: expanding D = E M E^T for the
-// rotation E gives exactly these entries. (mu_1 - mu_2) is formed without
-// cancellation: 1 - mu = q mu with q = nu^2 / lambda^2, and for two unmasked
-// eigenvalues mu_1 - mu_2 = -4 m' r mu_1 mu_2 / lambda^2 (m' the mean and r the
-// half-difference of the eigenvalues), which also removes the division by r.
+// Two kernels:
+//  * fed_hrho_kernel: one substep from H_rho, rebuilding the fourth-order
+//    tensor (tensor_math.h) in registers at every position it needs.
+//  * fed_coef_kernel<STEPS>: STEPS consecutive substeps from the compact
+//    tensor planes (m, al, be) computed once per cycle; P is frozen over the
+//    cycle, so this produces bit-identical values with none of the per-substep
+//    eigen-solves. With STEPS = 2 a tile keeps the intermediate image in LDS
+//    (temporal blocking): u and the tensor planes are read once and u written
+//    once per two substeps; the halo positions are recomputed by
+//    neighbouring tiles with the same operations in the same order.
 #include "mf4d_internal.h"
+#include "tensor_math.h"
 
 namespace mf4d {
 
 namespace {
 
-constexpr int kTW = 64, kTH = 16;   // output tile
-
-template <int MODE>
-__device__ __forceinline__ void tensor_coeffs(float a, float b, float d, float inv_lam2,
-                                              float &mbar, float &al, float &be)
+// XCD-aware tile order: consecutive blocks go to different XCDs, so give each
+// XCD a contiguous band of tiles and keep halo re-reads in its own L2.
+__device__ __forceinline__ int xcd_tile(int per_xcd)
 {
-    const float mm = 0.5f * (a + d);
-    const float hd = 0.5f * (a - d);
-    const float r = sqrtf(hd * hd + b * b);
-    const float nu1 = mm + r, nu2 = mm - r;
-    const float q1 = nu1 * nu1 * inv_lam2, q2 = nu2 * nu2 * inv_lam2;
-    float mu1 = 1.f / (1.f + q1), mu2 = 1.f / (1.f + q2);
-    bool k1 = false, k2 = false;   // masked eigenvalue: mu = 1
-    if (MODE == MF4D_RIDGE) { k1 = nu1 >= 0.f; k2 = nu2 >= 0.f; }
-    if (MODE == MF4D_VALLEY) { k1 = nu1 <= 0.f; k2 = nu2 <= 0.f; }
-    if (!k1 && !k2) {
-        const float k = -2.f * mm * mu1 * mu2 * inv_lam2;
-        mbar = 0.5f * (mu1 + mu2);
-        al = k * hd;
-        be = k * b;
-    } else if (k1 && k2) {
-        mbar = 1.f;
-        al = 0.f;
-        be = 0.f;
-    } else {
-        float half_diff;   // (mu_1 - mu_2) / 2
-        if (k1) { half_diff = 0.5f * q2 * mu2; mu1 = 1.f; }
-        else { half_diff = -0.5f * q1 * mu1; mu2 = 1.f; }
-        mbar = 0.5f * (mu1 + mu2);
-        const float ir = r > 0.f ? 1.f / r : 0.f;
-        al = half_diff * hd * ir;
-        be = half_diff * b * ir;
-    }
+    return (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
 }
 
+constexpr int kTW = 64, kTH = 16;   // output tile of the H_rho kernel
+
 template <int MODE>
-__global__ __launch_bounds__(256) void fed_substep_kernel(const float *__restrict__ u,
-                                                          float *__restrict__ uo,
-                                                          const float *__restrict__ hrho,
-                                                          int H, int W, float tau, float inv_lam2,
-                                                          int tiles_x, int ntiles, int per_xcd)
+__global__ __launch_bounds__(256) void fed_hrho_kernel(const float *__restrict__ u,
+                                                       float *__restrict__ uo,
+                                                       const float *__restrict__ hrho,
+                                                       int H, int W, float tau, float inv_lam2,
+                                                       int tiles_x, int ntiles, int per_xcd)
 {
     __shared__ float su[kTH + 4][kTW + 4 + 1];
     __shared__ float sT[3][kTH + 2][kTW + 2 + 1];
-    // XCD-aware order: consecutive blocks land on different XCDs, so give each
-    // XCD a contiguous band of tiles to keep halo re-reads in its own L2.
-    const int tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    const int tile = xcd_tile(per_xcd);
     if (tile >= ntiles) return;
     const int x0 = (tile % tiles_x) * kTW, y0 = (tile / tiles_x) * kTH;
     const size_t plane = (size_t)H * W;
@@ -110,22 +80,297 @@ __global__ __launch_bounds__(256) void fed_substep_kernel(const float *__restric
         const float rxx = sT[0][ly + 1][lx] - 2.f * sT[0][ly + 1][lx + 1] + sT[0][ly + 1][lx + 2];
         const float ryy = sT[2][ly][lx + 1] - 2.f * sT[2][ly + 1][lx + 1] + sT[2][ly + 2][lx + 1];
         const float rxy = 0.5f * ((sT[1][ly][lx] + sT[1][ly + 2][lx + 2]) - (sT[1][ly + 2][lx] + sT[1][ly][lx + 2]));
-        const float r = rxx + rxy + ryy;
-        uo[(size_t)gy * W + gx] = su[ly + 2][lx + 2] - tau * r;
+        uo[(size_t)gy * W + gx] = su[ly + 2][lx + 2] - tau * (rxx + rxy + ryy);
     }
 }
 
-template <int MODE>
-__global__ void dparams_kernel(const float *__restrict__ hrho, float *__restrict__ dp, size_t plane,
-                               float inv_lam2)
+// ----------------------------------------------------------------- compact
+constexpr int kCW = 64, kCH = 16;   // output tile of the coefficient kernel
+
+// T = D h at one position from the u tile (centre at su[cy][cx]).
+__device__ __forceinline__ void flux(const float *su, int pitch, int cy, int cx, float mb, float al,
+                                     float be, float &txx, float &txy, float &tyy)
 {
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= plane) return;
-    float mbar, al, be;
-    tensor_coeffs<MODE>(hrho[i], hrho[plane + i], hrho[2 * plane + i], inv_lam2, mbar, al, be);
-    dp[i] = mbar;
-    dp[plane + i] = al;
-    dp[2 * plane + i] = be;
+    const float *c = su + cy * pitch + cx;
+    const float v = c[0];
+    const float hxx = c[-1] - 2.f * v + c[1];
+    const float hyy = c[-pitch] - 2.f * v + c[pitch];
+    const float hxy = 0.25f * ((c[-pitch - 1] + c[pitch + 1]) - (c[pitch - 1] + c[-pitch + 1]));
+    txx = (mb + al) * hxx + be * hxy;
+    txy = mb * hxy + be * 0.5f * (hxx + hyy);
+    tyy = (mb - al) * hyy + be * hxy;
+}
+
+// r = L^T T at one position (centre at sT[.][cy][cx]).
+__device__ __forceinline__ float divergence(const float *sxx, const float *sxy, const float *syy, int pitch,
+                                            int cy, int cx)
+{
+    const int o = cy * pitch + cx;
+    const float rxx = sxx[o - 1] - 2.f * sxx[o] + sxx[o + 1];
+    const float ryy = syy[o - pitch] - 2.f * syy[o] + syy[o + pitch];
+    const float rxy = 0.5f * ((sxy[o - pitch - 1] + sxy[o + pitch + 1]) - (sxy[o + pitch - 1] + sxy[o - pitch + 1]));
+    return rxx + rxy + ryy;
+}
+
+__device__ __forceinline__ bool interior(int gx, int gy, int W, int H)
+{
+    return gx >= 1 && gx <= W - 2 && gy >= 1 && gy <= H - 2;
+}
+
+template <int STEPS>
+__global__ __launch_bounds__(256) void fed_coef_kernel(const float *__restrict__ u, float *__restrict__ uo,
+                                                       const float *__restrict__ coef, int H, int W,
+                                                       float tau0, float tau1, int tiles_x, int ntiles,
+                                                       int per_xcd)
+{
+    constexpr int HALO = 2 * STEPS;                 // u halo
+    constexpr int UW = kCW + 2 * HALO, UH = kCH + 2 * HALO, UP = UW + 1;
+    constexpr int CW_ = kCW + 2 * HALO - 2, CH_ = kCH + 2 * HALO - 2, CP = CW_ + 1;   // T region
+    constexpr int VW = kCW + 2 * HALO - 4, VH = kCH + 2 * HALO - 4, VP = VW + 1;      // u1 region (STEPS = 2)
+    __shared__ float su[UH * UP];
+    __shared__ float sT[3][CH_ * CP];
+    __shared__ float sv[STEPS == 2 ? VH * VP : 1];
+
+    const int tile = xcd_tile(per_xcd);
+    if (tile >= ntiles) return;
+    const int x0 = (tile % tiles_x) * kCW, y0 = (tile / tiles_x) * kCH;
+    const size_t plane = (size_t)H * W;
+
+    // tensor planes of this thread's first-substep positions, loaded up front
+    constexpr int NC = (CH_ * CW_ + 255) / 256;
+    float cm[NC], ca[NC], cb[NC];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+        const int i = threadIdx.x + 256 * j;
+        const int ly = i / CW_, lx = i - ly * CW_;
+        const int gy = y0 - HALO + 1 + ly, gx = x0 - HALO + 1 + lx;
+        cm[j] = ca[j] = cb[j] = 0.f;
+        if (i < CH_ * CW_ && interior(gx, gy, W, H)) {
+            const size_t o = (size_t)gy * W + gx;
+            cm[j] = coef[o];
+            ca[j] = coef[plane + o];
+            cb[j] = coef[2 * plane + o];
+        }
+    }
+    // u on the tile plus HALO
+    for (int i = threadIdx.x; i < UH * UW; i += 256) {
+        const int ly = i / UW, lx = i - ly * UW;
+        const int gy = y0 - HALO + ly, gx = x0 - HALO + lx;
+        su[ly * UP + lx] = (gy >= 0 && gy < H && gx >= 0 && gx < W) ? u[(size_t)gy * W + gx] : 0.f;
+    }
+    __syncthreads();
+
+    // ---- substep 1: T on the T region (zero outside the interior)
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+        const int i = threadIdx.x + 256 * j;
+        if (i < CH_ * CW_) {
+            const int ly = i / CW_, lx = i - ly * CW_;
+            const int gy = y0 - HALO + 1 + ly, gx = x0 - HALO + 1 + lx;
+            float txx = 0.f, txy = 0.f, tyy = 0.f;
+            if (interior(gx, gy, W, H)) flux(su, UP, ly + 1, lx + 1, cm[j], ca[j], cb[j], txx, txy, tyy);
+            sT[0][ly * CP + lx] = txx;
+            sT[1][ly * CP + lx] = txy;
+            sT[2][ly * CP + lx] = tyy;
+        }
+    }
+    __syncthreads();
+    if (STEPS == 1) {
+        for (int i = threadIdx.x; i < kCH * kCW; i += 256) {
+            const int ly = i / kCW, lx = i - ly * kCW;
+            const int gy = y0 + ly, gx = x0 + lx;
+            if (gy >= H || gx >= W) continue;
+            const float r = divergence(sT[0], sT[1], sT[2], CP, ly + 1, lx + 1);
+            uo[(size_t)gy * W + gx] = su[(ly + 2) * UP + lx + 2] - tau0 * r;
+        }
+        return;
+    }
+    // u1 on the tile plus 2 (positions outside the image are never read)
+    for (int i = threadIdx.x; i < VH * VW; i += 256) {
+        const int ly = i / VW, lx = i - ly * VW;
+        const float r = divergence(sT[0], sT[1], sT[2], CP, ly + 1, lx + 1);
+        sv[ly * VP + lx] = su[(ly + 2) * UP + lx + 2] - tau0 * r;
+    }
+    // tensor planes of the second-substep positions (L2-resident: just read)
+    constexpr int N2 = ((kCH + 2) * (kCW + 2) + 255) / 256;
+    float dm[N2], da[N2], db[N2];
+#pragma unroll
+    for (int j = 0; j < N2; ++j) {
+        const int i = threadIdx.x + 256 * j;
+        const int ly = i / (kCW + 2), lx = i - ly * (kCW + 2);
+        const int gy = y0 - 1 + ly, gx = x0 - 1 + lx;
+        dm[j] = da[j] = db[j] = 0.f;
+        if (i < (kCH + 2) * (kCW + 2) && interior(gx, gy, W, H)) {
+            const size_t o = (size_t)gy * W + gx;
+            dm[j] = coef[o];
+            da[j] = coef[plane + o];
+            db[j] = coef[2 * plane + o];
+        }
+    }
+    __syncthreads();
+    // ---- substep 2: T on the tile plus 1 from u1, then the output
+#pragma unroll
+    for (int j = 0; j < N2; ++j) {
+        const int i = threadIdx.x + 256 * j;
+        if (i < (kCH + 2) * (kCW + 2)) {
+            const int ly = i / (kCW + 2), lx = i - ly * (kCW + 2);
+            const int gy = y0 - 1 + ly, gx = x0 - 1 + lx;
+            float txx = 0.f, txy = 0.f, tyy = 0.f;
+            if (interior(gx, gy, W, H)) flux(sv, VP, ly + 1, lx + 1, dm[j], da[j], db[j], txx, txy, tyy);
+            const int co = (ly + 2) * CP + lx + 2;   // same position in the T region
+            sT[0][co] = txx;
+            sT[1][co] = txy;
+            sT[2][co] = tyy;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kCH * kCW; i += 256) {
+        const int ly = i / kCW, lx = i - ly * kCW;
+        const int gy = y0 + ly, gx = x0 + lx;
+        if (gy >= H || gx >= W) continue;
+        const float r = divergence(sT[0], sT[1], sT[2], CP, ly + 3, lx + 3);
+        uo[(size_t)gy * W + gx] = sv[(ly + 2) * VP + lx + 2] - tau1 * r;
+    }
+}
+
+// ------------------------------------------------------------ row streaming
+// fed_stream_kernel<S>: S consecutive substeps per launch without LDS or
+// barriers. A wave owns 64 adjacent columns (lane = column) and walks down a
+// segment of rows; every intermediate quantity lives in per-lane register
+// rings indexed by row, and x-neighbours come from lane shifts. Each level
+// of the substep pipeline (flux T_k, then u_k) lags the previous one by one
+// row and spoils one more lane at each wave edge, so a wave owns 64 - 4 S
+// output columns and reads u and the tensor planes with a 2 S lane and 2 S
+// row halo.
+//
+// With D(x) = T_xy(p-1, x) - T_xy(p+1, x) the divergence at row p is
+//   r = [T_xx(p) + D/2](x-1) + [T_xx(p) - D/2](x+1) - 2 T_xx(p)(x)
+//       + T_yy(p-1) - 2 T_yy(p) + T_yy(p+1),
+// i.e. L_xx^T T_xx + 2 L_xy^T T_xy + L_yy^T T_yy with two lane shifts.
+struct FedTaus {
+    float t[4];
+};
+
+// lane i receives the value of lane i - 1 (x - 1) / lane i + 1 (x + 1); the
+// wave's edge lanes receive 0, which only ever reaches halo lanes.
+__device__ __forceinline__ float from_left(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float from_right(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void fed_stream_kernel(const float *__restrict__ u, float *__restrict__ uo,
+                                                         const float *__restrict__ coef, int H, int W,
+                                                         FedTaus taus, int strips, int segs, int seg_rows,
+                                                         int blocks_per_xcd, int nblocks)
+{
+    constexpr int HALO = 2 * S;
+    constexpr int OUTW = 64 - 2 * HALO;
+    constexpr int D = 8;                                  // rows loaded ahead
+    constexpr int NC = 2 * S;                             // tensor rows kept
+    constexpr int U = 24;                                 // unroll: multiple of 3, NC and D
+    // XCD-aware: each XCD takes a contiguous run of blocks
+    const int blk = (blockIdx.x % 8) * blocks_per_xcd + blockIdx.x / 8;
+    if (blk >= nblocks) return;
+    const int wave = blk * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int strip = wave % strips, seg = wave / strips;
+    if (seg >= segs) return;
+    const int x = strip * OUTW - HALO + lane;
+    const int ys = seg * seg_rows;
+    const int ye = min(ys + seg_rows, H);
+    const bool xin = x >= 0 && x < W;
+    const bool xint = x >= 1 && x <= W - 2;
+    const bool store = lane >= HALO && lane < 64 - HALO && x < W;
+    const size_t plane = (size_t)H * W;
+    const int xc = min(max(x, 0), W - 1);
+
+    float uL[S][3], uC[S][3], uR[S][3];   // u_k rows, k < S: left / centre / right
+    float txx[S][3], txy[S][3], tyy[S][3];   // T_k rows, k = 1..S
+    float cm[NC], ca[NC], cb[NC];         // tensor planes of the last NC rows
+    float qu[D], qm[D], qa[D], qb[D];     // rows in flight
+#pragma unroll
+    for (int k = 0; k < S; ++k)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            uL[k][j] = uC[k][j] = uR[k][j] = txx[k][j] = txy[k][j] = tyy[k][j] = 0.f;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) cm[j] = ca[j] = cb[j] = 0.f;
+
+    const int y0 = ys - HALO;           // first row loaded
+    const int y1 = ye + HALO;           // one past the last row needed
+    // rows are loaded from a clamped address and masked when consumed
+    auto issue = [&](int y, float &vu, float &vm, float &va, float &vb) {
+        const size_t o = (size_t)min(max(y, 0), H - 1) * W + xc;
+        vu = u[o];
+        vm = coef[o];
+        va = coef[plane + o];
+        vb = coef[2 * plane + o];
+    };
+#pragma unroll
+    for (int d = 0; d < D; ++d) issue(y0 + d, qu[d], qm[d], qa[d], qb[d]);
+
+    for (int yb = y0; yb < y1; yb += U) {
+#pragma unroll
+        for (int t = 0; t < U; ++t) {
+            const int y = yb + t;
+            // arrival of row y of u_0 and of the tensor planes
+            const int qs = t % D;
+            const float nu = (xin && y >= 0 && y < H) ? qu[qs] : 0.f;
+            cm[t % NC] = qm[qs];
+            ca[t % NC] = qa[qs];
+            cb[t % NC] = qb[qs];
+            issue(y + D, qu[qs], qm[qs], qa[qs], qb[qs]);
+            {
+                const int w0 = t % 3;
+                uC[0][w0] = nu;
+                uL[0][w0] = from_left(nu);
+                uR[0][w0] = from_right(nu);
+            }
+#pragma unroll
+            for (int k = 1; k <= S; ++k) {
+                // flux T_k at row q = y - (2k - 1) from u_{k-1} rows q-1, q, q+1
+                const int q = y - (2 * k - 1);
+                const int wn = (t - 2 * (k - 1) + 300) % 3;        // u_{k-1} row q+1
+                const int wc = (t - 2 * (k - 1) - 1 + 300) % 3;    // row q
+                const int wo = (t - 2 * (k - 1) - 2 + 300) % 3;    // row q-1
+                const int ci = (t - (2 * k - 1) + 2 * NC * 50) % NC;
+                const float v = uC[k - 1][wc];
+                const float hxx = uL[k - 1][wc] - 2.f * v + uR[k - 1][wc];
+                const float hyy = uC[k - 1][wo] - 2.f * v + uC[k - 1][wn];
+                const float hxy = 0.25f * ((uL[k - 1][wo] + uR[k - 1][wn]) - (uL[k - 1][wn] + uR[k - 1][wo]));
+                const float mb = cm[ci], al = ca[ci], be = cb[ci];
+                const bool on = xint && q >= 1 && q <= H - 2;
+                const int tw = (t - (2 * k - 1) + 300) % 3;
+                txx[k - 1][tw] = on ? (mb + al) * hxx + be * hxy : 0.f;
+                txy[k - 1][tw] = on ? mb * hxy + be * 0.5f * (hxx + hyy) : 0.f;
+                tyy[k - 1][tw] = on ? (mb - al) * hyy + be * hxy : 0.f;
+                // u_k at row p = y - 2k from T_k rows p-1, p, p+1 and u_{k-1} row p
+                const int p = y - 2 * k;
+                const int sn = tw;                            // T_k row p+1
+                const int sc = (t - 2 * k + 300) % 3;         // row p
+                const int so = (t - 2 * k - 1 + 300) % 3;     // row p-1
+                const float dxy = txy[k - 1][so] - txy[k - 1][sn];
+                const float el = txx[k - 1][sc] + 0.5f * dxy;
+                const float er = txx[k - 1][sc] - 0.5f * dxy;
+                const float r = (from_left(el) + from_right(er) - 2.f * txx[k - 1][sc]) +
+                                (tyy[k - 1][so] - 2.f * tyy[k - 1][sc] + tyy[k - 1][sn]);
+                const float nv = uC[k - 1][(t - 2 * k + 300) % 3] - taus.t[k - 1] * r;
+                if (k < S) {
+                    const int w = (t - 2 * k + 300) % 3;
+                    uC[k][w] = nv;
+                    uL[k][w] = from_left(nv);
+                    uR[k][w] = from_right(nv);
+                } else if (store && p >= ys && p < ye) {
+                    uo[(size_t)p * W + x] = nv;
+                }
+            }
+        }
+    }
 }
 
 }  // namespace
@@ -139,37 +384,68 @@ hipError_t launch_fed_substep(const float *u_in, float *u_out, const float *hrho
     dim3 grid(8 * per), block(256);
     switch (mode) {
     case MF4D_RIDGE:
-        hipLaunchKernelGGL(fed_substep_kernel<MF4D_RIDGE>, grid, block, 0, s, u_in, u_out, hrho, H, W,
-                           tau, inv_lam2, tiles_x, ntiles, per);
+        hipLaunchKernelGGL(fed_hrho_kernel<MF4D_RIDGE>, grid, block, 0, s, u_in, u_out, hrho, H, W, tau,
+                           inv_lam2, tiles_x, ntiles, per);
         break;
     case MF4D_VALLEY:
-        hipLaunchKernelGGL(fed_substep_kernel<MF4D_VALLEY>, grid, block, 0, s, u_in, u_out, hrho, H, W,
-                           tau, inv_lam2, tiles_x, ntiles, per);
+        hipLaunchKernelGGL(fed_hrho_kernel<MF4D_VALLEY>, grid, block, 0, s, u_in, u_out, hrho, H, W, tau,
+                           inv_lam2, tiles_x, ntiles, per);
         break;
     default:
-        hipLaunchKernelGGL(fed_substep_kernel<MF4D_BOTH>, grid, block, 0, s, u_in, u_out, hrho, H, W,
-                           tau, inv_lam2, tiles_x, ntiles, per);
+        hipLaunchKernelGGL(fed_hrho_kernel<MF4D_BOTH>, grid, block, 0, s, u_in, u_out, hrho, H, W, tau,
+                           inv_lam2, tiles_x, ntiles, per);
         break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_dparams(const float *hrho, float *dp, int H, int W, int mode, float inv_lam2,
-                          hipStream_t s)
+hipError_t launch_fed_stream(const float *u_in, float *u_out, const float *coef, int H, int W, int steps,
+                             const float *taus, int seg_rows, hipStream_t s)
 {
-    const size_t plane = (size_t)H * W;
-    dim3 grid((unsigned)((plane + 255) / 256)), block(256);
-    switch (mode) {
-    case MF4D_RIDGE:
-        hipLaunchKernelGGL(dparams_kernel<MF4D_RIDGE>, grid, block, 0, s, hrho, dp, plane, inv_lam2);
+    FedTaus t{};
+    for (int k = 0; k < steps; ++k) t.t[k] = taus[k];
+    const int outw = 64 - 4 * steps;
+    const int strips = (W + outw - 1) / outw;
+    const int segs = (H + seg_rows - 1) / seg_rows;
+    const int nblocks = (strips * segs + 3) / 4;
+    const int per = (nblocks + 7) / 8;
+    dim3 grid(8 * per), block(256);
+    switch (steps) {
+    case 1:
+        hipLaunchKernelGGL(fed_stream_kernel<1>, grid, block, 0, s, u_in, u_out, coef, H, W, t, strips, segs,
+                           seg_rows, per, nblocks);
         break;
-    case MF4D_VALLEY:
-        hipLaunchKernelGGL(dparams_kernel<MF4D_VALLEY>, grid, block, 0, s, hrho, dp, plane, inv_lam2);
+    case 2:
+        hipLaunchKernelGGL(fed_stream_kernel<2>, grid, block, 0, s, u_in, u_out, coef, H, W, t, strips, segs,
+                           seg_rows, per, nblocks);
+        break;
+    case 3:
+        hipLaunchKernelGGL(fed_stream_kernel<3>, grid, block, 0, s, u_in, u_out, coef, H, W, t, strips, segs,
+                           seg_rows, per, nblocks);
+        break;
+    case 4:
+        hipLaunchKernelGGL(fed_stream_kernel<4>, grid, block, 0, s, u_in, u_out, coef, H, W, t, strips, segs,
+                           seg_rows, per, nblocks);
         break;
     default:
-        hipLaunchKernelGGL(dparams_kernel<MF4D_BOTH>, grid, block, 0, s, hrho, dp, plane, inv_lam2);
-        break;
+        return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_fed_coef(const float *u_in, float *u_out, const float *coef, int H, int W, int steps,
+                           float tau0, float tau1, hipStream_t s)
+{
+    const int tiles_x = (W + kCW - 1) / kCW, tiles_y = (H + kCH - 1) / kCH;
+    const int ntiles = tiles_x * tiles_y;
+    const int per = (ntiles + 7) / 8;
+    dim3 grid(8 * per), block(256);
+    if (steps == 2)
+        hipLaunchKernelGGL(fed_coef_kernel<2>, grid, block, 0, s, u_in, u_out, coef, H, W, tau0, tau1,
+                           tiles_x, ntiles, per);
+    else
+        hipLaunchKernelGGL(fed_coef_kernel<1>, grid, block, 0, s, u_in, u_out, coef, H, W, tau0, tau0,
+                           tiles_x, ntiles, per);
     return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 // C ABI of libmf4d: validation, FED schedule, workspace layout and the
 // orchestration of the scale sweep, tensor and FED kernels on one stream.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -11,6 +12,7 @@ using namespace mf4d;
 namespace {
 
 constexpr double kTauLimit = 1.0 / 17.0;   // Eq. (20) at unit pixel spacing
+constexpr int kSubstepsPerLaunch = 4;
 
 int radius_of(double sigma)
 {
@@ -18,23 +20,32 @@ int radius_of(double sigma)
     return r < 1 ? 1 : r;
 }
 
-// Sampled Gaussian of radius max(1, ceil(3 sigma)) normalised to unit sum
-// (computed in double), and its central first and second differences.
-void make_taps(double sigma, Taps *t)
+// Sampled Gaussian of radius r = max(1, ceil(3 sigma)) normalised to unit sum
+// (computed in double), and its central first and second differences, laid
+// out as full correlation tables: entry t is the tap at offset i = t - R with
+// R = r + 1, i.e. G(i), (G(i-1) - G(i+1)) / 2 and G(i-1) - 2 G(i) + G(i+1),
+// zero-padded to a multiple of the register window.
+void make_taps(double sigma, WinTaps *t)
 {
     const int r = radius_of(sigma);
-    std::vector<double> g(r + 3, 0.0);
+    const int R = r + 1;
+    std::vector<double> g(2 * R + 3, 0.0);   // g[i + R + 1] = G(i), zero beyond r
     double sum = 0.0;
     for (int j = -r; j <= r; ++j) sum += std::exp(-(double)j * j / (2.0 * sigma * sigma));
-    for (int j = 0; j <= r; ++j) g[j] = std::exp(-(double)j * j / (2.0 * sigma * sigma)) / sum;
+    for (int j = -r; j <= r; ++j) g[j + R + 1] = std::exp(-(double)j * j / (2.0 * sigma * sigma)) / sum;
+    auto G = [&](int i) { return (i < -R - 1 || i > R + 1) ? 0.0 : g[i + R + 1]; };
     std::memset(t, 0, sizeof(*t));
-    t->r = r;
-    for (int i = 0; i <= r; ++i) t->g[i] = (float)g[i];
-    for (int i = 1; i <= r + 1; ++i) {
-        const double gm = g[i - 1], gp = g[i + 1];
-        t->d1[i] = (float)(0.5 * (gm - gp));
-        t->d2[i] = (float)(gm - 2.0 * g[i] + gp);
+    t->R = R;
+    t->ntaps = ((2 * R + 1 + kWin - 1) / kWin) * kWin;
+    float gs = 0.f;
+    for (int k = 0; k <= 2 * R; ++k) {
+        const int i = k - R;
+        t->g[k] = (float)G(i);
+        t->d1[k] = (float)(0.5 * (G(i - 1) - G(i + 1)));
+        t->d2[k] = (float)(G(i - 1) - 2.0 * G(i) + G(i + 1));
+        gs += t->g[k];
     }
+    t->gsum = gs;
 }
 
 void make_rho_taps(double rho, RhoTaps *t)
@@ -145,10 +156,10 @@ std::vector<double> natural_steps(int n, double T_over_M)
 }
 
 struct Workspace {
-    float *hA, *hB, *hC;     // horizontal pass, one scale at a time
+    float *hA, *hB, *hC;     // horizontal pass, one scale at a time; then N at the chosen scale
     float *S, *A, *N;        // per-scale planes
     uint8_t *idx;
-    float *hrho;
+    float *tens;             // compact tensor planes of the current cycle
     float *utmp;
     unsigned *smax;
 };
@@ -165,14 +176,14 @@ size_t layout(int H, int W, int ns, Workspace *w, char *base)
         return p;
     };
     Workspace t;
-    t.hA = (float *)take(m * 4);
-    t.hB = (float *)take(m * 4);
-    t.hC = (float *)take(m * 4);
+    t.hA = (float *)take(m * 12);
+    t.hB = t.hA ? t.hA + m : nullptr;
+    t.hC = t.hA ? t.hA + 2 * m : nullptr;
     t.S = (float *)take(m * 4 * ns);
     t.A = (float *)take(m * 4 * ns);
     t.N = (float *)take(m * 12 * ns);
     t.idx = (uint8_t *)take(m);
-    t.hrho = (float *)take(m * 12);
+    t.tens = (float *)take(m * 12);
     t.utmp = (float *)take(m * 4);
     t.smax = (unsigned *)take(256);
     if (w) *w = t;
@@ -187,6 +198,44 @@ int hip_status(hipError_t e) { return e == hipSuccess ? MF4D_OK : MF4D_EHIP; }
         if (e_ != hipSuccess) return MF4D_EHIP;      \
     } while (0)
 
+
+// Rows per wave of the streaming substep kernel. Measured on MI355X at
+// 4096 x 4096: ~96 rows for 3-4 substeps per launch, ~160 for 1-2; smaller
+// images use shorter segments so that the grid still has ~4k waves.
+// MF4D_STREAM_ROWS overrides (tuning).
+int stream_rows(int H, int W, int steps)
+{
+    static const int env = [] {
+        const char *e = std::getenv("MF4D_STREAM_ROWS");
+        return e ? std::atoi(e) : 0;
+    }();
+    if (env > 0) return env;
+    const int outw = 64 - 4 * steps;
+    const long long strips = (W + outw - 1) / outw;
+    const int target = steps >= 3 ? 96 : 160;
+    long long segs = (4096 + strips - 1) / strips;
+    int rows = (int)((H + segs - 1) / segs);
+    if (rows > target) rows = target;
+    return rows < 16 ? 16 : rows;
+}
+
+// Substeps of one cycle in launches of up to `spl` substeps.
+int run_substeps(const float *u_first, float *const bufs[2], int &launch_index, const float *coef, int H,
+                 int W, const float *tau32, int n, int spl, hipStream_t s, const float **last)
+{
+    const float *src = u_first;
+    for (int i = 0; i < n;) {
+        const int k = (n - i < spl) ? n - i : spl;
+        float *dst = bufs[launch_index % 2];
+        CHECK_HIP(launch_fed_stream(src, dst, coef, H, W, k, tau32 + i, stream_rows(H, W, k), s));
+        ++launch_index;
+        i += k;
+        src = dst;
+    }
+    *last = src;
+    return MF4D_OK;
+}
+
 // Scale sweep over all scales: S and blob planes (when want_sa), N planes
 // (when want_n) and the image-wide maximum of S.
 int run_sweep(const float *u, int H, int W, const mf4d_params *p, const Workspace &w,
@@ -194,7 +243,7 @@ int run_sweep(const float *u, int H, int W, const mf4d_params *p, const Workspac
 {
     const size_t m = (size_t)H * W;
     CHECK_HIP(launch_fill_u32(w.smax, 0u, 1, s));
-    Taps t;
+    WinTaps t;
     for (int k = 0; k < p->nscales; ++k) {
         make_taps(p->sigmas[k], &t);
         CHECK_HIP(launch_hpass(u, w.hA, w.hB, w.hC, H, W, t, s));
@@ -214,6 +263,7 @@ SelectArgs select_args(const mf4d_params *p, const Workspace &w)
     a.N = w.N;
     a.ns = p->nscales;
     a.smax_bits = w.smax;
+    a.nsel = w.hA;
     a.c_param = p->c;
     a.mode = p->mode;
     a.inv_lam2 = 1.f / (p->lambda * p->lambda);
@@ -344,8 +394,8 @@ int mf4d_tensor(const float *u, int H, int W, const uint8_t *idx, const mf4d_par
     SelectArgs a = select_args(p, w);
     a.idx_in = idx;
     a.hrho = hrho_out;
+    a.coef = dparams_out;
     CHECK_HIP(launch_select(a, H, W, s));
-    if (dparams_out) CHECK_HIP(launch_dparams(hrho_out, dparams_out, H, W, p->mode, a.inv_lam2, s));
     return MF4D_OK;
 }
 
@@ -371,6 +421,27 @@ int mf4d_fed_cycle(float *u, float *u_tmp, int H, int W, const float *hrho, cons
     return MF4D_OK;
 }
 
+int mf4d_fed_cycle_tensor(float *u, float *u_tmp, int H, int W, const float *dparams, const double *taus,
+                          int n, int steps_per_launch, void *stream)
+{
+    if (H < 3 || W < 3 || (long long)H * (long long)W >= (1LL << 31)) return MF4D_EINVAL;
+    if (!u || !u_tmp || u == u_tmp || !dparams || !taus || n < 1 || n > MF4D_MAX_SUBSTEPS)
+        return MF4D_EINVAL;
+    if (steps_per_launch < 1 || steps_per_launch > 4) return MF4D_EINVAL;
+    for (int i = 0; i < n; ++i)
+        if (!(taus[i] > 0.0) || !std::isfinite(taus[i])) return MF4D_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<float> tau32(n);
+    for (int i = 0; i < n; ++i) tau32[i] = (float)taus[i];
+    float *const bufs[2] = {u_tmp, u};
+    int li = 0;
+    const float *last = nullptr;
+    int st = run_substeps(u, bufs, li, dparams, H, W, tau32.data(), n, steps_per_launch, s, &last);
+    if (st != MF4D_OK) return st;
+    if (last != u) CHECK_HIP(launch_copy_f32(last, u, (size_t)H * W, s));
+    return MF4D_OK;
+}
+
 int mf4d_filter(const float *u_in, float *u_out, int H, int W, const mf4d_params *p, void *ws,
                 size_t ws_bytes, void *stream)
 {
@@ -390,38 +461,39 @@ int mf4d_filter(const float *u_in, float *u_out, int H, int W, const mf4d_params
     if (st != MF4D_OK) return st;
     std::vector<float> tau32(n);
     for (int i = 0; i < n; ++i) tau32[i] = (float)ordered[i];
+    // substeps run kSubstepsPerLaunch per launch (the intermediate images stay
+    // in registers); the last launch of a cycle takes the remainder
+    const int spl = kSubstepsPerLaunch;
+    const int launches_per_cycle = (n + spl - 1) / spl;
 
     Workspace w;
     layout(H, W, p->nscales, &w, (char *)ws);
-    // substep j writes `first` when j is even and `second` when j is odd, so
-    // that the last of the M n substeps writes u_out
-    const long long total = (long long)p->cycles * n;
-    float *first = (total % 2 == 1) ? u_out : w.utmp;
-    float *second = (total % 2 == 1) ? w.utmp : u_out;
+    // launch j writes bufs[j % 2]; the last launch must write u_out
+    const long long total = (long long)p->cycles * launches_per_cycle;
+    float *bufs[2];
+    bufs[0] = (total % 2 == 1) ? u_out : w.utmp;
+    bufs[1] = (total % 2 == 1) ? w.utmp : u_out;
     const float *src = u_in;
-    if ((const float *)first == u_in) {
-        // in-place call whose first substep would overwrite its own input
+    if ((const float *)bufs[0] == u_in) {
+        // in-place call whose first launch would overwrite its own input
         CHECK_HIP(launch_copy_f32(u_in, w.utmp, m, s));
         src = w.utmp;
-        first = u_out;
-        second = w.utmp;
+        bufs[0] = u_out;
+        bufs[1] = w.utmp;
     }
     SelectArgs a = select_args(p, w);
-    long long j = 0;
+    a.coef = w.tens;
+    int li = 0;
     for (int k = 0; k < p->cycles; ++k) {
         const bool reselect = (k == 0) || p->reselect_each_cycle;
         st = run_sweep(src, H, W, p, w, true, s);
         if (st != MF4D_OK) return st;
         SelectArgs ak = a;
-        ak.hrho = w.hrho;
         if (reselect) ak.idx_out = w.idx;
         else ak.idx_in = w.idx;
         CHECK_HIP(launch_select(ak, H, W, s));
-        for (int i = 0; i < n; ++i, ++j) {
-            float *dst = (j % 2 == 0) ? first : second;
-            CHECK_HIP(launch_fed_substep(src, dst, w.hrho, H, W, tau32[i], p->mode, a.inv_lam2, s));
-            src = dst;
-        }
+        st = run_substeps(src, bufs, li, w.tens, H, W, tau32.data(), n, spl, s, &src);
+        if (st != MF4D_OK) return st;
     }
     return MF4D_OK;
 }

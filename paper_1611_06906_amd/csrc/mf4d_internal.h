@@ -10,18 +10,19 @@
 namespace mf4d {
 
 constexpr int kMaxR = MF4D_MAX_RADIUS;   // Gaussian radius limit
-constexpr int kMaxRhoR = 8;              // integration-scale radius limit
+constexpr int kMaxRhoR = 8;              // integration-scale radius limit (0: none)
 
-// Separable filter taps of one scale, correlation form out[x] = sum_i k[i] in[x+i]:
-//   g[i]  Gaussian G_sigma, i = 0..r (symmetric)
-//   d1[i] central difference of G: (g[i-1] - g[i+1]) / 2, i = 1..r+1 (antisymmetric)
-//   d2[i] second difference of G: g[i-1] - 2 g[i] + g[i+1], i = 1..r+1 (symmetric,
-//         applied around the centre value so the filter sums to zero exactly)
-struct Taps {
-    int r;
-    float g[kMaxR + 2];
-    float d1[kMaxR + 2];
-    float d2[kMaxR + 2];
+// Full-width tap tables for the register-window passes: entry t holds the
+// tap at offset t - R (R = r + 1), zero-padded to a multiple of kWin.
+constexpr int kWin = 16;
+constexpr int kMaxTaps = ((2 * (kMaxR + 1) + 1 + kWin - 1) / kWin) * kWin;
+struct WinTaps {
+    int R;       // r + 1
+    int ntaps;   // padded tap count, multiple of kWin
+    float gsum;  // sum of the float32 Gaussian taps
+    float g[kMaxTaps];
+    float d1[kMaxTaps];
+    float d2[kMaxTaps];
 };
 
 struct RhoTaps {
@@ -38,11 +39,11 @@ struct ScalePlanes {
 
 // Horizontal pass of one scale: A = G u, B = D1G u, C = D2G u along x.
 hipError_t launch_hpass(const float *u, float *A, float *B, float *C, int H, int W,
-                        const Taps &t, hipStream_t s);
+                        const WinTaps &t, hipStream_t s);
 
 // Vertical pass of one scale plus the per-pixel vesselness ingredients.
 hipError_t launch_vpass(const float *A, const float *B, const float *C, int H, int W,
-                        const Taps &t, float sigma, int mode, float beta, ScalePlanes out,
+                        const WinTaps &t, float sigma, int mode, float beta, ScalePlanes out,
                         unsigned *smax_bits, hipStream_t s);
 
 hipError_t launch_fill_u32(unsigned *p, unsigned v, size_t n, hipStream_t s);
@@ -51,8 +52,8 @@ hipError_t launch_copy_f32(const float *src, float *dst, size_t n, hipStream_t s
 // Argmax over scales and/or normalised Hessian integration at the chosen scale.
 //   idx_in  != nullptr: use these indices (no argmax)
 //   idx_out != nullptr: write indices (tile interior)
-//   hrho    != nullptr: write H_rho (needs N planes)
-//   dparams != nullptr: write the compact tensor of H_rho
+//   hrho    != nullptr: write H_rho
+//   coef    != nullptr: write the compact tensor planes (m, al, be) of H_rho
 struct SelectArgs {
     const float *S;      // [ns][H][W]
     const float *A;      // [ns][H][W]
@@ -65,7 +66,8 @@ struct SelectArgs {
     float *vmax_out;
     float *c_out;
     float *hrho;
-    float *dparams;
+    float *coef;
+    float *nsel;         // [3][H][W] scratch: N at the chosen scale
     int mode;
     float inv_lam2;
     RhoTaps rho;
@@ -76,8 +78,14 @@ hipError_t launch_select(const SelectArgs &a, int H, int W, hipStream_t s);
 hipError_t launch_fed_substep(const float *u_in, float *u_out, const float *hrho, int H, int W,
                               float tau, int mode, float inv_lam2, hipStream_t s);
 
-// Compact tensor planes (m, al, be) of H_rho.
-hipError_t launch_dparams(const float *hrho, float *dp, int H, int W, int mode, float inv_lam2,
-                          hipStream_t s);
+// `steps` (1 or 2) consecutive substeps with steps tau0 (then tau1) from the
+// compact tensor planes (m, al, be) of the cycle.
+hipError_t launch_fed_coef(const float *u_in, float *u_out, const float *coef, int H, int W, int steps,
+                           float tau0, float tau1, hipStream_t s);
+
+// `steps` (1..4) consecutive substeps with taus[0..steps-1], one wave per
+// 64 - 4 steps columns x seg_rows rows, intermediate images in registers.
+hipError_t launch_fed_stream(const float *u_in, float *u_out, const float *coef, int H, int W, int steps,
+                             const float *taus, int seg_rows, hipStream_t s);
 
 }  // namespace mf4d

@@ -24,7 +24,8 @@ MF4D_MAX_SCALES, MF4D_MAX_RADIUS, MF4D_MAX_SUBSTEPS = 16, 64, 1024
 # every symbol include/mf4d.h declares
 EXPORTS = ["mf4d_status_string", "mf4d_params_default", "mf4d_fed_schedule",
            "mf4d_fed_substeps", "mf4d_fed_plan", "mf4d_workspace_bytes",
-           "mf4d_scale_select", "mf4d_tensor", "mf4d_fed_cycle", "mf4d_filter"]
+           "mf4d_scale_select", "mf4d_tensor", "mf4d_fed_cycle", "mf4d_fed_cycle_tensor",
+           "mf4d_filter"]
 
 
 class MF4DError(RuntimeError):
@@ -119,6 +120,8 @@ def lib():
         L.mf4d_tensor.restype = i
         L.mf4d_fed_cycle.argtypes = [vp, vp, i, i, vp, P(mf4d_params), P(d), i, vp]
         L.mf4d_fed_cycle.restype = i
+        L.mf4d_fed_cycle_tensor.argtypes = [vp, vp, i, i, vp, P(d), i, i, vp]
+        L.mf4d_fed_cycle_tensor.restype = i
         L.mf4d_filter.argtypes = [vp, vp, i, i, P(mf4d_params), vp, sz, vp]
         L.mf4d_filter.restype = i
         _lib = L
@@ -242,6 +245,16 @@ def mf4d_fed_cycle(u, u_tmp, hrho, params: Params, taus, stream=None):
     _check(lib().mf4d_fed_cycle(_ptr(u), _ptr(u_tmp), H, W, _ptr(hrho), ctypes.byref(st),
                                 t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(t),
                                 _stream(stream)), "mf4d_fed_cycle")
+
+
+def mf4d_fed_cycle_tensor(u, u_tmp, dparams, taus, steps_per_launch=2, stream=None):
+    H, W = _hw(_dev(u, torch.float32, name="u"))
+    _dev(u_tmp, torch.float32, (H, W), "u_tmp")
+    _dev(dparams, torch.float32, (3, H, W), "dparams")
+    t = np.ascontiguousarray(np.asarray(taus, dtype=np.float64))
+    _check(lib().mf4d_fed_cycle_tensor(_ptr(u), _ptr(u_tmp), H, W, _ptr(dparams),
+                                       t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(t),
+                                       int(steps_per_launch), _stream(stream)), "mf4d_fed_cycle_tensor")
 
 
 def mf4d_filter(u_in, u_out, params: Params, ws=None, stream=None):

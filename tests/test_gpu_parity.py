@@ -262,3 +262,35 @@ def test_filter_parity_fundus1024(env):
     e, r = _err(got, ref)
     _log(f"  max-abs {e:.3e} rel-L2 {r:.3e}")
     assert e <= MAXABS and r <= RELL2
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("shape", [(67, 131), (130, 70), (3, 3), (5, 200)])
+def test_fed_cycle_tensor_parity(env, mode, shape):
+    """Cycles from the compact tensor planes (1 and 2 substeps per launch)
+    against the oracle's literal 4x4 tensor built from the same H_rho."""
+    o, m, torch, synth = env["o"], env["m"], env["torch"], env["synth"]
+    H, W = shape
+    _log(f"fed_cycle_tensor parity {shape} mode {mode}")
+    u = synth.creases(H, W, 3, seed=H + 3 * W + mode)
+    sig = [1.0, 2.0]
+    idx = o.scale_select(u, sig, mode)["idx"]
+    p = m.Params(sig, mode=mode)
+    hr = torch.empty((3, H, W), dtype=torch.float32, device=env["dev"])
+    dp = torch.empty_like(hr)
+    m.mf4d_tensor(_to(env, u), _to(env, idx), p, hr, dp)
+    torch.cuda.synchronize()
+    D = o.dtensor(hr.cpu().numpy().astype(np.float64), float(np.float32(0.005)), mode)
+    for n in (1, 2, 7, 20):
+        taus, _, _ = m.mf4d_fed_schedule(n, 0.05)
+        ref = o.fed_cycle(u.astype(np.float64), D, o.fed_schedule(n, 0.05)[0])
+        outs = []
+        for spl in (1, 2):
+            ug = _to(env, u)
+            tmp = torch.empty_like(ug)
+            m.mf4d_fed_cycle_tensor(ug, tmp, dp, taus, spl)
+            torch.cuda.synchronize()
+            outs.append(ug.cpu().numpy())
+            e, r = _err(outs[-1], ref)
+            assert e <= MAXABS and r <= RELL2, (shape, mode, n, spl, e, r)
+        assert np.array_equal(outs[0], outs[1])   # temporal blocking changes no value
