@@ -25,7 +25,37 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
-SUBSTEP_BYTES_PER_PX = 20  # u in 4 + H_rho in 12 + u out 4
+# FP32 vector peak without packed FP32: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+VALU_PEAK = 78.6e12        # FLOP/s
+SUBSTEP_BYTES_PER_PX = 20  # per launch: u in 4 + tensor planes in 12 + u out 4
+SUBSTEP_FLOPS_PER_PX = 37  # per substep: L u 10, D L u 13, L^T and update 14
+SUBSTEPS_PER_LAUNCH = 4    # as mf4d_filter launches the fused substep kernel
+
+
+def counter_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, calibrated on a plain copy),
+    or None if the kernel source changed since the counters were taken."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "creases4096_hbm_counters.txt")
+    src = os.path.join(ROOT, "paper_1611_06906_amd", "csrc", "fed_kernels.hip")
+    try:
+        text = open(prof).read()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if f"sha256 prefix: {digest}" not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith(kernel + " ") or line.startswith("void " + kernel + " "):
+            cols = line.split()
+            try:
+                i = cols.index(next(c for c in cols if c.replace(".", "").isdigit() and "." in c))
+                read_mb, write_mb = float(cols[i + 2]), float(cols[i + 3])
+            except (StopIteration, ValueError, IndexError):
+                return None
+            return (read_mb + write_mb) * 1e6
+    return None
 
 
 def _events(torch):
@@ -85,35 +115,58 @@ def main():
     print(f"[bench] {args.steps} steps, {ms:.2f} ms/step, {value:.0f} Mpx-substeps/s", file=sys.stderr,
           flush=True)
 
-    # roofline of the fused FED substep: same kernel and shapes, H_rho of the workload
+    # roofline of the fused FED substep kernel as the filter launches it: same
+    # kernel, shapes, substeps per launch and tensor planes of the workload
     n, taus = mf4d.mf4d_fed_plan(p)
     hrho = torch.empty((3, w.H, w.W), dtype=torch.float32, device=dev)
+    dpar = torch.empty_like(hrho)
     idx = torch.empty((w.H, w.W), dtype=torch.uint8, device=dev)
     mf4d.mf4d_scale_select(u_in, p, idx, None, None, ws)
-    mf4d.mf4d_tensor(u_in, idx, p, hrho, None, ws)
+    mf4d.mf4d_tensor(u_in, idx, p, hrho, dpar, ws)
     uc = u_in.clone()
     ut = torch.empty_like(uc)
-    cyc = lambda: mf4d.mf4d_fed_cycle(uc, ut, hrho, p, taus)
+    spl = SUBSTEPS_PER_LAUNCH
+    # two cycles' steps per call: an even number of full launches, so the
+    # timing holds only the substep kernel (no remainder launch, no copy-back)
+    taus2 = np.concatenate([taus, taus])
+    launches = 2 * n // spl
+    assert (2 * n) % spl == 0 and launches % 2 == 0
+    cyc = lambda: mf4d.mf4d_fed_cycle_tensor(uc, ut, dpar, taus2, spl)
     cyc()
-    reps = 5
+    reps = 10
     ms_cycle = time_stream(torch, cyc, reps)
-    ms_substep = ms_cycle / n   # n even: no copy-back launch in the cycle
-    achieved = SUBSTEP_BYTES_PER_PX * w.H * w.W / (ms_substep * 1e-3)
-    roofline = {"bound": "hbm", "kernel": "fed_substep_kernel", "achieved": achieved / 1e9,
-                "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None,
-                "us_per_launch": ms_substep * 1e3, "bytes_per_px": SUBSTEP_BYTES_PER_PX}
+    us_launch = ms_cycle * 1e3 / launches
+    t = us_launch * 1e-6
+    m = w.H * w.W
+    flops = SUBSTEP_FLOPS_PER_PX * spl * m / t
+    hbm = SUBSTEP_BYTES_PER_PX * m / t
+    roofline = {"bound": "alu", "kernel": f"fed_stream_kernel<{spl}> (fused FED substep, {spl} substeps per launch)",
+                "achieved": flops / 1e12, "peak": VALU_PEAK / 1e12, "unit": "TFLOP/s",
+                "frac": flops / VALU_PEAK, "traffic": counter_traffic(f"fed_stream_kernel<{spl}>"),
+                "traffic_unit": "B per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
+                "us_per_launch": us_launch,
+                "hbm_achieved_GBs": hbm / 1e9, "hbm_frac": hbm / HBM_PEAK,
+                "hbm_per_substep_equivalent_GBs": hbm * spl / 1e9,
+                "flops_per_px_substep": SUBSTEP_FLOPS_PER_PX, "bytes_per_px_launch": SUBSTEP_BYTES_PER_PX}
+    # the same kernel at one substep per launch is HBM-bound: report it too
+    ms1 = time_stream(torch, lambda: mf4d.mf4d_fed_cycle_tensor(uc, ut, dpar, taus2, 1), reps)
+    t1 = ms1 * 1e-3 / (2 * n)
+    roofline_single = {"bound": "hbm", "kernel": "fed_stream_kernel<1>", "achieved": SUBSTEP_BYTES_PER_PX * m / t1 / 1e9,
+                       "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": SUBSTEP_BYTES_PER_PX * m / t1 / HBM_PEAK,
+                       "us_per_launch": t1 * 1e6}
 
-    # one single-step cycle: a substep plus the plain copy of H*W floats back
-    # into u (4 B read + 4 B write per pixel), the reference for HBM counters
+    # a one-substep cycle from H_rho: that substep plus the plain copy of H*W
+    # floats back into u (4 B read + 4 B write per pixel), the reference for
+    # HBM counters
     mf4d.mf4d_fed_cycle(uc, ut, hrho, p, taus[:1])
     torch.cuda.synchronize()
 
     stages = None
     if not args.no_stages:
         sel_ms = time_stream(torch, lambda: mf4d.mf4d_scale_select(u_in, p, idx, None, None, ws), 3)
-        ten_ms = time_stream(torch, lambda: mf4d.mf4d_tensor(u_in, idx, p, hrho, None, ws), 3)
-        stages = {"scale_select_ms": sel_ms, "tensor_incl_sweep_ms": ten_ms,
-                  "fed_cycle_ms": ms_cycle, "cycles": w.cycles}
+        ten_ms = time_stream(torch, lambda: mf4d.mf4d_tensor(u_in, idx, p, hrho, dpar, ws), 3)
+        stages = {"per_cycle_scale_select_ms": sel_ms, "per_cycle_tensor_incl_sweep_ms": ten_ms,
+                  "per_cycle_substeps_ms": ms_cycle / 2, "cycles": w.cycles}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -147,6 +200,7 @@ def main():
                    "H": w.H, "W": w.W, "cycles": w.cycles, "substeps": w.substeps,
                    "nscales": len(w.sigmas), "mode": "both", "path": "plain"},
         "roofline": roofline,
+        "roofline_single_substep": roofline_single,
         "cpu_baseline": cpu,
         "stages": stages,
     }
