@@ -191,6 +191,53 @@ int mf4d_fed_cycle_tensor(float *u, float *u_tmp, int H, int W, const float *dpa
 int mf4d_filter(const float *u_in, float *u_out, int H, int W, const mf4d_params *p,
                 void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------ batches */
+
+/* A batch plan: many images of different sizes filtered together. Every
+ * stage of the filter is one launch over all images of the batch and the
+ * whole launch sequence is recorded once into a hipGraph that each
+ * mf4d_filter_batch call replays; each image's result is identical to a
+ * separate mf4d_filter call with its own parameters. */
+typedef struct mf4d_batch mf4d_batch;
+
+/* Creates a plan for nimg images packed in one device buffer: image i is
+ * float32 [H[i]][W[i]] starting at element offsets[i] (images must not
+ * overlap). per_image[i] are its filter parameters: mode and cycles may
+ * differ between images; every other field (scales, lambda, rho, beta, c,
+ * substeps, stop_time, tau_max, reselect_each_cycle) must equal image 0's
+ * (with substeps == 0, cycles must match too). All arrays are host memory
+ * and are copied. *plan receives the plan (destroy with mf4d_batch_destroy).
+ * Errors: MF4D_EINVAL. */
+int mf4d_batch_create(int nimg, const int64_t *offsets, const int *H, const int *W,
+                      const mf4d_params *per_image, mf4d_batch **plan);
+
+/* Device workspace bytes mf4d_filter_batch and mf4d_batch_autotune need. */
+size_t mf4d_batch_workspace_bytes(const mf4d_batch *plan);
+
+/* Runs the filter on every image of the plan. packed_in / packed_out are
+ * device buffers laid out as given to mf4d_batch_create; packed_out may alias
+ * packed_in. The first call for a given (packed_in, packed_out, ws) uploads
+ * the plan's tables into ws, synchronises `stream` and records the graph;
+ * later calls only launch the graph on `stream`. Calls on one plan must not
+ * overlap. Errors: MF4D_EINVAL, MF4D_ENOMEM, MF4D_EHIP. */
+int mf4d_filter_batch(mf4d_batch *plan, const float *packed_in, float *packed_out, void *ws,
+                      size_t ws_bytes, void *stream);
+
+/* Autotuner: times the fused substep kernel on the plan's shapes for each
+ * candidate decomposition (substeps per launch 2..4, rows per wave) and keeps
+ * the fastest in the plan; no result value depends on this choice. Uses ws
+ * as scratch (its contents are overwritten) and synchronises `stream`.
+ * Errors: MF4D_EINVAL, MF4D_ENOMEM, MF4D_EHIP. */
+int mf4d_batch_autotune(mf4d_batch *plan, void *ws, size_t ws_bytes, void *stream);
+
+/* Reads / sets the substep decomposition of a plan (substeps per launch 1..4,
+ * rows per wave, 0 = default). Errors: MF4D_EINVAL. */
+int mf4d_batch_get_tuning(const mf4d_batch *plan, int *substeps_per_launch, int *rows_per_wave);
+int mf4d_batch_set_tuning(mf4d_batch *plan, int substeps_per_launch, int rows_per_wave);
+
+/* Releases a plan and its recorded graph. Errors: MF4D_EINVAL (NULL). */
+int mf4d_batch_destroy(mf4d_batch *plan);
+
 #ifdef __cplusplus
 }
 #endif

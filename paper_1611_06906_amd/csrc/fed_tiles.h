@@ -1,0 +1,144 @@
+// Wave-level device code of the row-streaming FED substep kernel, shared by
+// the single-image and the batched launches.
+#pragma once
+
+#include "mf4d_internal.h"
+
+namespace mf4d {
+namespace tiles {
+
+// ------------------------------------------------------------ row streaming
+// fed_stream_kernel<S>: S consecutive substeps per launch without LDS or
+// barriers. A wave owns 64 adjacent columns (lane = column) and walks down a
+// segment of rows; every intermediate quantity lives in per-lane register
+// rings indexed by row, and x-neighbours come from lane shifts. Each level
+// of the substep pipeline (flux T_k, then u_k) lags the previous one by one
+// row and spoils one more lane at each wave edge, so a wave owns 64 - 4 S
+// output columns and reads u and the tensor planes with a 2 S lane and 2 S
+// row halo.
+//
+// With D(x) = T_xy(p-1, x) - T_xy(p+1, x) the divergence at row p is
+//   r = [T_xx(p) + D/2](x-1) + [T_xx(p) - D/2](x+1) - 2 T_xx(p)(x)
+//       + T_yy(p-1) - 2 T_yy(p) + T_yy(p+1),
+// i.e. L_xx^T T_xx + 2 L_xy^T T_xy + L_yy^T T_yy with two lane shifts.
+
+// lane i receives the value of lane i - 1 (x - 1) / lane i + 1 (x + 1); the
+// wave's edge lanes receive 0, which only ever reaches halo lanes.
+__device__ __forceinline__ float from_left(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float from_right(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+
+template <int S>
+__device__ __forceinline__ void fed_stream_wave(const float *__restrict__ u, float *__restrict__ uo,
+                                                const float *__restrict__ coef, int H, int W, const FedTaus &taus,
+                                                int strip, int seg, int seg_rows)
+{
+#pragma clang fp contract(off)   // fused multiply-adds are written out: every launch shape rounds alike
+    constexpr int HALO = 2 * S;
+    constexpr int OUTW = 64 - 2 * HALO;
+    constexpr int D = 8;                                  // rows loaded ahead
+    constexpr int NC = 2 * S;                             // tensor rows kept
+    constexpr int U = 24;                                 // unroll: multiple of 3, NC and D
+    const int lane = threadIdx.x & 63;
+    const int x = strip * OUTW - HALO + lane;
+    const int ys = seg * seg_rows;
+    const int ye = min(ys + seg_rows, H);
+    const bool xin = x >= 0 && x < W;
+    const bool xint = x >= 1 && x <= W - 2;
+    const bool store = lane >= HALO && lane < 64 - HALO && x < W;
+    const size_t plane = (size_t)H * W;
+    const int xc = min(max(x, 0), W - 1);
+
+    float uL[S][3], uC[S][3], uR[S][3];   // u_k rows, k < S: left / centre / right
+    float txx[S][3], txy[S][3], tyy[S][3];   // T_k rows, k = 1..S
+    float cm[NC], ca[NC], cb[NC];         // tensor planes of the last NC rows
+    float qu[D], qm[D], qa[D], qb[D];     // rows in flight
+#pragma unroll
+    for (int k = 0; k < S; ++k)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            uL[k][j] = uC[k][j] = uR[k][j] = txx[k][j] = txy[k][j] = tyy[k][j] = 0.f;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) cm[j] = ca[j] = cb[j] = 0.f;
+
+    const int y0 = ys - HALO;           // first row loaded
+    const int y1 = ye + HALO;           // one past the last row needed
+    // rows are loaded from a clamped address and masked when consumed
+    auto issue = [&](int y, float &vu, float &vm, float &va, float &vb) {
+        const size_t o = (size_t)min(max(y, 0), H - 1) * W + xc;
+        vu = u[o];
+        vm = coef[o];
+        va = coef[plane + o];
+        vb = coef[2 * plane + o];
+    };
+#pragma unroll
+    for (int d = 0; d < D; ++d) issue(y0 + d, qu[d], qm[d], qa[d], qb[d]);
+
+    for (int yb = y0; yb < y1; yb += U) {
+#pragma unroll
+        for (int t = 0; t < U; ++t) {
+            const int y = yb + t;
+            // arrival of row y of u_0 and of the tensor planes
+            const int qs = t % D;
+            const float nu = (xin && y >= 0 && y < H) ? qu[qs] : 0.f;
+            cm[t % NC] = qm[qs];
+            ca[t % NC] = qa[qs];
+            cb[t % NC] = qb[qs];
+            issue(y + D, qu[qs], qm[qs], qa[qs], qb[qs]);
+            {
+                const int w0 = t % 3;
+                uC[0][w0] = nu;
+                uL[0][w0] = from_left(nu);
+                uR[0][w0] = from_right(nu);
+            }
+#pragma unroll
+            for (int k = 1; k <= S; ++k) {
+                // flux T_k at row q = y - (2k - 1) from u_{k-1} rows q-1, q, q+1
+                const int q = y - (2 * k - 1);
+                const int wn = (t - 2 * (k - 1) + 300) % 3;        // u_{k-1} row q+1
+                const int wc = (t - 2 * (k - 1) - 1 + 300) % 3;    // row q
+                const int wo = (t - 2 * (k - 1) - 2 + 300) % 3;    // row q-1
+                const int ci = (t - (2 * k - 1) + 2 * NC * 50) % NC;
+                const float v = uC[k - 1][wc];
+                const float hxx = fmaf(-2.f, v, uL[k - 1][wc] + uR[k - 1][wc]);
+                const float hyy = fmaf(-2.f, v, uC[k - 1][wo] + uC[k - 1][wn]);
+                const float hxy = 0.25f * ((uL[k - 1][wo] + uR[k - 1][wn]) - (uL[k - 1][wn] + uR[k - 1][wo]));
+                const float mb = cm[ci], al = ca[ci], be = cb[ci];
+                const bool on = xint && q >= 1 && q <= H - 2;
+                const int tw = (t - (2 * k - 1) + 300) % 3;
+                const float bxy = be * hxy;
+                txx[k - 1][tw] = on ? fmaf(mb + al, hxx, bxy) : 0.f;
+                txy[k - 1][tw] = on ? fmaf(mb, hxy, (be * 0.5f) * (hxx + hyy)) : 0.f;
+                tyy[k - 1][tw] = on ? fmaf(mb - al, hyy, bxy) : 0.f;
+                // u_k at row p = y - 2k from T_k rows p-1, p, p+1 and u_{k-1} row p
+                const int p = y - 2 * k;
+                const int sn = tw;                            // T_k row p+1
+                const int sc = (t - 2 * k + 300) % 3;         // row p
+                const int so = (t - 2 * k - 1 + 300) % 3;     // row p-1
+                const float dxy = txy[k - 1][so] - txy[k - 1][sn];
+                const float el = fmaf(0.5f, dxy, txx[k - 1][sc]);
+                const float er = fmaf(-0.5f, dxy, txx[k - 1][sc]);
+                const float rx = fmaf(-2.f, txx[k - 1][sc], from_left(el) + from_right(er));
+                const float ry = fmaf(-2.f, tyy[k - 1][sc], tyy[k - 1][so] + tyy[k - 1][sn]);
+                const float r = rx + ry;
+                const float nv = fmaf(-taus.t[k - 1], r, uC[k - 1][(t - 2 * k + 300) % 3]);
+                if (k < S) {
+                    const int w = (t - 2 * k + 300) % 3;
+                    uC[k][w] = nv;
+                    uL[k][w] = from_left(nv);
+                    uR[k][w] = from_right(nv);
+                } else if (store && p >= ys && p < ye) {
+                    uo[(size_t)p * W + x] = nv;
+                }
+            }
+        }
+    }
+}
+
+}  // namespace tiles
+}  // namespace mf4d

@@ -291,6 +291,30 @@ int plan(const mf4d_params *p, int *n_out, std::vector<double> &ordered)
 
 }  // namespace
 
+namespace mf4d {
+// host helpers shared with the batch module (batch.hip)
+int validate_params(int H, int W, const mf4d_params *p) { return validate(H, W, p); }
+size_t image_workspace_bytes(int H, int W, int ns) { return layout(H, W, ns, nullptr, nullptr); }
+void image_workspace(int H, int W, int ns, char *base, float **hA, float **S, float **A, float **N,
+                     uint8_t **idx, float **tens, float **utmp, unsigned **smax)
+{
+    Workspace w;
+    layout(H, W, ns, &w, base);
+    *hA = w.hA;
+    *S = w.S;
+    *A = w.A;
+    *N = w.N;
+    *idx = w.idx;
+    *tens = w.tens;
+    *utmp = w.utmp;
+    *smax = w.smax;
+}
+void window_taps(double sigma, WinTaps *t) { make_taps(sigma, t); }
+void rho_taps(double rho, RhoTaps *t) { make_rho_taps(rho, t); }
+int fed_plan_host(const mf4d_params *p, int *n_out, std::vector<double> &ordered) { return plan(p, n_out, ordered); }
+int default_stream_rows(int H, int W, int steps) { return stream_rows(H, W, steps); }
+}  // namespace mf4d
+
 extern "C" {
 
 const char *mf4d_status_string(int status)

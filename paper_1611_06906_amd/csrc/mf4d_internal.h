@@ -25,6 +25,11 @@ struct WinTaps {
     float d2[kMaxTaps];
 };
 
+// Step sizes of the substeps of one streaming launch.
+struct FedTaus {
+    float t[4];
+};
+
 struct RhoTaps {
     int r;  // 0: identity
     float g[kMaxRhoR + 1];

@@ -28,9 +28,10 @@ template <int MODE>
 __device__ __forceinline__ void tensor_coeffs(float a, float b, float d, float inv_lam2,
                                               float &mbar, float &al, float &be)
 {
+#pragma clang fp contract(off)   // fused multiply-adds are written out
     const float mm = 0.5f * (a + d);
     const float hd = 0.5f * (a - d);
-    const float r = sqrtf(hd * hd + b * b);
+    const float r = sqrtf(fmaf(hd, hd, b * b));
     const float nu1 = mm + r, nu2 = mm - r;
     const float q1 = nu1 * nu1 * inv_lam2, q2 = nu2 * nu2 * inv_lam2;
     float mu1 = 1.f / (1.f + q1), mu2 = 1.f / (1.f + q2);

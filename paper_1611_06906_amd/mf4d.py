@@ -25,7 +25,8 @@ MF4D_MAX_SCALES, MF4D_MAX_RADIUS, MF4D_MAX_SUBSTEPS = 16, 64, 1024
 EXPORTS = ["mf4d_status_string", "mf4d_params_default", "mf4d_fed_schedule",
            "mf4d_fed_substeps", "mf4d_fed_plan", "mf4d_workspace_bytes",
            "mf4d_scale_select", "mf4d_tensor", "mf4d_fed_cycle", "mf4d_fed_cycle_tensor",
-           "mf4d_filter"]
+           "mf4d_filter", "mf4d_batch_create", "mf4d_batch_workspace_bytes", "mf4d_filter_batch",
+           "mf4d_batch_autotune", "mf4d_batch_get_tuning", "mf4d_batch_set_tuning", "mf4d_batch_destroy"]
 
 
 class MF4DError(RuntimeError):
@@ -124,6 +125,20 @@ def lib():
         L.mf4d_fed_cycle_tensor.restype = i
         L.mf4d_filter.argtypes = [vp, vp, i, i, P(mf4d_params), vp, sz, vp]
         L.mf4d_filter.restype = i
+        L.mf4d_batch_create.argtypes = [i, P(ctypes.c_int64), P(i), P(i), P(mf4d_params), P(vp)]
+        L.mf4d_batch_create.restype = i
+        L.mf4d_batch_workspace_bytes.argtypes = [vp]
+        L.mf4d_batch_workspace_bytes.restype = sz
+        L.mf4d_filter_batch.argtypes = [vp, vp, vp, vp, sz, vp]
+        L.mf4d_filter_batch.restype = i
+        L.mf4d_batch_autotune.argtypes = [vp, vp, sz, vp]
+        L.mf4d_batch_autotune.restype = i
+        L.mf4d_batch_get_tuning.argtypes = [vp, P(i), P(i)]
+        L.mf4d_batch_get_tuning.restype = i
+        L.mf4d_batch_set_tuning.argtypes = [vp, i, i]
+        L.mf4d_batch_set_tuning.restype = i
+        L.mf4d_batch_destroy.argtypes = [vp]
+        L.mf4d_batch_destroy.restype = i
         _lib = L
     return _lib
 
@@ -266,3 +281,66 @@ def mf4d_filter(u_in, u_out, params: Params, ws=None, stream=None):
     st = params.struct()
     _check(lib().mf4d_filter(_ptr(u_in), _ptr(u_out), H, W, ctypes.byref(st), _ptr(ws), ws.numel(),
                              _stream(stream)), "mf4d_filter")
+
+
+# ------------------------------------------------------------------ batches
+class Batch:
+    """A batch plan (mf4d_batch_create) for images packed in one buffer.
+
+    shapes: list of (H, W); params: list of Params (mode and cycles may
+    differ). offsets default to the images packed back to back.
+    """
+
+    def __init__(self, shapes, params, offsets=None):
+        self.shapes = [(int(h), int(w)) for h, w in shapes]
+        if offsets is None:
+            offsets = np.concatenate([[0], np.cumsum([h * w for h, w in self.shapes])[:-1]])
+        self.offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        self.total = int(max(o + h * w for o, (h, w) in zip(self.offsets, self.shapes)))
+        self._params = list(params)
+        arr = (mf4d_params * len(params))(*[p.struct() for p in params])
+        H = (ctypes.c_int * len(shapes))(*[h for h, _ in self.shapes])
+        W = (ctypes.c_int * len(shapes))(*[w for _, w in self.shapes])
+        h = ctypes.c_void_p()
+        _check(lib().mf4d_batch_create(len(shapes), self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                       H, W, arr, ctypes.byref(h)), "mf4d_batch_create")
+        self.handle = h
+
+    def workspace_bytes(self) -> int:
+        return int(lib().mf4d_batch_workspace_bytes(self.handle))
+
+    def workspace(self, device="cuda"):
+        return torch.empty(self.workspace_bytes(), dtype=torch.uint8, device=device)
+
+    def autotune(self, ws, stream=None):
+        _dev(ws, torch.uint8, name="ws")
+        _check(lib().mf4d_batch_autotune(self.handle, _ptr(ws), ws.numel(), _stream(stream)), "mf4d_batch_autotune")
+
+    def tuning(self):
+        a, b = ctypes.c_int(0), ctypes.c_int(0)
+        _check(lib().mf4d_batch_get_tuning(self.handle, ctypes.byref(a), ctypes.byref(b)), "mf4d_batch_get_tuning")
+        return a.value, b.value
+
+    def set_tuning(self, substeps_per_launch, rows_per_wave=0):
+        _check(lib().mf4d_batch_set_tuning(self.handle, int(substeps_per_launch), int(rows_per_wave)),
+               "mf4d_batch_set_tuning")
+
+    def filter(self, packed_in, packed_out, ws, stream=None):
+        _dev(packed_in, torch.float32, name="packed_in")
+        _dev(packed_out, torch.float32, name="packed_out")
+        _dev(ws, torch.uint8, name="ws")
+        if packed_in.numel() < self.total or packed_out.numel() < self.total:
+            raise ValueError("packed buffers are smaller than the plan's layout")
+        _check(lib().mf4d_filter_batch(self.handle, _ptr(packed_in), _ptr(packed_out), _ptr(ws), ws.numel(),
+                                       _stream(stream)), "mf4d_filter_batch")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().mf4d_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -106,3 +106,27 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(mf4d, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError):
         mf4d.lib()
+
+
+def test_batch_plan_validation(m):
+    sig = [1.0, 2.0]
+    P = m.Params
+    shapes = [(32, 40), (20, 20)]
+    b = m.Batch(shapes, [P(sig, mode=0, cycles=2), P(sig, mode=1, cycles=5)])
+    assert b.workspace_bytes() > m.mf4d_workspace_bytes(32, 40, P(sig))
+    assert b.tuning()[0] in (1, 2, 3, 4)
+    b.set_tuning(2, 64)
+    assert b.tuning() == (2, 64)
+    with pytest.raises(m.MF4DError):
+        b.set_tuning(5, 0)
+    b.close()
+    bad = [
+        (shapes, [P(sig), P([1.0, 3.0])], None),                    # different scales
+        (shapes, [P(sig), P(sig, lam=0.01)], None),                 # different lambda
+        (shapes, [P(sig, substeps=5), P(sig, substeps=6)], None),   # different schedule
+        (shapes, [P(sig), P(sig)], [0, 100]),                       # overlapping images
+        ([(2, 40), (20, 20)], [P(sig), P(sig)], None),              # invalid size
+    ]
+    for sh, prm, off in bad:
+        with pytest.raises(m.MF4DError):
+            m.Batch(sh, prm, offsets=off)
