@@ -74,6 +74,63 @@ def time_stream(torch, fn, reps):
     return s.elapsed_time(e) / reps
 
 
+def _batch_image(spec):
+    from paper_1611_06906_amd import synth
+    return synth.batch_image(spec)
+
+
+def batched_comparison(torch, mf4d, synth, dev, reps=2):
+    """256 uneven images (sizes U[256, 1536], ridge/valley, cycles U[5, 25],
+    scales 1, 1.5, 2, 3, n = 10): one batched graph vs per-image calls."""
+    import numpy as np
+    from concurrent.futures import ProcessPoolExecutor
+    specs = synth.batch_of_images()
+    t0 = time.time()
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    with ProcessPoolExecutor(workers) as ex:
+        imgs = list(ex.map(_batch_image, specs, chunksize=4))
+    print(f"[bench] batch of {len(imgs)} images generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    sig = [1.0, 1.5, 2.0, 3.0]
+    params = [mf4d.Params(sig, mode=sp["mode"], cycles=sp["cycles"], substeps=10) for sp in specs]
+    shapes = [(sp["H"], sp["W"]) for sp in specs]
+    packed = torch.from_numpy(np.concatenate([im.ravel() for im in imgs])).to(dev)
+    out_b = torch.empty_like(packed)
+    plan = mf4d.Batch(shapes, params)
+    ws_b = plan.workspace(dev)
+    t1 = time.time()
+    plan.autotune(ws_b)
+    tune = plan.tuning()
+    plan.filter(packed, out_b, ws_b)          # records the graph
+    torch.cuda.synchronize()
+    print(f"[bench] batch autotune {tune}, setup {time.time() - t1:.1f}s", file=sys.stderr, flush=True)
+    ms_b = time_stream(torch, lambda: plan.filter(packed, out_b, ws_b), reps)
+    # per-image plain launches over the same images
+    offs = np.concatenate([[0], np.cumsum([h * w for h, w in shapes])])
+    views_in = [packed[offs[i]:offs[i + 1]].view(shapes[i]) for i in range(len(shapes))]
+    out_p = torch.empty_like(packed)
+    views_out = [out_p[offs[i]:offs[i + 1]].view(shapes[i]) for i in range(len(shapes))]
+    big = max(mf4d.mf4d_workspace_bytes(h, w, p) for (h, w), p in zip(shapes, params))
+    ws_p = torch.empty(big, dtype=torch.uint8, device=dev)
+
+    def plain():
+        for vi, vo, p in zip(views_in, views_out, params):
+            mf4d.mf4d_filter(vi, vo, p, ws_p)
+
+    plain()
+    ms_p = time_stream(torch, plain, reps)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(out_b, out_p))
+    px_sub = sum(h * w * sp["cycles"] * 10 for (h, w), sp in zip(shapes, specs))
+    plan.close()
+    return {"images": len(imgs), "megapixels": float(offs[-1]) / 1e6,
+            "batched_ms": ms_b, "plain_ms": ms_p,
+            "batched_images_per_s": len(imgs) / (ms_b * 1e-3), "plain_images_per_s": len(imgs) / (ms_p * 1e-3),
+            "batched_Mpx_substeps_per_s": px_sub / (ms_b * 1e-3) / 1e6,
+            "plain_Mpx_substeps_per_s": px_sub / (ms_p * 1e-3) / 1e6,
+            "speedup": ms_p / ms_b, "bit_identical_to_plain": same,
+            "substeps_per_launch": tune[0], "rows_per_wave": tune[1]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +139,7 @@ def main():
     ap.add_argument("--workload", default="creases4096")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stages", action="store_true")
+    ap.add_argument("--no-extensions", action="store_true", help="skip the batched comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -168,6 +226,11 @@ def main():
         stages = {"per_cycle_scale_select_ms": sel_ms, "per_cycle_tensor_incl_sweep_ms": ten_ms,
                   "per_cycle_substeps_ms": ms_cycle / 2, "cycles": w.cycles}
 
+    extensions = None
+    if not args.no_extensions:
+        extensions = {"batched_256": batched_comparison(torch, mf4d, synth, dev)}
+        print(f"[bench] batched: {json.dumps(extensions['batched_256'])}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -203,6 +266,7 @@ def main():
         "roofline_single_substep": roofline_single,
         "cpu_baseline": cpu,
         "stages": stages,
+        "extensions": extensions,
     }
     print(json.dumps(out), flush=True)
 

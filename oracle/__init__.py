@@ -25,6 +25,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mf4d_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "net_oracle.c")]
 _LIB = os.path.join(_HERE, "libmf4d_oracle.so")
 
 RIDGE, VALLEY, BOTH = 0, 1, 2
@@ -32,10 +33,10 @@ RIDGE, VALLEY, BOTH = 0, 1, 2
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no GPU involved)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in _SRCS):
         tmp = _LIB + ".tmp"
         cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fopenmp",
-               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+               "-fPIC", "-shared", "-o", tmp, *_SRCS, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB)
     return _LIB
@@ -47,7 +48,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in _SRCS):
             build(force=True)
         _lib = ctypes.CDLL(_LIB)
         _declare(_lib)
@@ -92,6 +93,12 @@ def _declare(L):
                              ctypes.c_double, ctypes.c_double, ctypes.c_int,
                              _u8p, _dp, _dp, _dp]
     L.ref_filter.restype = ctypes.c_int
+    L.net_param_count.restype = ctypes.c_int
+    L.net_forward.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp]
+    L.net_loss.argtypes = [_dp, _u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp]
+    L.net_loss.restype = ctypes.c_double
+    L.net_grad.argtypes = [_dp, _dp, _u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp]
+    L.net_grad.restype = ctypes.c_double
 
 
 def _d(a):
@@ -253,3 +260,57 @@ def filter(u, sigmas, mode, lam=0.005, rho=0.5, beta=0.5, c=-1.0, cycles=1, subs
     if record:
         return out, dict(idx=idx_rec, c=c_rec[:cycles], hrho=hrho_rec, u=u_rec, n=n)
     return out
+
+
+# ------------------------------------------------------------- learned net
+NET_CHANNELS = (1, 32, 32, 32, 32, 9)
+
+
+def net_param_count():
+    return lib().net_param_count()
+
+
+def net_unpack(theta):
+    """theta -> list of (W [cout][cin][3][3], b [cout]) per layer."""
+    out, pos = [], 0
+    for l in range(5):
+        ci, co = NET_CHANNELS[l], NET_CHANNELS[l + 1]
+        w = theta[pos:pos + co * ci * 9].reshape(co, ci, 3, 3)
+        pos += co * ci * 9
+        b = theta[pos:pos + co]
+        pos += co
+        out.append((w, b))
+    return out
+
+
+def net_pack(layers):
+    return np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in layers]).astype(np.float64)
+
+
+def net_forward(theta, u):
+    """u: [B][H][W]; returns z [B][9][H][W]."""
+    theta = _f64(theta)
+    u = _f64(u)
+    B, H, W = u.shape
+    z = np.zeros((B, 9, H, W))
+    lib().net_forward(_d(theta), _d(u), B, H, W, _null(_dp), _d(z))
+    return z
+
+
+def net_loss(z, label, w_conf=0.1):
+    z = _f64(z)
+    B, _, H, W = z.shape
+    lab = np.ascontiguousarray(label, dtype=np.uint8)
+    dz = np.zeros_like(z)
+    loss = lib().net_loss(_d(z), lab.ctypes.data_as(_u8p), B, H, W, float(w_conf), _d(dz))
+    return loss, dz
+
+
+def net_grad(theta, u, label, w_conf=0.1):
+    theta = _f64(theta)
+    u = _f64(u)
+    B, H, W = u.shape
+    lab = np.ascontiguousarray(label, dtype=np.uint8)
+    g = np.zeros_like(theta)
+    loss = lib().net_grad(_d(theta), _d(u), lab.ctypes.data_as(_u8p), B, H, W, float(w_conf), _d(g))
+    return loss, g
