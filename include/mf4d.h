@@ -238,6 +238,62 @@ int mf4d_batch_set_tuning(mf4d_batch *plan, int substeps_per_launch, int rows_pe
 /* Releases a plan and its recorded graph. Errors: MF4D_EINVAL (NULL). */
 int mf4d_batch_destroy(mf4d_batch *plan);
 
+/* ------------------------------------------------------ learned surrogate */
+
+/* A small convolutional network standing in for the scale selection: five
+ * 3x3 convolutions with zero padding, channels 1 -> 32 -> 32 -> 32 -> 32 -> 9,
+ * ReLU between layers; outputs 8 scale logits and 1 confidence logit per
+ * pixel. Products use BF16 weights and activations with FP32 accumulation on
+ * the matrix cores. theta is the FP32 parameter vector (device memory): for
+ * each layer W[cout][cin][3][3] then b[cout]. Images are [B][H][W] float32
+ * with H and W multiples of 16. Not part of the paper: a project extension. */
+
+/* Number of floats in theta. */
+size_t mf4d_net_param_count(void);
+
+/* Workspace bytes for B images of H x W (train != 0: also for the backward
+ * pass); 0 if the shape is invalid. */
+size_t mf4d_net_workspace_bytes(int B, int H, int W, int train);
+
+/* Forward pass. logits (nullable): [B*H*W][16] float32 (entries 0..7 scale
+ * logits, 8 confidence logit, 9..15 zero); idx_out (nullable): argmax of the
+ * scale logits, uint8 [B][H][W]; conf_out (nullable): sigmoid of the
+ * confidence logit, float32 [B][H][W]. Errors: MF4D_EINVAL, MF4D_ENOMEM,
+ * MF4D_EHIP. */
+int mf4d_net_forward(const float *theta, const float *u, int B, int H, int W, float *logits,
+                     uint8_t *idx_out, float *conf_out, void *ws, size_t ws_bytes, void *stream);
+
+/* Gradient of the training loss with respect to theta (written to grad,
+ * device float32, param_count entries). Loss, averaged over pixels: softmax
+ * cross-entropy of the scale logits against labels (uint8 [B][H][W], the
+ * exact sweep's indices), plus w_conf times the binary cross-entropy of the
+ * confidence against "the predicted scale is the label". stats_out
+ * (nullable, device float32[2]): the loss and the fraction of correct
+ * predictions. Errors: MF4D_EINVAL, MF4D_ENOMEM, MF4D_EHIP. */
+int mf4d_net_backward(const float *theta, const float *u, const uint8_t *labels, int B, int H, int W,
+                      float w_conf, float *grad, float *stats_out, void *ws, size_t ws_bytes, void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on theta with moment
+ * buffers adam_m, adam_v (device float32, zero-initialised before step 1);
+ * step counts from 1. Errors: MF4D_EINVAL, MF4D_EHIP. */
+int mf4d_net_step(float *theta, const float *grad, float *adam_m, float *adam_v, int step, float lr,
+                  void *stream);
+
+/* Workspace bytes for mf4d_filter_learned (0 if invalid). */
+size_t mf4d_learned_workspace_bytes(int H, int W, const mf4d_params *p);
+
+/* The filter with the network's scale where its confidence reaches
+ * conf_threshold (0..1) and the exact argmax of Eq. (9) elsewhere; the exact
+ * sweep still runs every cycle, since the normalised Hessian at the chosen
+ * scale and the image-wide c need it. conf_threshold = 1 with an unsure
+ * network reproduces mf4d_filter. H, W multiples of 16, nscales <= 8,
+ * reselect_each_cycle = 1. fallback_count (nullable, device uint32): number
+ * of pixel-cycles that fell back to the exact argmax. Errors: MF4D_EINVAL,
+ * MF4D_ENOMEM, MF4D_EHIP. */
+int mf4d_filter_learned(const float *u_in, float *u_out, int H, int W, const mf4d_params *p,
+                        const float *theta, float conf_threshold, unsigned *fallback_count, void *ws,
+                        size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

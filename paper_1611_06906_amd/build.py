@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmf4d.so")
-SOURCES = ["mf4d_api.hip", "scale_kernels.hip", "fed_kernels.hip", "batch.hip"]
+SOURCES = ["mf4d_api.hip", "scale_kernels.hip", "fed_kernels.hip", "batch.hip", "learned.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

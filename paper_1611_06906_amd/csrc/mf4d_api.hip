@@ -522,4 +522,71 @@ int mf4d_filter(const float *u_in, float *u_out, int H, int W, const mf4d_params
     return MF4D_OK;
 }
 
+size_t mf4d_learned_workspace_bytes(int H, int W, const mf4d_params *p)
+{
+    if (validate(H, W, p) != MF4D_OK || p->nscales > 8 || H % 16 != 0 || W % 16 != 0) return 0;
+    return align256(layout(H, W, p->nscales, nullptr, nullptr)) + align256(net_forward_bytes(H, W)) + 256;
+}
+
+int mf4d_filter_learned(const float *u_in, float *u_out, int H, int W, const mf4d_params *p, const float *theta,
+                        float conf_threshold, unsigned *fallback_count, void *ws, size_t ws_bytes, void *stream)
+{
+    int st = validate(H, W, p);
+    if (st != MF4D_OK) return st;
+    if (!u_in || !u_out || !theta || !ws || p->nscales > 8 || H % 16 != 0 || W % 16 != 0) return MF4D_EINVAL;
+    if (!(conf_threshold >= 0.f) || conf_threshold > 1.f || p->reselect_each_cycle != 1) return MF4D_EINVAL;
+    const size_t need = mf4d_learned_workspace_bytes(H, W, p);
+    if (ws_bytes < need) return MF4D_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t m = (size_t)H * W;
+    char *base = (char *)ws;
+    const size_t img_bytes = align256(layout(H, W, p->nscales, nullptr, nullptr));
+    char *net_ws = base + img_bytes;
+    unsigned *fb = (unsigned *)(net_ws + align256(net_forward_bytes(H, W)));
+    CHECK_HIP(launch_fill_u32(fb, 0u, 1, s));
+    if (p->cycles == 0) {
+        if (u_in != u_out) CHECK_HIP(launch_copy_f32(u_in, u_out, m, s));
+        if (fallback_count) CHECK_HIP(hipMemcpyAsync(fallback_count, fb, 4, hipMemcpyDeviceToDevice, s));
+        return MF4D_OK;
+    }
+    std::vector<double> ordered;
+    int n = 0;
+    st = plan(p, &n, ordered);
+    if (st != MF4D_OK) return st;
+    std::vector<float> tau32(n);
+    for (int i = 0; i < n; ++i) tau32[i] = (float)ordered[i];
+    const int spl = kSubstepsPerLaunch;
+    const int launches_per_cycle = (n + spl - 1) / spl;
+    Workspace w;
+    layout(H, W, p->nscales, &w, base);
+    const long long total = (long long)p->cycles * launches_per_cycle;
+    float *bufs[2];
+    bufs[0] = (total % 2 == 1) ? u_out : w.utmp;
+    bufs[1] = (total % 2 == 1) ? w.utmp : u_out;
+    const float *src = u_in;
+    if ((const float *)bufs[0] == u_in) {
+        CHECK_HIP(launch_copy_f32(u_in, w.utmp, m, s));
+        src = w.utmp;
+        bufs[0] = u_out;
+        bufs[1] = w.utmp;
+    }
+    SelectArgs a = select_args(p, w);
+    a.coef = w.tens;
+    a.idx_out = w.idx;
+    int li = 0;
+    for (int k = 0; k < p->cycles; ++k) {
+        const float *z = nullptr;
+        st = net_forward_into(theta, src, H, W, net_ws, s, &z);
+        if (st != MF4D_OK) return st;
+        st = run_sweep(src, H, W, p, w, true, s);
+        if (st != MF4D_OK) return st;
+        CHECK_HIP(launch_learned_select(z, conf_threshold, a, H, W, fb, s));
+        CHECK_HIP(launch_rho(a, H, W, s));
+        st = run_substeps(src, bufs, li, w.tens, H, W, tau32.data(), n, spl, s, &src);
+        if (st != MF4D_OK) return st;
+    }
+    if (fallback_count) CHECK_HIP(hipMemcpyAsync(fallback_count, fb, 4, hipMemcpyDeviceToDevice, s));
+    return MF4D_OK;
+}
+
 }  // extern "C"

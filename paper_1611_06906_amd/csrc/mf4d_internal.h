@@ -93,4 +93,16 @@ hipError_t launch_fed_coef(const float *u_in, float *u_out, const float *coef, i
 hipError_t launch_fed_stream(const float *u_in, float *u_out, const float *coef, int H, int W, int steps,
                              const float *taus, int seg_rows, hipStream_t s);
 
+// Integration with G_rho and tensor planes only (nsel already gathered).
+hipError_t launch_rho(const SelectArgs &a, int H, int W, hipStream_t s);
+
+// Learned surrogate (learned.hip): network forward on one H x W image into
+// `ws` (net_forward_bytes(H, W) bytes), logits [H*W][16] returned in *z; and
+// the learned selection (network scale where confident, exact argmax
+// elsewhere; counts the fallback pixels into *fallback).
+int net_forward_into(const float *theta, const float *u, int H, int W, char *ws, hipStream_t s, const float **z);
+size_t net_forward_bytes(int H, int W);
+hipError_t launch_learned_select(const float *z, float thr, const SelectArgs &a, int H, int W, unsigned *fallback,
+                                 hipStream_t s);
+
 }  // namespace mf4d

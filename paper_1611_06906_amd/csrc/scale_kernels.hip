@@ -126,6 +126,24 @@ hipError_t launch_copy_f32(const float *src, float *dst, size_t n, hipStream_t s
     return hipGetLastError();
 }
 
+hipError_t launch_rho(const SelectArgs &a, int H, int W, hipStream_t s)
+{
+    const int tiles_x = (W + kBTW - 1) / kBTW, tiles_y = (H + kBTH - 1) / kBTH;
+    dim3 grid(tiles_x * tiles_y), block(256);
+    switch (a.rho.r) {
+#define MF4D_RHO_ONLY(R)                                                                                       \
+    case R:                                                                                                    \
+        hipLaunchKernelGGL(rho_blur_kernel<R>, grid, block, 0, s, a.nsel, a.hrho, a.coef, a.mode, a.inv_lam2, H, \
+                           W, a.rho, tiles_x);                                                                 \
+        break;
+        MF4D_RHO_ONLY(0) MF4D_RHO_ONLY(1) MF4D_RHO_ONLY(2) MF4D_RHO_ONLY(3) MF4D_RHO_ONLY(4)
+        MF4D_RHO_ONLY(5) MF4D_RHO_ONLY(6) MF4D_RHO_ONLY(7) MF4D_RHO_ONLY(8)
+#undef MF4D_RHO_ONLY
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_select(const SelectArgs &a, int H, int W, hipStream_t s)
 {
     const size_t plane = (size_t)H * W;

@@ -26,7 +26,9 @@ EXPORTS = ["mf4d_status_string", "mf4d_params_default", "mf4d_fed_schedule",
            "mf4d_fed_substeps", "mf4d_fed_plan", "mf4d_workspace_bytes",
            "mf4d_scale_select", "mf4d_tensor", "mf4d_fed_cycle", "mf4d_fed_cycle_tensor",
            "mf4d_filter", "mf4d_batch_create", "mf4d_batch_workspace_bytes", "mf4d_filter_batch",
-           "mf4d_batch_autotune", "mf4d_batch_get_tuning", "mf4d_batch_set_tuning", "mf4d_batch_destroy"]
+           "mf4d_batch_autotune", "mf4d_batch_get_tuning", "mf4d_batch_set_tuning", "mf4d_batch_destroy",
+           "mf4d_net_param_count", "mf4d_net_workspace_bytes", "mf4d_net_forward", "mf4d_net_backward",
+           "mf4d_net_step", "mf4d_learned_workspace_bytes", "mf4d_filter_learned"]
 
 
 class MF4DError(RuntimeError):
@@ -139,6 +141,20 @@ def lib():
         L.mf4d_batch_set_tuning.restype = i
         L.mf4d_batch_destroy.argtypes = [vp]
         L.mf4d_batch_destroy.restype = i
+        L.mf4d_net_param_count.argtypes = []
+        L.mf4d_net_param_count.restype = sz
+        L.mf4d_net_workspace_bytes.argtypes = [i, i, i, i]
+        L.mf4d_net_workspace_bytes.restype = sz
+        L.mf4d_net_forward.argtypes = [vp, vp, i, i, i, vp, vp, vp, vp, sz, vp]
+        L.mf4d_net_forward.restype = i
+        L.mf4d_net_backward.argtypes = [vp, vp, vp, i, i, i, ctypes.c_float, vp, vp, vp, sz, vp]
+        L.mf4d_net_backward.restype = i
+        L.mf4d_net_step.argtypes = [vp, vp, vp, vp, i, ctypes.c_float, vp]
+        L.mf4d_net_step.restype = i
+        L.mf4d_learned_workspace_bytes.argtypes = [i, i, P(mf4d_params)]
+        L.mf4d_learned_workspace_bytes.restype = sz
+        L.mf4d_filter_learned.argtypes = [vp, vp, i, i, P(mf4d_params), vp, ctypes.c_float, vp, vp, sz, vp]
+        L.mf4d_filter_learned.restype = i
         _lib = L
     return _lib
 
@@ -344,3 +360,92 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------ learned net
+def mf4d_net_param_count() -> int:
+    return int(lib().mf4d_net_param_count())
+
+
+def net_workspace(B, H, W, train, device="cuda"):
+    nb = int(lib().mf4d_net_workspace_bytes(int(B), int(H), int(W), int(bool(train))))
+    if nb == 0:
+        raise MF4DError(MF4D_EINVAL, "mf4d_net_workspace_bytes")
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def _bhw(u):
+    if u.dim() == 2:
+        return 1, int(u.shape[0]), int(u.shape[1])
+    if u.dim() == 3:
+        return int(u.shape[0]), int(u.shape[1]), int(u.shape[2])
+    raise ValueError("images must be [H, W] or [B, H, W]")
+
+
+def mf4d_net_forward(theta, u, logits=None, idx_out=None, conf_out=None, ws=None, stream=None):
+    _dev(theta, torch.float32, (mf4d_net_param_count(),), "theta")
+    B, H, W = _bhw(_dev(u, torch.float32, name="u"))
+    _dev(logits, torch.float32, (B * H * W, 16), "logits")
+    _dev(idx_out, torch.uint8, tuple(u.shape), "idx_out")
+    _dev(conf_out, torch.float32, tuple(u.shape), "conf_out")
+    if ws is None:
+        ws = net_workspace(B, H, W, False, u.device)
+    _check(lib().mf4d_net_forward(_ptr(theta), _ptr(u), B, H, W, _ptr(logits), _ptr(idx_out), _ptr(conf_out),
+                                  _ptr(ws), ws.numel(), _stream(stream)), "mf4d_net_forward")
+
+
+def mf4d_net_backward(theta, u, labels, grad, w_conf=0.1, stats_out=None, ws=None, stream=None):
+    _dev(theta, torch.float32, (mf4d_net_param_count(),), "theta")
+    B, H, W = _bhw(_dev(u, torch.float32, name="u"))
+    _dev(labels, torch.uint8, tuple(u.shape), "labels")
+    _dev(grad, torch.float32, (mf4d_net_param_count(),), "grad")
+    _dev(stats_out, torch.float32, (2,), "stats_out")
+    if ws is None:
+        ws = net_workspace(B, H, W, True, u.device)
+    _check(lib().mf4d_net_backward(_ptr(theta), _ptr(u), _ptr(labels), B, H, W, float(w_conf), _ptr(grad),
+                                   _ptr(stats_out), _ptr(ws), ws.numel(), _stream(stream)), "mf4d_net_backward")
+
+
+def mf4d_net_step(theta, grad, adam_m, adam_v, step, lr, stream=None):
+    n = mf4d_net_param_count()
+    for t, nm in ((theta, "theta"), (grad, "grad"), (adam_m, "adam_m"), (adam_v, "adam_v")):
+        _dev(t, torch.float32, (n,), nm)
+    _check(lib().mf4d_net_step(_ptr(theta), _ptr(grad), _ptr(adam_m), _ptr(adam_v), int(step), float(lr),
+                               _stream(stream)), "mf4d_net_step")
+
+
+def mf4d_filter_learned(u_in, u_out, params: Params, theta, conf_threshold=0.9, fallback_count=None, ws=None,
+                        stream=None):
+    H, W = _hw(_dev(u_in, torch.float32, name="u_in"))
+    _dev(u_out, torch.float32, (H, W), "u_out")
+    _dev(theta, torch.float32, (mf4d_net_param_count(),), "theta")
+    _dev(fallback_count, torch.int32, (1,), "fallback_count")
+    st = params.struct()
+    if ws is None:
+        nb = int(lib().mf4d_learned_workspace_bytes(H, W, ctypes.byref(st)))
+        if nb == 0:
+            raise MF4DError(MF4D_EINVAL, "mf4d_learned_workspace_bytes")
+        ws = torch.empty(nb, dtype=torch.uint8, device=u_in.device)
+    _check(lib().mf4d_filter_learned(_ptr(u_in), _ptr(u_out), H, W, ctypes.byref(st), _ptr(theta),
+                                     float(conf_threshold), _ptr(fallback_count), _ptr(ws), ws.numel(),
+                                     _stream(stream)), "mf4d_filter_learned")
+
+
+def learned_workspace(H, W, params: Params, device="cuda"):
+    st = params.struct()
+    nb = int(lib().mf4d_learned_workspace_bytes(int(H), int(W), ctypes.byref(st)))
+    if nb == 0:
+        raise MF4DError(MF4D_EINVAL, "mf4d_learned_workspace_bytes")
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def net_init(seed=0, device="cuda"):
+    """He-normal initial parameters (host RNG), as a device tensor."""
+    rng = np.random.default_rng(seed)
+    ch = (1, 32, 32, 32, 32, 9)
+    parts = []
+    for l in range(5):
+        fan_in = ch[l] * 9
+        parts.append(rng.normal(0.0, np.sqrt(2.0 / fan_in), size=ch[l + 1] * ch[l] * 9))
+        parts.append(np.zeros(ch[l + 1]))
+    return torch.from_numpy(np.concatenate(parts).astype(np.float32)).to(device)
