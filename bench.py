@@ -131,6 +131,115 @@ def batched_comparison(torch, mf4d, synth, dev, reps=2):
             "substeps_per_launch": tune[0], "rows_per_wave": tune[1]}
 
 
+def _fundus(args):
+    from paper_1611_06906_amd import synth
+    H, seed, invert_ridges = args
+    if invert_ridges:
+        u = synth.creases(H, H, max(1, round(3 * H / 128)), seed)
+        return (1.0 - u.astype("float64")).astype("float32")
+    return synth.fundus(H, H, seed)
+
+
+def learned_comparison(torch, mf4d, synth, dev, train_steps=600, reps=1):
+    """Learned scale surrogate vs the plain filter on four 2048 x 2048
+    fundus-like images (8 scales 8^(k/7), valley mode, 20 FED cycles x 15):
+    the network is first trained here, on the GPU, on random 256 x 256 crops
+    of 16 images labelled by the exact sweep."""
+    import numpy as np
+    from concurrent.futures import ProcessPoolExecutor
+    sig = [8.0 ** (k / 7.0) for k in range(8)]
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    t0 = time.time()
+    jobs = [(1024, 10000 + i, i % 2 == 1) for i in range(16)] + [(2048, 50000 + i, False) for i in range(4)]
+    with ProcessPoolExecutor(workers) as ex:
+        imgs = list(ex.map(_fundus, jobs))
+    train_imgs, test_imgs = imgs[:16], imgs[16:]
+    print(f"[bench] learned: images generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    psel = mf4d.Params(sig, mode=mf4d.MF4D_VALLEY)
+    U = torch.stack([torch.from_numpy(u).to(dev) for u in train_imgs])
+    L = torch.empty(U.shape, dtype=torch.uint8, device=dev)
+    for i in range(len(train_imgs)):
+        mf4d.mf4d_scale_select(U[i], psel, L[i])
+    th = mf4d.net_init(0, dev)
+    g = torch.zeros_like(th)
+    mm, vv = torch.zeros_like(th), torch.zeros_like(th)
+    stats = torch.zeros(2, dtype=torch.float32, device=dev)
+    B, C = 8, 256
+    ws = mf4d.net_workspace(B, C, C, True, dev)
+    rng = np.random.default_rng(0)
+    xb = torch.empty((B, C, C), dtype=torch.float32, device=dev)
+    yb = torch.empty((B, C, C), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    t1 = time.time()
+    for step in range(1, train_steps + 1):
+        for b in range(B):
+            i, y0, x0 = rng.integers(0, len(train_imgs)), rng.integers(0, 1024 - C + 1), rng.integers(0, 1024 - C + 1)
+            xb[b].copy_(U[i, y0:y0 + C, x0:x0 + C])
+            yb[b].copy_(L[i, y0:y0 + C, x0:x0 + C])
+        lr = 3e-3 if step < train_steps * 0.7 else 1e-3
+        mf4d.mf4d_net_backward(th, xb, yb, g, 0.1, stats, ws)
+        mf4d.mf4d_net_step(th, g, mm, vv, step, lr)
+    torch.cuda.synchronize()
+    train_s = time.time() - t1
+    train_loss, train_acc = (float(v) for v in stats.cpu())
+    print(f"[bench] learned: {train_steps} steps in {train_s:.1f}s, loss {train_loss:.3f}, "
+          f"crop accuracy {train_acc:.3f}", file=sys.stderr, flush=True)
+
+    p = mf4d.Params(sig, mode=mf4d.MF4D_VALLEY, cycles=20, substeps=15)
+    H = W = 2048
+    ins = [torch.from_numpy(u).to(dev) for u in test_imgs]
+    outs_p = [torch.empty_like(x) for x in ins]
+    outs_l = [torch.empty_like(x) for x in ins]
+    ws_p = mf4d.workspace(H, W, p, dev)
+    ws_l = mf4d.learned_workspace(H, W, p, dev)
+    fb = torch.zeros(1, dtype=torch.int32, device=dev)
+    fb_total = 0
+
+    def plain():
+        for x, y in zip(ins, outs_p):
+            mf4d.mf4d_filter(x, y, p, ws_p)
+
+    def learned():
+        nonlocal fb_total
+        for x, y in zip(ins, outs_l):
+            mf4d.mf4d_filter_learned(x, y, p, th, 0.9, fb, ws_l)
+
+    plain()
+    learned()
+    ms_p = time_stream(torch, plain, reps)
+    ms_l = time_stream(torch, learned, reps)
+    # agreement with the exact sweep on the input images, and fallback share
+    agree, agree_conf, conf_frac, fb_frac = [], [], [], 0
+    nws = mf4d.net_workspace(1, H, W, False, dev)
+    for x, y in zip(ins, outs_l):
+        exact = torch.empty((H, W), dtype=torch.uint8, device=dev)
+        mf4d.mf4d_scale_select(x, p, exact, None, None, ws_p)
+        pred = torch.empty_like(exact)
+        conf = torch.empty((H, W), dtype=torch.float32, device=dev)
+        mf4d.mf4d_net_forward(th, x, None, pred, conf, nws)
+        ok = conf >= 0.9
+        agree.append(float((pred == exact).float().mean()))
+        agree_conf.append(float((pred[ok] == exact[ok]).float().mean()) if bool(ok.any()) else 1.0)
+        conf_frac.append(float(ok.float().mean()))
+        mf4d.mf4d_filter_learned(x, y, p, th, 0.9, fb, ws_l)
+        torch.cuda.synchronize()
+        fb_frac += int(fb.item()) / (20 * H * W) / len(ins)
+    d = torch.cat([(a.double() - b.double()).ravel() for a, b in zip(outs_l, outs_p)])
+    ref = torch.cat([b.double().ravel() for b in outs_p])
+    return {"images": len(ins), "size": [H, W], "cycles": 20, "substeps": 15, "scales": len(sig),
+            "train_steps": train_steps, "train_seconds": train_s, "train_loss": train_loss,
+            "train_crop_accuracy": train_acc,
+            "plain_ms": ms_p, "learned_ms": ms_l,
+            "plain_images_per_s": len(ins) / (ms_p * 1e-3), "learned_images_per_s": len(ins) / (ms_l * 1e-3),
+            "speedup": ms_p / ms_l,
+            "scale_agreement_cycle0": float(np.mean(agree)),
+            "scale_agreement_confident_cycle0": float(np.mean(agree_conf)),
+            "confident_fraction_cycle0": float(np.mean(conf_frac)),
+            "fallback_fraction_all_cycles": fb_frac,
+            "final_max_abs_vs_plain": float(d.abs().max()),
+            "final_rel_l2_vs_plain": float(d.norm() / ref.norm())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,6 +339,8 @@ def main():
     if not args.no_extensions:
         extensions = {"batched_256": batched_comparison(torch, mf4d, synth, dev)}
         print(f"[bench] batched: {json.dumps(extensions['batched_256'])}", file=sys.stderr, flush=True)
+        extensions["learned_2048"] = learned_comparison(torch, mf4d, synth, dev)
+        print(f"[bench] learned: {json.dumps(extensions['learned_2048'])}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
