@@ -1,0 +1,37 @@
+#!/bin/bash
+# Mutation check of the FP64 oracle (CPU only, not collected by pytest).
+# Plants one mistake at a time in a scratch copy of oracle/mf4d_oracle.c and
+# runs the oracle's pin tests on it; each mistake should make a pin fail.
+# Usage: bash tests/oracle_mutations.sh   (from the repository root)
+set -u
+root=$(cd "$(dirname "$0")/.." && pwd)
+muts=(
+ 's|R(y - 1, x - 1) += tp\[k\] / 4.0;|R(y - 1, x - 1) -= tp[k] / 4.0;|'
+ 's|const double rs2 = 1.0 / sqrt(2.0);|const double rs2 = 1.0;|'
+ 's|double f = 1.0 / sqrt(1.0 + sqrt(ux\[p\] \* ux\[p\] + uy\[p\] \* uy\[p\]));|double f = 1.0 / sqrt(1.0 + (ux[p] * ux[p] + uy[p] * uy[p]));|'
+ 's|mu\[2\] = 0.5 \* (mu\[0\] + mu\[1\]);|mu[2] = mu[0];|'
+ 's|double s2 = sigma \* sigma;|double s2 = sigma;|'
+ 's|if (mode == REF_RIDGE \&\& nt2 > 0.0) return 0.0;|if (mode == REF_RIDGE \&\& nt2 < 0.0) return 0.0;|'
+ 's|E\[c\]\[3\] = rs2 \* (e1\[k\] \* e2\[l\] - e2\[k\] \* e1\[l\]);|E[c][3] = rs2 * (e1[k] * e2[l] + e2[k] * e1[l]);|'
+ 's|mu\[3\] = 0.0;|mu[3] = 1.0;|'
+ 's|double c = c_param > 0.0 ? c_param : 0.5 \* smax;|double c = c_param > 0.0 ? c_param : smax;|'
+ 's|if (V\[s \* m + p\] > bv)|if (V[s * m + p] >= bv)|'
+ 's|tau\[i\] = 3.0 \* T / (2.0 \* (double)M \* ((double)n \* n + n) \* c \* c);|tau[i] = 3.0 * T / (2.0 * (double)M * ((double)n * n + n) * c);|'
+ 's|int p = 2 \* n;|int p = 2 * n + 1;|'
+ 's|for (int y = 1 + phase; y < H - 1; y += 3)|for (int y = 1 + phase; y < H; y += 3)|'
+ 's|if (uxy) uxy\[c\] = (V(ym, xm) + V(yp, xp) - V(yp, xm) - V(ym, xp)) / 4.0;|if (uxy) uxy[c] = (V(ym, xm) + V(yp, xp) - V(yp, xm) - V(ym, xp)) / 2.0;|'
+ 's|double theta = 0.5 \* atan2(2.0 \* b, a - d);|double theta = 0.5 * atan2(b, a - d);|'
+ 's|if (nu1 >= 0.0) mu\[0\] = 1.0;|if (nu1 > 0.1) mu[0] = 1.0;|'
+)
+pins="tests/test_oracle_schedule.py tests/test_oracle_scalespace.py tests/test_oracle_tensor_operator.py tests/test_oracle_filter.py"
+i=0
+for m in "${muts[@]}"; do
+  i=$((i+1)); d=$(mktemp -d)
+  cp -r "$root/oracle" "$root/tests" "$root/paper_1611_06906_amd" "$d/"
+  rm -f "$d"/oracle/*.so
+  sed -i "$m" "$d/oracle/mf4d_oracle.c"
+  if cmp -s "$d/oracle/mf4d_oracle.c" "$root/oracle/mf4d_oracle.c"; then echo "MUT $i: pattern did not apply"; continue; fi
+  (cd "$d" && timeout 300 python -m pytest $pins -x -q -p no:cacheprovider > log 2>&1); rc=$?
+  if [ $rc -eq 0 ]; then echo "MUT $i: not caught"; else echo "MUT $i: caught by $(grep -m1 -o 'FAILED [^ ]*' "$d/log")"; fi
+  rm -rf "$d"
+done
