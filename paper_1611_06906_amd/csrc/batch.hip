@@ -20,7 +20,7 @@
 #include <vector>
 
 #include "fed_tiles.h"
-#include "scale_tiles.h"
+#include "scale_mfma.h"
 
 namespace mf4d {
 
@@ -38,7 +38,11 @@ struct BImg {
     int strips[5], segs[5], seg_rows[5];   // streaming decomposition per substeps-per-launch
 };
 
-enum { PT_HV = 0, PT_PX, PT_RHO, PT_ST1, PT_ST2, PT_ST3, PT_ST4, PT_COUNT };
+enum { PT_HV = 0, PT_PX, PT_RHO, PT_ST1, PT_ST2, PT_ST3, PT_ST4, PT_HM, PT_VM, PT_COUNT };
+
+// rows per workgroup of the batched matrix-core vertical pass (any multiple
+// of its step gives the same values)
+constexpr int kBatchVSegRows = 256;
 
 namespace {
 
@@ -111,6 +115,42 @@ __global__ __launch_bounds__(256) void batch_vpass_kernel(const BImg *imgs, cons
     if (im.mode == MF4D_RIDGE) v = vpass_tile<MF4D_RIDGE>(A, B, C, im.H, im.W, t, sigma2, inv2beta2, So, Ao, No, x0, y0);
     else if (im.mode == MF4D_VALLEY) v = vpass_tile<MF4D_VALLEY>(A, B, C, im.H, im.W, t, sigma2, inv2beta2, So, Ao, No, x0, y0);
     else v = vpass_tile<MF4D_BOTH>(A, B, C, im.H, im.W, t, sigma2, inv2beta2, So, Ao, No, x0, y0);
+    block_max_to(v, im.smax);
+}
+
+template <int NC>
+__global__ __launch_bounds__(256) void batch_hpass_mfma_kernel(const BImg *imgs, const int *pre, int nact, WinTaps t,
+                                                               int jsrc, int per_xcd)
+{
+    extern __shared__ f4 lds4[];
+    const int b = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (b >= pre[nact]) return;
+    const int i = image_of(pre, nact, b);
+    const BImg &im = imgs[i];
+    const int lt = b - pre[i];
+    const int tx = (im.W + kHMW - 1) / kHMW;
+    const size_t m = (size_t)im.H * im.W;
+    hpass_mfma_tile<NC>(state_src(im, jsrc), im.hA, im.hA + m, im.hA + 2 * m, im.H, im.W, t, (lt % tx) * kHMW,
+                        (lt / tx) * kHMH, (float *)lds4);
+}
+
+template <int NC>
+__global__ __launch_bounds__(256) void batch_vpass_mfma_kernel(const BImg *imgs, const int *pre, int nact, WinTaps t,
+                                                               float sigma2, float inv2beta2, int s, int per_xcd)
+{
+    extern __shared__ f4 lds4[];
+    const int b = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (b >= pre[nact]) return;
+    const int i = image_of(pre, nact, b);
+    const BImg &im = imgs[i];
+    const int lt = b - pre[i];
+    const int segs = (im.H + kBatchVSegRows - 1) / kBatchVSegRows;
+    const int strip = lt / segs, seg = lt - strip * segs;
+    const int ys = seg * kBatchVSegRows, ye = min(im.H, ys + kBatchVSegRows);
+    const size_t m = (size_t)im.H * im.W;
+    const float v = vpass_mfma_tile<NC>(im.hA, im.hA + m, im.hA + 2 * m, im.H, im.W, t, sigma2, inv2beta2, im.mode,
+                                        im.S + s * m, im.A + s * m, im.N + 3 * s * m, strip * kVMW, ys, ye,
+                                        (float *)lds4);
     block_max_to(v, im.smax);
 }
 
@@ -259,6 +299,8 @@ void build_tables(mf4d_batch *b, const float *in, float *out, char *ws, std::vec
         pre[PT_HV][r + 1] = pre[PT_HV][r] + hv;
         pre[PT_PX][r + 1] = pre[PT_PX][r] + px;
         pre[PT_RHO][r + 1] = pre[PT_RHO][r] + rho;
+        pre[PT_HM][r + 1] = pre[PT_HM][r] + ((W + kHMW - 1) / kHMW) * ((H + kHMH - 1) / kHMH);
+        pre[PT_VM][r + 1] = pre[PT_VM][r] + ((W + kVMW - 1) / kVMW) * ((H + kBatchVSegRows - 1) / kBatchVSegRows);
         for (int s = 1; s <= 4; ++s)
             pre[PT_ST1 + s - 1][r + 1] = pre[PT_ST1 + s - 1][r] + (im.strips[s] * im.segs[s] + 3) / 4;
     }
@@ -298,13 +340,41 @@ int enqueue_batch(mf4d_batch *b, char *ws, const std::vector<int> pre[PT_COUNT],
         hipLaunchKernelGGL(batch_fill_kernel, dim3((nact + 255) / 256), dim3(256), 0, s, imgs, nact);
         BCHECK(hipGetLastError());
         for (int sc = 0; sc < ns; ++sc) {
-            const size_t lds = (size_t)64 * (taps[sc].ntaps + 65) * sizeof(float);
-            hipLaunchKernelGGL(batch_hpass_kernel, dim3(pre[PT_HV][nact]), dim3(256), lds, s, imgs, P(PT_HV), nact,
-                               taps[sc], j);
-            BCHECK(hipGetLastError());
             const float sig = p.sigmas[sc];
-            hipLaunchKernelGGL(batch_vpass_kernel, dim3(pre[PT_HV][nact]), dim3(256), 0, s, imgs, P(PT_HV), nact,
-                               taps[sc], sig * sig, inv2beta2, sc);
+            if (const int nc = sweep_chunks(taps[sc])) {
+                const int per_h = (pre[PT_HM][nact] + 7) / 8;
+                switch (nc) {
+#define MF4D_BHM(NC)                                                                                              \
+    case NC:                                                                                                      \
+        hipLaunchKernelGGL(batch_hpass_mfma_kernel<NC>, dim3(8 * per_h), dim3(256), hpass_mfma_lds(NC), s, imgs,      \
+                           P(PT_HM), nact, taps[sc], j, per_h);                                                   \
+        break;
+                    MF4D_BHM(2) MF4D_BHM(3) MF4D_BHM(4) MF4D_BHM(5) MF4D_BHM(6) MF4D_BHM(7) MF4D_BHM(8) MF4D_BHM(9)
+#undef MF4D_BHM
+                default: return MF4D_EINVAL;
+                }
+            } else {
+                const size_t lds = (size_t)64 * (taps[sc].ntaps + 65) * sizeof(float);
+                hipLaunchKernelGGL(batch_hpass_kernel, dim3(pre[PT_HV][nact]), dim3(256), lds, s, imgs, P(PT_HV), nact,
+                                   taps[sc], j);
+            }
+            BCHECK(hipGetLastError());
+            if (const int nc = sweep_chunks(taps[sc])) {
+                const int per_v = (pre[PT_VM][nact] + 7) / 8;
+                switch (nc) {
+#define MF4D_BVM(NC)                                                                                              \
+    case NC:                                                                                                      \
+        hipLaunchKernelGGL(batch_vpass_mfma_kernel<NC>, dim3(8 * per_v), dim3(256), vpass_mfma_lds(NC), s, imgs,      \
+                           P(PT_VM), nact, taps[sc], sig * sig, inv2beta2, sc, per_v);                            \
+        break;
+                    MF4D_BVM(2) MF4D_BVM(3) MF4D_BVM(4) MF4D_BVM(5) MF4D_BVM(6) MF4D_BVM(7) MF4D_BVM(8) MF4D_BVM(9)
+#undef MF4D_BVM
+                default: return MF4D_EINVAL;
+                }
+            } else {
+                hipLaunchKernelGGL(batch_vpass_kernel, dim3(pre[PT_HV][nact]), dim3(256), 0, s, imgs, P(PT_HV), nact,
+                                   taps[sc], sig * sig, inv2beta2, sc);
+            }
             BCHECK(hipGetLastError());
         }
         const int keep = (k > 0 && !p.reselect_each_cycle) ? 1 : 0;

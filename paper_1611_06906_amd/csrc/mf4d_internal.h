@@ -51,6 +51,14 @@ hipError_t launch_vpass(const float *A, const float *B, const float *C, int H, i
                         const WinTaps &t, float sigma, int mode, float beta, ScalePlanes out,
                         unsigned *smax_bits, hipStream_t s);
 
+// Matrix-core chunk count (K / 16) used for a scale's passes, 0 for the
+// register-window passes (radius beyond the matrix-core tiles, or the
+// environment variable MF4D_SWEEP=valu).
+int sweep_chunks(const WinTaps &t);
+// Rows per workgroup of the single-image matrix-core vertical pass (the
+// environment variable MF4D_VSEG_ROWS overrides it; values do not change).
+int vpass_seg_rows(int H, int W);
+
 hipError_t launch_fill_u32(unsigned *p, unsigned v, size_t n, hipStream_t s);
 hipError_t launch_copy_f32(const float *src, float *dst, size_t n, hipStream_t s);
 

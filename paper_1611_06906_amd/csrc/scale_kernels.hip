@@ -1,6 +1,10 @@
 // Single-image kernels of the scale sweep and of the normalised, integrated
 // Hessian; the tile-level code lives in scale_tiles.h.
-#include "scale_tiles.h"
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+
+#include "scale_mfma.h"
 
 namespace mf4d {
 
@@ -25,6 +29,37 @@ __global__ __launch_bounds__(256) void vpass_kernel(const float *__restrict__ A,
 {
     const float v = vpass_tile<MODE>(A, B, C, H, W, t, sigma2, inv2beta2, So, Ao, No, blockIdx.x * 64,
                                      blockIdx.y * 64);
+    block_max_to(v, smax_bits);
+}
+
+// Matrix-core passes; blocks are remapped so that each XCD takes a
+// contiguous run of neighbouring tiles (their halos share its L2).
+template <int NC>
+__global__ __launch_bounds__(256) void hpass_mfma_kernel(const float *__restrict__ u, float *__restrict__ A,
+                                                         float *__restrict__ B, float *__restrict__ C, int H, int W,
+                                                         WinTaps t, int tiles_x, int ntiles, int per_xcd)
+{
+    extern __shared__ f4 lds4[];
+    const int b = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (b >= ntiles) return;
+    hpass_mfma_tile<NC>(u, A, B, C, H, W, t, (b % tiles_x) * kHMW, (b / tiles_x) * kHMH, (float *)lds4);
+}
+
+template <int NC>
+__global__ __launch_bounds__(256) void vpass_mfma_kernel(const float *__restrict__ A, const float *__restrict__ B,
+                                                         const float *__restrict__ C, int H, int W, WinTaps t,
+                                                         float sigma2, float inv2beta2, int mode,
+                                                         float *__restrict__ So, float *__restrict__ Ao,
+                                                         float *__restrict__ No, unsigned *__restrict__ smax_bits,
+                                                         int segs, int seg_rows, int nblk, int per_xcd)
+{
+    extern __shared__ f4 lds4[];
+    const int b = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (b >= nblk) return;
+    const int strip = b / segs, seg = b - strip * segs;
+    const int ys = seg * seg_rows, ye = min(H, ys + seg_rows);
+    const float v = vpass_mfma_tile<NC>(A, B, C, H, W, t, sigma2, inv2beta2, mode, So, Ao, No, strip * kVMW, ys, ye,
+                                        (float *)lds4);
     block_max_to(v, smax_bits);
 }
 
@@ -81,9 +116,45 @@ __global__ __launch_bounds__(256) void rho_blur_kernel(const float *__restrict__
 
 }  // namespace
 
+int sweep_chunks(const WinTaps &t)
+{
+    const int nc = mfma_chunks_for(t.R);
+    if (nc > kMfmaMaxChunks) return 0;
+    const char *e = std::getenv("MF4D_SWEEP");
+    if (e && std::strcmp(e, "valu") == 0) return 0;
+    return nc;
+}
+
+int vpass_seg_rows(int H, int W)
+{
+    if (const char *e = std::getenv("MF4D_VSEG_ROWS")) {   // any multiple of the step gives the same values
+        const int r = std::atoi(e);
+        if (r > 0) return kVMStep * ((r + kVMStep - 1) / kVMStep);
+    }
+    const int strips = (W + kVMW - 1) / kVMW, steps = (H + kVMStep - 1) / kVMStep;
+    const int segs = std::max(1, std::min(steps, (1024 + strips - 1) / strips));
+    return kVMStep * ((steps + segs - 1) / segs);
+}
+
 hipError_t launch_hpass(const float *u, float *A, float *B, float *C, int H, int W,
                         const WinTaps &t, hipStream_t s)
 {
+    if (const int nc = sweep_chunks(t)) {
+        const int tiles_x = (W + kHMW - 1) / kHMW;
+        const int ntiles = tiles_x * ((H + kHMH - 1) / kHMH);
+        const int per = (ntiles + 7) / 8;
+        switch (nc) {
+#define MF4D_HM(NC)                                                                                           \
+    case NC:                                                                                                  \
+        hipLaunchKernelGGL(hpass_mfma_kernel<NC>, dim3(8 * per), dim3(256), hpass_mfma_lds(NC), s, u, A, B, C, H, \
+                           W, t, tiles_x, ntiles, per);                                                      \
+        break;
+            MF4D_HM(2) MF4D_HM(3) MF4D_HM(4) MF4D_HM(5) MF4D_HM(6) MF4D_HM(7) MF4D_HM(8) MF4D_HM(9)
+#undef MF4D_HM
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     dim3 grid((W + 63) / 64, (H + 63) / 64);
     const size_t lds = (size_t)64 * (t.ntaps + 65) * sizeof(float);
     hipLaunchKernelGGL(hpass_kernel, grid, dim3(256), lds, s, u, A, B, C, H, W, t);
@@ -94,9 +165,26 @@ hipError_t launch_vpass(const float *A, const float *B, const float *C, int H, i
                         const WinTaps &t, float sigma, int mode, float beta, ScalePlanes out,
                         unsigned *smax_bits, hipStream_t s)
 {
-    dim3 grid((W + 63) / 64, (H + 63) / 64);
     const float sigma2 = sigma * sigma;
     const float inv2beta2 = 1.f / (2.f * beta * beta);
+    if (const int nc = sweep_chunks(t)) {
+        const int seg_rows = vpass_seg_rows(H, W);
+        const int segs = (H + seg_rows - 1) / seg_rows;
+        const int nblk = segs * ((W + kVMW - 1) / kVMW);
+        const int per = (nblk + 7) / 8;
+        switch (nc) {
+#define MF4D_VM(NC)                                                                                            \
+    case NC:                                                                                                   \
+        hipLaunchKernelGGL(vpass_mfma_kernel<NC>, dim3(8 * per), dim3(256), vpass_mfma_lds(NC), s, A, B, C, H, W, \
+                           t, sigma2, inv2beta2, mode, out.S, out.A, out.N, smax_bits, segs, seg_rows, nblk, per); \
+        break;
+            MF4D_VM(2) MF4D_VM(3) MF4D_VM(4) MF4D_VM(5) MF4D_VM(6) MF4D_VM(7) MF4D_VM(8) MF4D_VM(9)
+#undef MF4D_VM
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    dim3 grid((W + 63) / 64, (H + 63) / 64);
     switch (mode) {
     case MF4D_RIDGE:
         hipLaunchKernelGGL(vpass_kernel<MF4D_RIDGE>, grid, dim3(256), 0, s, A, B, C, H, W, t, sigma2,

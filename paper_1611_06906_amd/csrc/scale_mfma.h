@@ -1,0 +1,261 @@
+// Matrix-core (FP32 MFMA) forms of the two separable passes of the scale
+// sweep (Sec. 3.3, derivatives of u_sigma for Eq. (9) and Eq. (6)), shared by
+// the single-image and the batched kernels.
+//
+// A 1-D correlation of 16 consecutive outputs with a (2R+1)-tap filter is the
+// product of a 16 x K banded Toeplitz matrix T[m][k] = tap[k - m] with the K
+// inputs starting R before the first output (K >= 16 + 2R, a multiple of 16).
+// One v_mfma_f32_16x16x4f32 multiplies a 16 x 4 slice of T by a 4 x 16 block
+// of inputs, so 16 columns (or rows) are filtered at once and K / 4 products
+// finish 256 outputs of one filter. Each lane keeps its Toeplitz entries for
+// all three filters (Gaussian, central difference, second difference) in
+// registers. The order of the K terms is free, so lane group q supplies the
+// four consecutive inputs 4q .. 4q+3 of each 16-input chunk over the four
+// products of the chunk, which one 16-byte LDS read delivers.
+//
+// Inputs are shifted by the value at the block's first output before the
+// products (as in the register-window passes), so locally constant lines
+// give exactly zero derivatives; the Gaussian output adds the shift back.
+// The values of a 16 x 16 block depend only on its position, not on how
+// blocks are grouped into workgroups.
+#pragma once
+
+#include "scale_tiles.h"
+
+namespace mf4d {
+namespace tiles {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMfmaMaxChunks = 9;      // K <= 144: radius R <= 64
+constexpr int kHMW = 256, kHMH = 16;   // horizontal tile: output columns x rows (4 waves x 4 blocks)
+constexpr int kVMW = 32, kVMStep = 32; // vertical strip width and rows per step (4 waves x one block)
+
+__host__ __device__ constexpr int mfma_chunks_for(int R) { return (16 + 2 * R + 15) / 16; }
+
+__host__ __device__ constexpr size_t hpass_mfma_lds(int nc) { return sizeof(float) * kHMH * (kHMW - 16 + 16 * nc + 4); }
+__host__ __device__ constexpr size_t vpass_mfma_lds(int nc) { return sizeof(float) * 3 * kVMW * (16 * nc + 16 + 4); }
+
+// Half-sample symmetric extension in closed form (the same index as
+// reflect() for any i): i mod 2n, mirrored in the upper half.
+__device__ __forceinline__ int reflect_any(int i, int n)
+{
+    const int p = 2 * n;
+    int j = i % p;
+    j = j < 0 ? j + p : j;
+    return j < n ? j : p - 1 - j;
+}
+
+__device__ __forceinline__ f4 mfma_f32(float a, float b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// This lane's entries of the Toeplitz slices: a[c][j] = tap[k - m] for row
+// m = lane % 16 and input k = 16c + 4(lane / 16) + j (zero outside 0..2R).
+template <int NC>
+__device__ __forceinline__ void toeplitz_lane(const float *tap, int R, float (&a)[NC][4])
+{
+    const int lane = threadIdx.x & 63, m = lane & 15, kq = lane >> 4;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int t = 16 * c + 4 * kq + j - m;
+            a[c][j] = (t >= 0 && t <= 2 * R) ? tap[t] : 0.f;
+        }
+}
+
+// ------------------------------------------------------------------ horizontal
+// Tile: 16 rows x 256 output columns at (x0, y0); wave w owns columns
+// 64w .. 64w+63 as four 16 x 16 blocks. The rows' inputs (x0 - R onwards)
+// are staged in LDS, row-major with a pitch of 4 mod 8 floats.
+template <int NC>
+__device__ __forceinline__ void hpass_mfma_tile(const float *__restrict__ u, float *__restrict__ A,
+                                               float *__restrict__ B, float *__restrict__ C, int H, int W,
+                                               const WinTaps &t, int x0, int y0, float *lds)
+{
+#pragma clang fp contract(off)   // fused multiply-adds are written out
+    constexpr int K = 16 * NC;
+    constexpr int Lc = kHMW - 16 + K;   // staged columns
+    constexpr int P = Lc + 4;
+    const int R = t.R;
+    float ag[NC][4], a1[NC][4], a2[NC][4];
+    toeplitz_lane<NC>(t.g, R, ag);
+    toeplitz_lane<NC>(t.d1, R, a1);
+    toeplitz_lane<NC>(t.d2, R, a2);
+    // 16 rows x Lc columns = (Lc / 16) values per thread, all loads issued
+    // before the LDS stores
+    constexpr int NI = Lc / 16;
+    const bool interior = (x0 - R >= 0) && (x0 - R + Lc <= W);
+    float v[NI];
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const int i = threadIdx.x + 256 * it;
+        const int r = i / Lc, c = i - r * Lc;
+        const int gy = min(y0 + r, H - 1);
+        const int gx = x0 - R + c;
+        v[it] = u[(size_t)gy * W + (interior ? gx : reflect_any(gx, W))];
+    }
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const int i = threadIdx.x + 256 * it;
+        const int r = i / Lc, c = i - r * Lc;
+        lds[r * P + c] = v[it];
+    }
+    __builtin_amdgcn_s_waitcnt(0);   // taps and staged values have arrived
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int n = lane & 15, kq = lane >> 4;
+    const float *row = lds + n * P;   // image row y0 + n
+    const int y = y0 + n;
+    const float gsum = t.gsum;
+    const bool vec = ((W & 3) == 0) && ((((uintptr_t)A | (uintptr_t)B | (uintptr_t)C) & 15) == 0);
+#pragma unroll 1
+    for (int blk = 0; blk < 4; ++blk) {
+        const int xb = 64 * wv + 16 * blk;   // staged column of the block's input x0 + xb - R
+        const float ref = row[xb + R];       // input at the block's first output
+        f4 cg = {0.f, 0.f, 0.f, 0.f}, c1 = cg, c2 = cg;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const f4 b = *(const f4 *)(row + xb + 16 * c + 4 * kq) - ref;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                cg = mfma_f32(ag[c][j], b[j], cg);
+                c1 = mfma_f32(a1[c][j], b[j], c1);
+                c2 = mfma_f32(a2[c][j], b[j], c2);
+            }
+        }
+        // this lane holds outputs x0 + xb + 4 kq + i of row y
+        const int xo = x0 + xb + 4 * kq;
+        if (y < H && xo < W) {
+            const float gref = ref * gsum;
+            const size_t o = (size_t)y * W + xo;
+            if (vec && xo + 3 < W) {
+                *(f4 *)(A + o) = cg + gref;
+                *(f4 *)(B + o) = c1;
+                *(f4 *)(C + o) = c2;
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (xo + i < W) {
+                        A[o + i] = cg[i] + gref;
+                        B[o + i] = c1[i];
+                        C[o + i] = c2[i];
+                    }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ vertical
+// Strip: 32 columns at x0, output rows ys .. ye-1 (ys a multiple of 32,
+// ye <= H). The three horizontal-pass planes stream through an LDS ring of
+// K + 16 rows (column-major, so a lane's four consecutive rows are one
+// 16-byte read); each step filters 32 rows (wave w: columns 16 (w & 1),
+// rows 16 (w >> 1)) while the next 32 rows are loaded. Writes S, the blob
+// factor and N; returns the largest S this thread wrote (0 if none).
+template <int NC>
+__device__ __forceinline__ float vpass_mfma_tile(const float *__restrict__ A, const float *__restrict__ B,
+                                                 const float *__restrict__ C, int H, int W, const WinTaps &t,
+                                                 float sigma2, float inv2beta2, int mode, float *__restrict__ So,
+                                                 float *__restrict__ Ao, float *__restrict__ No, int x0, int ys,
+                                                 int ye, float *lds)
+{
+#pragma clang fp contract(off)   // fused multiply-adds are written out
+    constexpr int K = 16 * NC;
+    constexpr int RS = K + 16;   // ring rows; ring slot of input row y is (y - ys + R) mod RS
+    constexpr int P = RS + 4;    // column pitch (4 mod 8 floats)
+    constexpr int PL = kVMW * P;
+    const int R = t.R;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int n = lane & 15, kq = lane >> 4;
+    const int fc = tid & 31, fq = tid >> 5;   // loader: column, quad of rows
+    const size_t fx = (size_t)min(x0 + fc, W - 1);
+    float *fA = lds + fc * P;
+    float ag[NC][4], a1[NC][4], a2[NC][4];
+    toeplitz_lane<NC>(t.g, R, ag);
+    toeplitz_lane<NC>(t.d1, R, a1);
+    toeplitz_lane<NC>(t.d2, R, a2);
+    // rows r0 + 4 fq + i, i < 4, of the three planes into registers
+    auto load_quad = [&](int r0, f4 &va, f4 &vb, f4 &vc) {
+        const bool inside = r0 >= 0 && r0 + 32 <= H;   // uniform over the block
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int y = r0 + 4 * fq + i;
+            const size_t o = (size_t)(inside ? y : reflect_any(y, H)) * W + fx;
+            va[i] = A[o];
+            vb[i] = B[o];
+            vc[i] = C[o];
+        }
+    };
+    // prologue: ring rows ys - R .. ys - R + RS - 1, 32 rows per pass
+    constexpr int NQ = RS / 32 + ((RS % 32) ? 1 : 0);
+#pragma unroll
+    for (int q0 = 0; q0 < NQ; ++q0) {
+        if (q0 * 32 + 4 * fq < RS) {
+            f4 va, vb, vc;
+            load_quad(ys - R + 32 * q0, va, vb, vc);
+            *(f4 *)(fA + 32 * q0 + 4 * fq) = va;
+            *(f4 *)(fA + PL + 32 * q0 + 4 * fq) = vb;
+            *(f4 *)(fA + 2 * PL + 32 * q0 + 4 * fq) = vc;
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);   // taps and ring rows have arrived
+    __syncthreads();
+    const int col = 16 * (wv & 1) + n;
+    const int x = x0 + col;
+    const float *rA = lds + col * P, *rB = rA + PL, *rC = rA + 2 * PL;
+    const size_t plane = (size_t)H * W;
+    const float gsum = t.gsum;
+    float smax = 0.f;
+    for (int yb = ys; yb < ye; yb += kVMStep) {
+        const bool more = yb + kVMStep < ye;
+        f4 na, nb, nc;   // rows of the next step (loaded even after the last step: the count stays fixed)
+        load_quad(yb - R + K + 16, na, nb, nc);
+        const int y0 = yb + 16 * (wv >> 1);
+        const int s0 = (y0 - ys) % RS;           // slot of input row y0 - R
+        const int sr = (y0 - ys + R) % RS;       // slot of input row y0
+        const float aref = rA[sr], bref = rB[sr];
+        f4 cuy = {0.f, 0.f, 0.f, 0.f}, cuyy = cuy, cux = cuy, cuxy = cuy, cuxx = cuy;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            int s = s0 + 16 * c + 4 * kq;
+            s = s >= RS ? s - RS : s;
+            const f4 va = *(const f4 *)(rA + s) - aref;
+            const f4 vb = *(const f4 *)(rB + s) - bref;
+            const f4 vc = *(const f4 *)(rC + s);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                cuy = mfma_f32(a1[c][j], va[j], cuy);
+                cuyy = mfma_f32(a2[c][j], va[j], cuyy);
+                cux = mfma_f32(ag[c][j], vb[j], cux);
+                cuxy = mfma_f32(a1[c][j], vb[j], cuxy);
+                cuxx = mfma_f32(ag[c][j], vc[j], cuxx);
+            }
+        }
+        __syncthreads();   // every wave is done with the ring rows yb - R .. yb - R + 31
+        if (more) {        // their slots take the next step's rows
+            const int sn = (yb - ys + 4 * fq) % RS;
+            *(f4 *)(fA + sn) = na;
+            *(f4 *)(fA + PL + sn) = nb;
+            *(f4 *)(fA + 2 * PL + sn) = nc;
+        }
+        // this lane holds rows y0 + 4 kq + i of column x
+        const float bsum = bref * gsum;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int y = y0 + 4 * kq + i;
+            if (x < W && y < ye) {
+                const float Sv = vessel_store_mode(mode, cuxx[i], cuxy[i], cuyy[i], cux[i] + bsum, cuy[i], sigma2,
+                                                   inv2beta2, So, Ao, No, (size_t)y * W + x, plane);
+                smax = fmaxf(smax, Sv);
+            }
+        }
+        __syncthreads();
+    }
+    return smax;
+}
+
+}  // namespace tiles
+}  // namespace mf4d

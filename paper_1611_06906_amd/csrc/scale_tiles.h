@@ -108,6 +108,57 @@ __device__ __forceinline__ void hpass_tile(const float *__restrict__ u, float *_
     }
 }
 
+// ------------------------------------------------------------------ per pixel
+// Vesselness ingredients that do not depend on the image-wide c (Eq. (9)):
+// S = |sigma^2 H|_F and the blob factor (0 where the mode's sign test fails),
+// and the normalised Hessian N = H / sqrt(1 + |grad u_sigma|) (Eq. (6)),
+// stored at pixel o. Returns S.
+template <int MODE>
+__device__ __forceinline__ float vessel_store(float uxx, float uxy, float uyy, float gx, float gy, float sigma2,
+                                              float inv2beta2, float *__restrict__ So, float *__restrict__ Ao,
+                                              float *__restrict__ No, size_t o, size_t plane)
+{
+#pragma clang fp contract(off)   // fused multiply-adds are written out
+    // scale-normalised Hessian sigma^2 H; eigenvalues m +- r
+    const float hxx = sigma2 * uxx, hxy = sigma2 * uxy, hyy = sigma2 * uyy;
+    const float m = 0.5f * (hxx + hyy);
+    const float hd = 0.5f * (hxx - hyy);
+    const float r = sqrtf(fmaf(hd, hd, hxy * hxy));
+    const float Sv = sqrtf(fmaf(2.f * hxy, hxy, fmaf(hxx, hxx, hyy * hyy)));   // sqrt(nu~1^2 + nu~2^2)
+    // |nu~2| = |m| + r carries the sign of m (a zero trace passes the test)
+    const float am = fabsf(m);
+    const float big = am + r;
+    bool pass = big > 0.f;
+    if (MODE == MF4D_RIDGE) pass = pass && !(m > 0.f);
+    if (MODE == MF4D_VALLEY) pass = pass && !(m < 0.f);
+    float blob = 0.f;
+    if (pass) {
+        const float rb = (am - r) / big;   // |R_B| = |nu~1| / |nu~2|
+        blob = expf(-(rb * rb) * inv2beta2);
+    }
+    So[o] = Sv;
+    Ao[o] = blob;
+    if (No) {
+        const float f = 1.f / sqrtf(1.f + sqrtf(fmaf(gx, gx, gy * gy)));
+        No[o] = uxx * f;
+        No[plane + o] = uxy * f;
+        No[2 * plane + o] = uyy * f;
+    }
+    return Sv;
+}
+
+__device__ __forceinline__ float vessel_store_mode(int mode, float uxx, float uxy, float uyy, float gx, float gy,
+                                                   float sigma2, float inv2beta2, float *__restrict__ So,
+                                                   float *__restrict__ Ao, float *__restrict__ No, size_t o,
+                                                   size_t plane)
+{
+    if (mode == MF4D_RIDGE)
+        return vessel_store<MF4D_RIDGE>(uxx, uxy, uyy, gx, gy, sigma2, inv2beta2, So, Ao, No, o, plane);
+    if (mode == MF4D_VALLEY)
+        return vessel_store<MF4D_VALLEY>(uxx, uxy, uyy, gx, gy, sigma2, inv2beta2, So, Ao, No, o, plane);
+    return vessel_store<MF4D_BOTH>(uxx, uxy, uyy, gx, gy, sigma2, inv2beta2, So, Ao, No, o, plane);
+}
+
 // ------------------------------------------------------------------ vertical
 // Tile: 64 output columns x 64 rows at (x0, ty0); lane = column, wave w owns
 // rows 16w .. 16w+15, streamed from global memory through the register
@@ -167,33 +218,8 @@ __device__ __forceinline__ float vpass_tile(const float *__restrict__ A, const f
     for (int k = 0; k < K; ++k) {
         const int y = y0 + k;
         if (x < W && y < H) {
-            // scale-normalised Hessian sigma^2 H; eigenvalues m +- r
-            const float hxx = sigma2 * uxx[k], hxy = sigma2 * uxy[k], hyy = sigma2 * uyy[k];
-            const float m = 0.5f * (hxx + hyy);
-            const float hd = 0.5f * (hxx - hyy);
-            const float r = sqrtf(fmaf(hd, hd, hxy * hxy));
-            const float Sv = sqrtf(fmaf(2.f * hxy, hxy, fmaf(hxx, hxx, hyy * hyy)));   // sqrt(nu~1^2 + nu~2^2)
-            // |nu~2| = |m| + r carries the sign of m (a zero trace passes the test)
-            const float am = fabsf(m);
-            const float big = am + r;
-            bool pass = big > 0.f;
-            if (MODE == MF4D_RIDGE) pass = pass && !(m > 0.f);
-            if (MODE == MF4D_VALLEY) pass = pass && !(m < 0.f);
-            float blob = 0.f;
-            if (pass) {
-                const float rb = (am - r) / big;   // |R_B| = |nu~1| / |nu~2|
-                blob = expf(-(rb * rb) * inv2beta2);
-            }
-            const size_t o = (size_t)y * W + x;
-            So[o] = Sv;
-            Ao[o] = blob;
-            if (No) {
-                const float gx = ux[k] + bsum, gy = uy[k];
-                const float f = 1.f / sqrtf(1.f + sqrtf(fmaf(gx, gx, gy * gy)));
-                No[o] = uxx[k] * f;
-                No[plane + o] = uxy[k] * f;
-                No[2 * plane + o] = uyy[k] * f;
-            }
+            const float Sv = vessel_store<MODE>(uxx[k], uxy[k], uyy[k], ux[k] + bsum, uy[k], sigma2, inv2beta2,
+                                                So, Ao, No, (size_t)y * W + x, plane);
             smax = fmaxf(smax, Sv);
         }
     }
@@ -243,7 +269,10 @@ __device__ __forceinline__ int argmax_px(const float *__restrict__ S, const floa
 }
 
 // H_rho = G_rho * N (separable, symmetric extension) on the 64 x 32 tile at
-// (x0, y0); writes H_rho and/or the compact tensor planes of H_rho.
+// (x0, y0); writes H_rho and/or the compact tensor planes of H_rho. The
+// tile's inputs (with a halo of HR) are staged in LDS; thread (x, g) blurs
+// rows 8g - HR .. 8g + 7 + HR of column x horizontally into registers and
+// then vertically, so only one LDS buffer is needed.
 template <int HR>
 __device__ __forceinline__ void rho_blur_tile(const float *__restrict__ N, float *__restrict__ Hr,
                                               float *__restrict__ coef, int mode, float inv_lam2, int H, int W,
@@ -251,8 +280,9 @@ __device__ __forceinline__ void rho_blur_tile(const float *__restrict__ N, float
 {
 #pragma clang fp contract(off)   // fused multiply-adds are written out
     constexpr int PW = kBTW + 2 * HR, PH = kBTH + 2 * HR;
+    constexpr int RG = kBTH / 4;       // output rows per thread
+    constexpr int RH = RG + 2 * HR;    // rows blurred horizontally per thread
     __shared__ float sN[3][PH][PW + 1];
-    __shared__ float sT[3][PH][kBTW + 1];
     const size_t plane = (size_t)H * W;
     const bool interior = x0 - HR >= 0 && y0 - HR >= 0 && x0 + kBTW + HR <= W && y0 + kBTH + HR <= H;
     for (int i = threadIdx.x; i < PW * PH; i += 256) {
@@ -265,38 +295,41 @@ __device__ __forceinline__ void rho_blur_tile(const float *__restrict__ N, float
         sN[2][ly][lx] = N[2 * plane + o];
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < PH * kBTW; i += 256) {
-        const int ly = i >> 6, lx = i & 63;
+    const int lx = threadIdx.x & 63, g = threadIdx.x >> 6;
+    float h[3][RG];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            float s = t.g[0] * sN[k][ly][lx + HR];
+    for (int k = 0; k < 3; ++k) {
+        float sT[RH];   // horizontal blur of staged rows RG g .. RG g + RH - 1
 #pragma unroll
-            for (int j = 1; j <= HR; ++j) s = fmaf(t.g[j], sN[k][ly][lx + HR - j] + sN[k][ly][lx + HR + j], s);
-            sT[k][ly][lx] = s;
+        for (int r = 0; r < RH; ++r) {
+            const float *row = &sN[k][RG * g + r][lx + HR];
+            float s = t.g[0] * row[0];
+#pragma unroll
+            for (int j = 1; j <= HR; ++j) s = fmaf(t.g[j], row[-j] + row[j], s);
+            sT[r] = s;
+        }
+#pragma unroll
+        for (int r = 0; r < RG; ++r) {
+            float s = t.g[0] * sT[r + HR];
+#pragma unroll
+            for (int j = 1; j <= HR; ++j) s = fmaf(t.g[j], sT[r + HR - j] + sT[r + HR + j], s);
+            h[k][r] = s;
         }
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < kBTH * kBTW; i += 256) {
-        const int ly = i >> 6, lx = i & 63;
-        const int gx = x0 + lx, gy = y0 + ly;
+    const int gx = x0 + lx;
+#pragma unroll
+    for (int r = 0; r < RG; ++r) {
+        const int gy = y0 + RG * g + r;
         if (gx >= W || gy >= H) continue;
         const size_t o = (size_t)gy * W + gx;
-        float h[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            float s = t.g[0] * sT[k][ly + HR][lx];
-#pragma unroll
-            for (int j = 1; j <= HR; ++j) s = fmaf(t.g[j], sT[k][ly + HR - j][lx] + sT[k][ly + HR + j][lx], s);
-            h[k] = s;
-        }
         if (Hr) {
-            Hr[o] = h[0];
-            Hr[plane + o] = h[1];
-            Hr[2 * plane + o] = h[2];
+            Hr[o] = h[0][r];
+            Hr[plane + o] = h[1][r];
+            Hr[2 * plane + o] = h[2][r];
         }
         if (coef) {
             float mb, al, be;
-            tensor_coeffs_mode(mode, h[0], h[1], h[2], inv_lam2, mb, al, be);
+            tensor_coeffs_mode(mode, h[0][r], h[1][r], h[2][r], inv_lam2, mb, al, be);
             coef[o] = mb;
             coef[plane + o] = al;
             coef[2 * plane + o] = be;

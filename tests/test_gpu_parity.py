@@ -5,6 +5,9 @@ relative L2 <= 1e-5. Scale indices: bit-exact except at stated near-ties,
 where the GPU's choice g is accepted iff the oracle's V_g is within
 1e-5 + 1e-4 V_max of the oracle's maximum V_max, or the oracle's vesselness
 sign test at scale g is itself a near-tie (|trace| <= 1e-5 |sigma^2 H|).
+Where such a near-tie pick differs from the oracle's, the image tolerance
+applies outside the reach of that difference (G_rho radius + 2 pixels per
+substep); the relative L2 bound applies to the whole image.
 """
 import math
 import sys
@@ -69,14 +72,16 @@ def _near_tie_ok(env, u, sig, mode, gpu_idx, ref):
     V = ref["V"]
     bad = 0
     sign_ties = 0
+    hess = {}
     for y, x in diff:
         g = gpu_idx[y, x]
         vmax = V[:, y, x].max()
         if V[g, y, x] >= vmax - (1e-5 + 1e-4 * vmax):
             continue
         # sign-test near-tie at scale g: trace of sigma^2 H small against its norm
-        s = float(np.float32(sig[g]))
-        _, _, hxx, hxy, hyy = o.derivatives(o.blur(u.astype(np.float64), s))
+        if g not in hess:
+            hess[g] = o.derivatives(o.blur(u.astype(np.float64), float(np.float32(sig[g]))))[2:]
+        hxx, hxy, hyy = hess[g]
         tr = abs(hxx[y, x] + hyy[y, x])
         nrm = math.sqrt(hxx[y, x] ** 2 + hyy[y, x] ** 2 + 2 * hxy[y, x] ** 2)
         if tr <= 1e-5 * nrm:
@@ -177,6 +182,81 @@ def test_scale_select_degenerate(env):
     assert c.item() == 0.0 and int(idx.max()) == 0
 
 
+# ------------------------------------------------------------------ sweep engines
+# Scales whose radii span the matrix-core passes (2, 3, 5 and 8 chunks of 16
+# inputs) and the register-window passes (radius 64). "default" is the
+# library's own choice per pass; "mfma_all" puts every vertical pass within
+# the matrix-core tiles' reach on them, and "mfma_ring" also makes it stream
+# several 32-row steps through its LDS ring per workgroup; "valu" forces the
+# register-window passes for every scale.
+LARGE_SIG = [1.0, 4.0, 10.0, 16.0, 21.3]
+ENGINES = {"default": {}, "mfma_all": {"MF4D_SWEEP": "mfma"},
+           "mfma_ring": {"MF4D_SWEEP": "mfma", "MF4D_VSEG_ROWS": "96"}, "valu": {"MF4D_SWEEP": "valu"}}
+
+
+def _large_image(env, H=190, W=300, seed=11):
+    return env["synth"].creases(H, W, 8, seed, background=0.5, amplitude=0.4, width_range=(1.0, 16.0),
+                                signs="mixed")
+
+
+def _gpu_select(env, u, p):
+    torch, m = env["torch"], env["m"]
+    idx = torch.empty(u.shape, dtype=torch.uint8, device=env["dev"])
+    vmax = torch.empty(u.shape, dtype=torch.float32, device=env["dev"])
+    c = torch.empty(1, dtype=torch.float32, device=env["dev"])
+    m.mf4d_scale_select(_to(env, u), p, idx, vmax, c)
+    torch.cuda.synchronize()
+    return idx.cpu().numpy(), vmax.cpu().numpy(), float(c.item())
+
+
+@pytest.mark.parametrize("engine", list(ENGINES))
+@pytest.mark.parametrize("mode", [0, 2])
+def test_scale_select_large_scales(env, engine, mode, monkeypatch):
+    for k, v in ENGINES[engine].items():
+        monkeypatch.setenv(k, v)
+    u = _large_image(env)
+    _log(f"scale select large scales {u.shape} mode {mode} engine {engine}")
+    ref = env["o"].scale_select(u, LARGE_SIG, mode)
+    gi, gv, gc = _gpu_select(env, u, env["m"].Params(LARGE_SIG, mode=mode))
+    assert math.isclose(gc, ref["c"], rel_tol=1e-5)
+    ndiff, bad, st = _near_tie_ok(env, u, LARGE_SIG, mode, gi, ref)
+    _log(f"  idx differences {ndiff} (sign near-ties {st}), unexplained {bad}")
+    assert bad == 0
+    assert np.abs(gv - ref["vmax"]).max() <= 2e-5
+    assert np.bincount(ref["idx"].ravel(), minlength=len(LARGE_SIG)).min() > 0   # every scale is chosen
+
+
+def test_sweep_segmentation_changes_no_value(env, monkeypatch):
+    """The matrix-core vertical pass gives the same bits for any number of
+    32-row steps per workgroup."""
+    monkeypatch.setenv("MF4D_SWEEP", "mfma")
+    u = _large_image(env, 260, 200, seed=5)
+    p = env["m"].Params(LARGE_SIG[:4], mode=2)
+    base = _gpu_select(env, u, p)
+    for rows in ("32", "64", "160", "4096"):
+        monkeypatch.setenv("MF4D_VSEG_ROWS", rows)
+        got = _gpu_select(env, u, p)
+        assert np.array_equal(got[0], base[0]) and np.array_equal(got[1], base[1]) and got[2] == base[2], rows
+
+
+@pytest.mark.parametrize("engine", ["default", "mfma_all", "valu"])
+def test_filter_parity_large_scales(env, engine, monkeypatch):
+    for k, v in ENGINES[engine].items():
+        monkeypatch.setenv(k, v)
+    w = env["synth"].ridges128(H=150, W=170)
+    w.sigmas = [2.0, 8.0, 16.0]
+    w.mode = 2
+    w.cycles = 2
+    w.substeps = 10
+    u = _large_image(env, 150, 170, seed=3)
+    _log(f"filter parity large scales 150x170 engine {engine}")
+    got = _gpu_filter(env, u, env["m"].Params.from_workload(w))
+    ref = _oracle_filter(env, u, w)
+    e, r = _err(got, ref)
+    _log(f"  max-abs {e:.3e} rel-L2 {r:.3e}")
+    assert e <= MAXABS and r <= RELL2
+
+
 # ------------------------------------------------------------------ filter
 def test_filter_parity_ridges128(env):
     w = env["synth"].ridges128()
@@ -262,6 +342,42 @@ def test_filter_parity_fundus1024(env):
     e, r = _err(got, ref)
     _log(f"  max-abs {e:.3e} rel-L2 {r:.3e}")
     assert e <= MAXABS and r <= RELL2
+
+
+@pytest.mark.slow
+def test_filter_parity_creases4096_one_cycle(env):
+    """Full-size bench workload (4096^2, 8 scales 1..16, both modes, 20
+    substeps): one whole cycle in the bench's launch configuration, every
+    output element against the oracle.
+
+    At this size a few pixels sit at near-ties of the argmax (stated above),
+    where the GPU may pick the other scale. Such a pick changes N there, and
+    H_rho within the G_rho radius; each substep of L^T D L then reaches 2
+    pixels further. Outside that support (Chebyshev radius r_rho + 2 n
+    around every differing index) the image tolerance holds; the relative
+    L2 bound holds everywhere."""
+    from scipy import ndimage
+    m, torch = env["m"], env["torch"]
+    w = env["synth"].creases4096(cycles=1)
+    u = w.image()
+    p = m.Params.from_workload(w)
+    _log("filter parity creases4096, one cycle of 20 substeps")
+    got = _gpu_filter(env, u, p)
+    gi, _, gc = _gpu_select(env, u, p)   # the selection of the cycle (on u^0)
+    ref = _oracle_filter(env, u, w)
+    sel = env["o"].scale_select(u, w.sigmas, w.mode)
+    assert math.isclose(gc, sel["c"], rel_tol=1e-5)
+    ndiff, bad, st = _near_tie_ok(env, u, w.sigmas, w.mode, gi, sel)
+    _log(f"  idx differences {ndiff} (sign near-ties {st}), unexplained {bad}")
+    assert bad == 0
+    d = np.abs(got.astype(np.float64) - ref)
+    reach = 2 + 2 * w.substeps   # G_rho radius ceil(3 * 0.5) plus 2 per substep
+    near = ndimage.maximum_filter((gi != sel["idx"]).astype(np.uint8), size=2 * reach + 1) > 0
+    e_far = float(d[~near].max())
+    _, r = _err(got, ref)
+    _log(f"  max-abs {d.max():.3e} (outside {int(near.sum())} px near differing indices: {e_far:.3e}) "
+         f"rel-L2 {r:.3e}")
+    assert e_far <= MAXABS and r <= RELL2
 
 
 @pytest.mark.parametrize("mode", [0, 1, 2])
