@@ -19,7 +19,7 @@ FLAGS = [
     "-shared",
     # packed FP32 instructions are disabled for every kernel of the library
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-ffp-contract=fast",
+    "-ffp-contract=fast-honor-pragmas",
     "-Wall",
     "-Wno-unused-function",
 ]

@@ -38,11 +38,12 @@ struct BImg {
     int strips[5], segs[5], seg_rows[5];   // streaming decomposition per substeps-per-launch
 };
 
-enum { PT_HV = 0, PT_PX, PT_RHO, PT_ST1, PT_ST2, PT_ST3, PT_ST4, PT_HM, PT_VM, PT_COUNT };
+enum { PT_HV = 0, PT_PX, PT_RHO, PT_ST1, PT_ST2, PT_ST3, PT_ST4, PT_HM, PT_VM, PT_FU, PT_COUNT };
 
-// rows per workgroup of the batched matrix-core vertical pass (any multiple
-// of its step gives the same values)
+// rows per workgroup of the batched matrix-core vertical pass and of the
+// batched fused kernel (any multiple of the step gives the same values)
 constexpr int kBatchVSegRows = 256;
+constexpr int kBatchFusedSegRows = 1024;
 
 namespace {
 
@@ -151,6 +152,26 @@ __global__ __launch_bounds__(256) void batch_vpass_mfma_kernel(const BImg *imgs,
     const float v = vpass_mfma_tile<NC>(im.hA, im.hA + m, im.hA + 2 * m, im.H, im.W, t, sigma2, inv2beta2, im.mode,
                                         im.S + s * m, im.A + s * m, im.N + 3 * s * m, strip * kVMW, ys, ye,
                                         (float *)lds4);
+    block_max_to(v, im.smax);
+}
+
+template <int NC>
+__global__ __launch_bounds__(256, 2) void batch_sweep_fused_kernel(const BImg *imgs, const int *pre, int nact, WinTaps t,
+                                                                float sigma2, float inv2beta2, int s, int jsrc,
+                                                                int per_xcd)
+{
+    extern __shared__ f4 lds4[];
+    const int b = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (b >= pre[nact]) return;
+    const int i = image_of(pre, nact, b);
+    const BImg &im = imgs[i];
+    const int lt = b - pre[i];
+    const int segs = (im.H + kBatchFusedSegRows - 1) / kBatchFusedSegRows;
+    const int strip = lt / segs, seg = lt - strip * segs;
+    const int ys = seg * kBatchFusedSegRows, ye = min(im.H, ys + kBatchFusedSegRows);
+    const size_t m = (size_t)im.H * im.W;
+    const float v = sweep_fused_tile<NC>(state_src(im, jsrc), im.H, im.W, t, sigma2, inv2beta2, im.mode, im.S + s * m,
+                                         im.A + s * m, im.N + 3 * s * m, strip * kVMW, ys, ye, (float *)lds4);
     block_max_to(v, im.smax);
 }
 
@@ -301,6 +322,7 @@ void build_tables(mf4d_batch *b, const float *in, float *out, char *ws, std::vec
         pre[PT_RHO][r + 1] = pre[PT_RHO][r] + rho;
         pre[PT_HM][r + 1] = pre[PT_HM][r] + ((W + kHMW - 1) / kHMW) * ((H + kHMH - 1) / kHMH);
         pre[PT_VM][r + 1] = pre[PT_VM][r] + ((W + kVMW - 1) / kVMW) * ((H + kBatchVSegRows - 1) / kBatchVSegRows);
+        pre[PT_FU][r + 1] = pre[PT_FU][r] + ((W + kVMW - 1) / kVMW) * ((H + kBatchFusedSegRows - 1) / kBatchFusedSegRows);
         for (int s = 1; s <= 4; ++s)
             pre[PT_ST1 + s - 1][r + 1] = pre[PT_ST1 + s - 1][r] + (im.strips[s] * im.segs[s] + 3) / 4;
     }
@@ -341,6 +363,21 @@ int enqueue_batch(mf4d_batch *b, char *ws, const std::vector<int> pre[PT_COUNT],
         BCHECK(hipGetLastError());
         for (int sc = 0; sc < ns; ++sc) {
             const float sig = p.sigmas[sc];
+            if (sweep_engine(taps[sc]) == kSweepFused) {
+                const int per_f = (pre[PT_FU][nact] + 7) / 8;
+                switch (sweep_chunks(taps[sc])) {
+#define MF4D_BFU(NC)                                                                                              \
+    case NC:                                                                                                      \
+        hipLaunchKernelGGL(batch_sweep_fused_kernel<NC>, dim3(8 * per_f), dim3(256), fused_lds(NC), s, imgs,          \
+                           P(PT_FU), nact, taps[sc], sig * sig, inv2beta2, sc, j, per_f);                         \
+        break;
+                    MF4D_BFU(2) MF4D_BFU(3) MF4D_BFU(4) MF4D_BFU(5) MF4D_BFU(6) MF4D_BFU(7) MF4D_BFU(8)
+#undef MF4D_BFU
+                default: return MF4D_EINVAL;
+                }
+                BCHECK(hipGetLastError());
+                continue;
+            }
             if (const int nc = sweep_chunks(taps[sc])) {
                 const int per_h = (pre[PT_HM][nact] + 7) / 8;
                 switch (nc) {

@@ -246,10 +246,9 @@ int run_sweep(const float *u, int H, int W, const mf4d_params *p, const Workspac
     WinTaps t;
     for (int k = 0; k < p->nscales; ++k) {
         make_taps(p->sigmas[k], &t);
-        CHECK_HIP(launch_hpass(u, w.hA, w.hB, w.hC, H, W, t, s));
         ScalePlanes planes{w.S + k * m, w.A + k * m, want_n ? w.N + 3 * k * m : nullptr};
-        CHECK_HIP(launch_vpass(w.hA, w.hB, w.hC, H, W, t, p->sigmas[k], p->mode, p->beta, planes,
-                               w.smax, s));
+        CHECK_HIP(launch_sweep_scale(u, w.hA, w.hB, w.hC, H, W, t, p->sigmas[k], p->mode, p->beta, planes,
+                                     w.smax, s));
     }
     return MF4D_OK;
 }

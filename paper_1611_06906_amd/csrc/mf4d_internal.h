@@ -55,6 +55,18 @@ hipError_t launch_vpass(const float *A, const float *B, const float *C, int H, i
 // register-window passes (radius beyond the matrix-core tiles, or the
 // environment variable MF4D_SWEEP=valu).
 int sweep_chunks(const WinTaps &t);
+// How a scale's two passes run: one fused matrix-core kernel, two
+// matrix-core kernels (MF4D_SWEEP=split, or too many chunks for the fused
+// kernel's LDS), or the register-window kernels.
+enum { kSweepFused = 0, kSweepSplit = 1, kSweepValu = 2 };
+int sweep_engine(const WinTaps &t);
+// Both passes of one scale (the planes hA, hB, hC are used by the split and
+// register-window forms only).
+hipError_t launch_sweep_scale(const float *u, float *hA, float *hB, float *hC, int H, int W, const WinTaps &t,
+                              float sigma, int mode, float beta, ScalePlanes out, unsigned *smax_bits, hipStream_t s);
+// Rows per workgroup of the single-image fused kernel (MF4D_VSEG_ROWS
+// overrides it; values do not change).
+int fused_seg_rows(int H, int W, int nc);
 // Rows per workgroup of the single-image matrix-core vertical pass (the
 // environment variable MF4D_VSEG_ROWS overrides it; values do not change).
 int vpass_seg_rows(int H, int W);

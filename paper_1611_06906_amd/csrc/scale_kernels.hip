@@ -63,6 +63,23 @@ __global__ __launch_bounds__(256) void vpass_mfma_kernel(const float *__restrict
     block_max_to(v, smax_bits);
 }
 
+template <int NC>
+__global__ __launch_bounds__(256, 2) void sweep_fused_kernel(const float *__restrict__ u, int H, int W, WinTaps t,
+                                                          float sigma2, float inv2beta2, int mode,
+                                                          float *__restrict__ So, float *__restrict__ Ao,
+                                                          float *__restrict__ No, unsigned *__restrict__ smax_bits,
+                                                          int segs, int seg_rows, int nblk, int per_xcd)
+{
+    extern __shared__ f4 lds4[];
+    const int b = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (b >= nblk) return;
+    const int strip = b / segs, seg = b - strip * segs;
+    const int ys = seg * seg_rows, ye = min(H, ys + seg_rows);
+    const float v = sweep_fused_tile<NC>(u, H, W, t, sigma2, inv2beta2, mode, So, Ao, No, strip * kVMW, ys, ye,
+                                         (float *)lds4);
+    block_max_to(v, smax_bits);
+}
+
 __global__ void fill_u32_kernel(unsigned *p, unsigned v, size_t n)
 {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -123,6 +140,56 @@ int sweep_chunks(const WinTaps &t)
     const char *e = std::getenv("MF4D_SWEEP");
     if (e && std::strcmp(e, "valu") == 0) return 0;
     return nc;
+}
+
+int sweep_engine(const WinTaps &t)
+{
+    const int nc = sweep_chunks(t);
+    if (!nc) return kSweepValu;
+    const char *e = std::getenv("MF4D_SWEEP");
+    if (e && std::strcmp(e, "split") == 0) return kSweepSplit;
+    return nc <= kFusedMaxChunks ? kSweepFused : kSweepSplit;
+}
+
+int fused_seg_rows(int H, int W, int nc)
+{
+    if (const char *e = std::getenv("MF4D_VSEG_ROWS")) {   // any multiple of the step gives the same values
+        const int r = std::atoi(e);
+        if (r > 0) return kVMStep * ((r + kVMStep - 1) / kVMStep);
+    }
+    // one round of workgroups at the kernel's occupancy (workgroups per CU
+    // by its registers and LDS); longer strips amortise each one's first window
+    const int per_cu = nc <= 3 ? 4 : (nc == 4 ? 3 : 2);
+    const int strips = (W + kVMW - 1) / kVMW, steps = (H + kVMStep - 1) / kVMStep;
+    const int segs = std::max(1, std::min(steps, (256 * per_cu + strips - 1) / strips));
+    return kVMStep * ((steps + segs - 1) / segs);
+}
+
+hipError_t launch_sweep_scale(const float *u, float *hA, float *hB, float *hC, int H, int W, const WinTaps &t,
+                              float sigma, int mode, float beta, ScalePlanes out, unsigned *smax_bits, hipStream_t s)
+{
+    if (sweep_engine(t) != kSweepFused) {
+        hipError_t e = launch_hpass(u, hA, hB, hC, H, W, t, s);
+        if (e != hipSuccess) return e;
+        return launch_vpass(hA, hB, hC, H, W, t, sigma, mode, beta, out, smax_bits, s);
+    }
+    const float sigma2 = sigma * sigma;
+    const float inv2beta2 = 1.f / (2.f * beta * beta);
+    const int seg_rows = fused_seg_rows(H, W, sweep_chunks(t));
+    const int segs = (H + seg_rows - 1) / seg_rows;
+    const int nblk = segs * ((W + kVMW - 1) / kVMW);
+    const int per = (nblk + 7) / 8;
+    switch (sweep_chunks(t)) {
+#define MF4D_FU(NC)                                                                                           \
+    case NC:                                                                                                  \
+        hipLaunchKernelGGL(sweep_fused_kernel<NC>, dim3(8 * per), dim3(256), fused_lds(NC), s, u, H, W, t, sigma2, \
+                           inv2beta2, mode, out.S, out.A, out.N, smax_bits, segs, seg_rows, nblk, per);      \
+        break;
+        MF4D_FU(2) MF4D_FU(3) MF4D_FU(4) MF4D_FU(5) MF4D_FU(6) MF4D_FU(7) MF4D_FU(8)
+#undef MF4D_FU
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 int vpass_seg_rows(int H, int W)

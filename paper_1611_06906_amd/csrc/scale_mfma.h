@@ -28,13 +28,14 @@ namespace tiles {
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMfmaMaxChunks = 9;      // K <= 144: radius R <= 64
+constexpr int kFusedMaxChunks = 8;     // LDS of two fused workgroups per CU
 constexpr int kHMW = 256, kHMH = 16;   // horizontal tile: output columns x rows (4 waves x 4 blocks)
 constexpr int kVMW = 32, kVMStep = 32; // vertical strip width and rows per step (4 waves x one block)
 
 __host__ __device__ constexpr int mfma_chunks_for(int R) { return (16 + 2 * R + 15) / 16; }
 
 __host__ __device__ constexpr size_t hpass_mfma_lds(int nc) { return sizeof(float) * kHMH * (kHMW - 16 + 16 * nc + 4); }
-__host__ __device__ constexpr size_t vpass_mfma_lds(int nc) { return sizeof(float) * 3 * kVMW * (16 * nc + 16 + 4); }
+__host__ __device__ constexpr size_t vpass_mfma_lds(int nc) { return sizeof(float) * 3 * kVMW * (16 * nc + 48 + 4); }
 
 // Half-sample symmetric extension in closed form (the same index as
 // reflect() for any i): i mod 2n, mirrored in the upper half.
@@ -151,10 +152,12 @@ __device__ __forceinline__ void hpass_mfma_tile(const float *__restrict__ u, flo
 // ------------------------------------------------------------------ vertical
 // Strip: 32 columns at x0, output rows ys .. ye-1 (ys a multiple of 32,
 // ye <= H). The three horizontal-pass planes stream through an LDS ring of
-// K + 16 rows (column-major, so a lane's four consecutive rows are one
-// 16-byte read); each step filters 32 rows (wave w: columns 16 (w & 1),
-// rows 16 (w >> 1)) while the next 32 rows are loaded. Writes S, the blob
-// factor and N; returns the largest S this thread wrote (0 if none).
+// K + 48 rows (column-major, so a lane's four consecutive rows are one
+// 16-byte read): each step filters 32 rows (wave w: columns 16 (w & 1),
+// rows 16 (w >> 1)) from the K + 16 rows of its window while the next 32
+// rows are loaded into the other 32 slots, so one barrier per step
+// suffices. Writes S, the blob factor and N; returns the largest S this
+// thread wrote (0 if none).
 template <int NC>
 __device__ __forceinline__ float vpass_mfma_tile(const float *__restrict__ A, const float *__restrict__ B,
                                                  const float *__restrict__ C, int H, int W, const WinTaps &t,
@@ -164,7 +167,7 @@ __device__ __forceinline__ float vpass_mfma_tile(const float *__restrict__ A, co
 {
 #pragma clang fp contract(off)   // fused multiply-adds are written out
     constexpr int K = 16 * NC;
-    constexpr int RS = K + 16;   // ring rows; ring slot of input row y is (y - ys + R) mod RS
+    constexpr int RS = K + 48;   // ring rows; ring slot of input row y is (y - ys + R) mod RS
     constexpr int P = RS + 4;    // column pitch (4 mod 8 floats)
     constexpr int PL = kVMW * P;
     const int R = t.R;
@@ -189,11 +192,11 @@ __device__ __forceinline__ float vpass_mfma_tile(const float *__restrict__ A, co
             vc[i] = C[o];
         }
     };
-    // prologue: ring rows ys - R .. ys - R + RS - 1, 32 rows per pass
-    constexpr int NQ = RS / 32 + ((RS % 32) ? 1 : 0);
+    // prologue: the first window, rows ys - R .. ys - R + K + 15, 32 rows per pass
+    constexpr int NQ = (K + 16 + 31) / 32;
 #pragma unroll
     for (int q0 = 0; q0 < NQ; ++q0) {
-        if (q0 * 32 + 4 * fq < RS) {
+        if (q0 * 32 + 4 * fq < K + 16) {
             f4 va, vb, vc;
             load_quad(ys - R + 32 * q0, va, vb, vc);
             *(f4 *)(fA + 32 * q0 + 4 * fq) = va;
@@ -234,12 +237,177 @@ __device__ __forceinline__ float vpass_mfma_tile(const float *__restrict__ A, co
                 cuxx = mfma_f32(ag[c][j], vc[j], cuxx);
             }
         }
-        __syncthreads();   // every wave is done with the ring rows yb - R .. yb - R + 31
-        if (more) {        // their slots take the next step's rows
-            const int sn = (yb - ys + 4 * fq) % RS;
+        if (more) {   // the next step's rows go to the slots no window of this step uses
+            const int sn = (yb - ys + K + 16 + 4 * fq) % RS;
             *(f4 *)(fA + sn) = na;
             *(f4 *)(fA + PL + sn) = nb;
             *(f4 *)(fA + 2 * PL + sn) = nc;
+        }
+        // this lane holds rows y0 + 4 kq + i of column x
+        const float bsum = bref * gsum;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int y = y0 + 4 * kq + i;
+            if (x < W && y < ye) {
+                const float Sv = vessel_store_mode(mode, cuxx[i], cuxy[i], cuyy[i], cux[i] + bsum, cuy[i], sigma2,
+                                                   inv2beta2, So, Ao, No, (size_t)y * W + x, plane);
+                smax = fmaxf(smax, Sv);
+            }
+        }
+        __syncthreads();
+    }
+    return smax;
+}
+
+
+// ------------------------------------------------------------------ fused
+// Both passes of one scale on a strip of 32 columns at x0, output rows
+// ys .. ye-1 (ys a multiple of 32, ye <= H), without the horizontal-pass
+// planes in HBM. Each step stages 32 rows of u (columns x0 - R onwards) in
+// LDS, runs the horizontal products on them (wave w: columns 16 (w & 1),
+// rows 16 (w >> 1), the same 16 x 16 blocks and shifts as hpass_mfma_tile)
+// and puts the three results into the vertical pass's ring of K + 16 rows,
+// whose products and per-pixel outputs are those of vpass_mfma_tile; the
+// values equal those of the two separate passes bit for bit. Rows outside
+// the image are the horizontal pass of the reflected row of u.
+__host__ __device__ constexpr size_t fused_lds(int nc) { return sizeof(float) * 4 * kVMW * (16 * nc + 16 + 4); }
+
+template <int NC>
+__device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, int H, int W, const WinTaps &t,
+                                                  float sigma2, float inv2beta2, int mode, float *__restrict__ So,
+                                                  float *__restrict__ Ao, float *__restrict__ No, int x0, int ys,
+                                                  int ye, float *lds)
+{
+#pragma clang fp contract(off)   // fused multiply-adds are written out
+    constexpr int K = 16 * NC;
+    constexpr int RS = K + 16;        // ring rows; ring slot of row y is (y - ys + R) mod RS
+    constexpr int P = RS + 4;         // ring column pitch (4 mod 8 floats)
+    constexpr int PL = kVMW * P;
+    constexpr int UW = K + 16;        // staged u columns x0 - R .. x0 - R + UW - 1
+    constexpr int UP = UW + 4;        // staged row pitch (4 mod 8 floats)
+    constexpr int NU = 32 * UW / 256; // staged values per thread
+    float *ring = lds, *us = lds + 3 * PL;
+    const int R = t.R;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int n = lane & 15, kq = lane >> 4;
+    const int cb = 16 * (wv & 1), rb = 16 * (wv >> 1);   // this wave's block: columns cb.., rows rb..
+    const bool xin = (x0 - R >= 0) && (x0 - R + UW <= W);
+    float ag[NC][4], a1[NC][4], a2[NC][4];
+    toeplitz_lane<NC>(t.g, R, ag);
+    toeplitz_lane<NC>(t.d1, R, a1);
+    toeplitz_lane<NC>(t.d2, R, a2);
+    const float gsum = t.gsum;
+    // 32 rows of u from row r0 on (reflected), all loads before any LDS store
+    auto load_u = [&](int r0, float (&v)[NU]) {
+        const bool yin = r0 >= 0 && r0 + 32 <= H;
+#pragma unroll
+        for (int it = 0; it < NU; ++it) {
+            const int e = tid + 256 * it;
+            const int r = e / UW, c = e - r * UW;
+            const int gy = yin ? r0 + r : reflect_any(r0 + r, H);
+            const int gx = x0 - R + c;
+            v[it] = u[(size_t)gy * W + (xin ? gx : reflect_any(gx, W))];
+        }
+    };
+    auto store_u = [&](const float (&v)[NU]) {
+#pragma unroll
+        for (int it = 0; it < NU; ++it) {
+            const int e = tid + 256 * it;
+            const int r = e / UW, c = e - r * UW;
+            us[r * UP + c] = v[it];
+        }
+    };
+    // horizontal products of this wave's block of the staged rows; lane holds
+    // columns cb + 4 kq + i of staged row rb + n
+    auto hpass_block = [&](f4 &hg, f4 &h1, f4 &h2) {
+#pragma clang fp contract(off)   // as in hpass_mfma_tile: the shift is added back after rounding ref * gsum
+        const float *row = us + (rb + n) * UP;
+        const float ref = row[cb + R];
+        hg = (f4){0.f, 0.f, 0.f, 0.f};
+        h1 = hg;
+        h2 = hg;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const f4 b = *(const f4 *)(row + cb + 16 * c + 4 * kq) - ref;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                hg = mfma_f32(ag[c][j], b[j], hg);
+                h1 = mfma_f32(a1[c][j], b[j], h1);
+                h2 = mfma_f32(a2[c][j], b[j], h2);
+            }
+        }
+        hg = hg + ref * gsum;
+    };
+    auto ring_put = [&](int slot, const f4 &hg, const f4 &h1, const f4 &h2) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float *cp = ring + (cb + 4 * kq + i) * P + slot;
+            cp[0] = hg[i];
+            cp[PL] = h1[i];
+            cp[2 * PL] = h2[i];
+        }
+    };
+    // prologue: the first window, rows ys - R .. ys - R + RS - 1, 32 rows at a time
+    constexpr int NB0 = (RS + 31) / 32;
+#pragma unroll 1
+    for (int bt = 0; bt < NB0; ++bt) {
+        float v[NU];
+        load_u(ys - R + 32 * bt, v);
+        if (bt > 0) __syncthreads();   // the previous batch's staged rows have been read
+        store_u(v);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        f4 hg, h1, h2;
+        hpass_block(hg, h1, h2);
+        const int slot = 32 * bt + rb + n;
+        if (slot < RS) ring_put(slot, hg, h1, h2);
+    }
+    {   // staged u for the rows that enter the window of the second step
+        float v[NU];
+        load_u(ys - R + RS, v);
+        __syncthreads();
+        store_u(v);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    const int col = cb + n;
+    const int x = x0 + col;
+    const float *rA = ring + col * P, *rB = rA + PL, *rC = rA + 2 * PL;
+    const size_t plane = (size_t)H * W;
+    float smax = 0.f;
+    for (int yb = ys; yb < ye; yb += kVMStep) {
+        const bool more = yb + kVMStep < ye;
+        float v[NU];   // u rows entering the window two steps ahead (loaded even when unused)
+        load_u(yb + kVMStep - R + RS, v);
+        // vertical products of this step's window
+        const int y0 = yb + rb;
+        const int s0 = (y0 - ys) % RS;           // slot of row y0 - R
+        const int sr = (y0 - ys + R) % RS;       // slot of row y0
+        const float aref = rA[sr], bref = rB[sr];
+        f4 cuy = {0.f, 0.f, 0.f, 0.f}, cuyy = cuy, cux = cuy, cuxy = cuy, cuxx = cuy;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            int s = s0 + 16 * c + 4 * kq;
+            s = s >= RS ? s - RS : s;
+            const f4 va = *(const f4 *)(rA + s) - aref;
+            const f4 vb = *(const f4 *)(rB + s) - bref;
+            const f4 vc = *(const f4 *)(rC + s);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                cuy = mfma_f32(a1[c][j], va[j], cuy);
+                cuyy = mfma_f32(a2[c][j], va[j], cuyy);
+                cux = mfma_f32(ag[c][j], vb[j], cux);
+                cuxy = mfma_f32(a1[c][j], vb[j], cuxy);
+                cuxx = mfma_f32(ag[c][j], vc[j], cuxx);
+            }
+        }
+        // horizontal products of the rows entering the next window
+        f4 hg, h1, h2;
+        hpass_block(hg, h1, h2);
+        __syncthreads();   // the window's first 32 rows and the staged rows have been read
+        if (more) {
+            ring_put((yb - ys + rb + n) % RS, hg, h1, h2);   // slots of rows yb - R .. yb - R + 31
+            store_u(v);
         }
         // this lane holds rows y0 + 4 kq + i of column x
         const float bsum = bref * gsum;

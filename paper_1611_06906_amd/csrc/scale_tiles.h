@@ -119,27 +119,28 @@ __device__ __forceinline__ float vessel_store(float uxx, float uxy, float uyy, f
                                               float *__restrict__ No, size_t o, size_t plane)
 {
 #pragma clang fp contract(off)   // fused multiply-adds are written out
+    // The hardware square root, reciprocal, reciprocal square root and 2^x
+    // (about 1 ulp each) replace the correctly rounded library sequences.
+    constexpr float kLog2e = 1.4426950408889634f;
     // scale-normalised Hessian sigma^2 H; eigenvalues m +- r
     const float hxx = sigma2 * uxx, hxy = sigma2 * uxy, hyy = sigma2 * uyy;
     const float m = 0.5f * (hxx + hyy);
     const float hd = 0.5f * (hxx - hyy);
-    const float r = sqrtf(fmaf(hd, hd, hxy * hxy));
-    const float Sv = sqrtf(fmaf(2.f * hxy, hxy, fmaf(hxx, hxx, hyy * hyy)));   // sqrt(nu~1^2 + nu~2^2)
+    const float r = __builtin_amdgcn_sqrtf(fmaf(hd, hd, hxy * hxy));
+    const float Sv = __builtin_amdgcn_sqrtf(fmaf(2.f * hxy, hxy, fmaf(hxx, hxx, hyy * hyy)));   // sqrt(nu~1^2 + nu~2^2)
     // |nu~2| = |m| + r carries the sign of m (a zero trace passes the test)
     const float am = fabsf(m);
     const float big = am + r;
     bool pass = big > 0.f;
     if (MODE == MF4D_RIDGE) pass = pass && !(m > 0.f);
     if (MODE == MF4D_VALLEY) pass = pass && !(m < 0.f);
-    float blob = 0.f;
-    if (pass) {
-        const float rb = (am - r) / big;   // |R_B| = |nu~1| / |nu~2|
-        blob = expf(-(rb * rb) * inv2beta2);
-    }
+    const float rb = (am - r) * __builtin_amdgcn_rcpf(big);   // |R_B| = |nu~1| / |nu~2|
+    const float e = __builtin_amdgcn_exp2f(-(rb * rb) * inv2beta2 * kLog2e);
+    const float blob = pass ? e : 0.f;
     So[o] = Sv;
     Ao[o] = blob;
     if (No) {
-        const float f = 1.f / sqrtf(1.f + sqrtf(fmaf(gx, gx, gy * gy)));
+        const float f = __builtin_amdgcn_rsqf(1.f + __builtin_amdgcn_sqrtf(fmaf(gx, gx, gy * gy)));
         No[o] = uxx * f;
         No[plane + o] = uxy * f;
         No[2 * plane + o] = uyy * f;

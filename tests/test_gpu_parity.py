@@ -184,14 +184,14 @@ def test_scale_select_degenerate(env):
 
 # ------------------------------------------------------------------ sweep engines
 # Scales whose radii span the matrix-core passes (2, 3, 5 and 8 chunks of 16
-# inputs) and the register-window passes (radius 64). "default" is the
-# library's own choice per pass; "mfma_all" puts every vertical pass within
-# the matrix-core tiles' reach on them, and "mfma_ring" also makes it stream
-# several 32-row steps through its LDS ring per workgroup; "valu" forces the
+# inputs) and the register-window passes (radius 64). "default" runs both
+# passes of a scale in one fused matrix-core kernel; "split" runs them as
+# two matrix-core kernels; the "_ring" forms make each workgroup stream
+# several 32-row steps through its LDS ring; "valu" forces the
 # register-window passes for every scale.
 LARGE_SIG = [1.0, 4.0, 10.0, 16.0, 21.3]
-ENGINES = {"default": {}, "mfma_all": {"MF4D_SWEEP": "mfma"},
-           "mfma_ring": {"MF4D_SWEEP": "mfma", "MF4D_VSEG_ROWS": "96"}, "valu": {"MF4D_SWEEP": "valu"}}
+ENGINES = {"default": {}, "fused_ring": {"MF4D_VSEG_ROWS": "96"}, "split": {"MF4D_SWEEP": "split"},
+           "split_ring": {"MF4D_SWEEP": "split", "MF4D_VSEG_ROWS": "96"}, "valu": {"MF4D_SWEEP": "valu"}}
 
 
 def _large_image(env, H=190, W=300, seed=11):
@@ -227,19 +227,22 @@ def test_scale_select_large_scales(env, engine, mode, monkeypatch):
 
 
 def test_sweep_segmentation_changes_no_value(env, monkeypatch):
-    """The matrix-core vertical pass gives the same bits for any number of
-    32-row steps per workgroup."""
-    monkeypatch.setenv("MF4D_SWEEP", "mfma")
+    """The fused kernel equals the two separate matrix-core passes bit for
+    bit, and neither changes any bit with the number of 32-row steps per
+    workgroup."""
     u = _large_image(env, 260, 200, seed=5)
     p = env["m"].Params(LARGE_SIG[:4], mode=2)
     base = _gpu_select(env, u, p)
-    for rows in ("32", "64", "160", "4096"):
-        monkeypatch.setenv("MF4D_VSEG_ROWS", rows)
-        got = _gpu_select(env, u, p)
-        assert np.array_equal(got[0], base[0]) and np.array_equal(got[1], base[1]) and got[2] == base[2], rows
+    for engine in ("", "split"):
+        for rows in ("", "32", "64", "160", "4096"):
+            monkeypatch.setenv("MF4D_SWEEP", engine)
+            monkeypatch.setenv("MF4D_VSEG_ROWS", rows)
+            got = _gpu_select(env, u, p)
+            assert np.array_equal(got[0], base[0]) and np.array_equal(got[1], base[1]) and got[2] == base[2], \
+                (engine, rows)
 
 
-@pytest.mark.parametrize("engine", ["default", "mfma_all", "valu"])
+@pytest.mark.parametrize("engine", ["default", "split", "valu"])
 def test_filter_parity_large_scales(env, engine, monkeypatch):
     for k, v in ENGINES[engine].items():
         monkeypatch.setenv(k, v)
