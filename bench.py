@@ -8,9 +8,13 @@ with the input already resident in HBM.
 
 Prints one JSON line:
   value     Mpixel-FED-substeps/s of the whole filter (H W M n per step / time)
-  roofline  the fused FED substep kernel: algorithmic bytes per launch
-            (20 B/px: u read 4, H_rho read 12, u write 4) / its average launch
-            time, timed with HIP events on the stream it is launched on
+  roofline  the fused FED substep kernel: algorithmic flops and bytes per launch
+            (37 flop/px per substep; 20 B/px per launch: u read 4, tensor
+            planes read 12, u write 4) / its average launch time, timed with
+            HIP events on the stream it is launched on
+  roofline_sweep  the fused scale-sweep kernel at sigma = 16 (both separable
+            passes of one scale on the matrix cores): algorithmic flops
+            (8 filters x 99 taps x 2 per pixel) against the FP32 MFMA peak
   cpu_baseline  the FP64 oracle on a bounded sample (one cycle of the same image)
 """
 from __future__ import annotations
@@ -27,34 +31,52 @@ sys.path.insert(0, ROOT)
 HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
 # FP32 vector peak without packed FP32: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 VALU_PEAK = 78.6e12        # FLOP/s
+MFMA_F32_PEAK = 157.3e12   # FLOP/s, dense FP32 matrix cores
 SUBSTEP_BYTES_PER_PX = 20  # per launch: u in 4 + tensor planes in 12 + u out 4
 SUBSTEP_FLOPS_PER_PX = 37  # per substep: L u 10, D L u 13, L^T and update 14
 SUBSTEPS_PER_LAUNCH = 4    # as mf4d_filter launches the fused substep kernel
 
 
-def counter_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, calibrated on a plain copy),
-    or None if the kernel source changed since the counters were taken."""
+CSRC = os.path.join(ROOT, "paper_1611_06906_amd", "csrc")
+# sources whose change invalidates a kernel's committed counter figures
+KERNEL_SOURCES = {
+    "fed_stream_kernel<4>": ["fed_kernels.hip", "fed_tiles.h", "mf4d_internal.h", "../build.py"],
+    "sweep_fused_kernel<8>": ["scale_kernels.hip", "scale_mfma.h", "scale_tiles.h", "mf4d_internal.h", "../build.py"],
+}
+
+
+def source_digest(kernel):
+    """sha256 prefix over the sources of `kernel` (in KERNEL_SOURCES order)."""
     import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel, row=None):
+    """HBM bytes per launch of `kernel` (its summary row `row`, default the
+    kernel itself) from the committed rocprofv3 counter summary
+    (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, calibrated on a plain copy), or
+    None if the kernel's sources changed since the counters were taken."""
     prof = os.path.join(ROOT, "profiles", "creases4096_hbm_counters.txt")
-    src = os.path.join(ROOT, "paper_1611_06906_amd", "csrc", "fed_kernels.hip")
     try:
         text = open(prof).read()
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    except OSError:
+        digest = source_digest(kernel)
+    except (OSError, KeyError):
         return None
-    if f"sha256 prefix: {digest}" not in text:
+    if f"{kernel} sources sha256 prefix: {digest}" not in text:
         return None
+    row = row or kernel
     for line in text.splitlines():
-        if line.startswith(kernel + " ") or line.startswith("void " + kernel + " "):
-            cols = line.split()
-            try:
-                i = cols.index(next(c for c in cols if c.replace(".", "").isdigit() and "." in c))
-                read_mb, write_mb = float(cols[i + 2]), float(cols[i + 3])
-            except (StopIteration, ValueError, IndexError):
-                return None
-            return (read_mb + write_mb) * 1e6
+        if "sha256" in line or not (line.startswith(row + " ") or line.startswith("void " + row + " ")):
+            continue
+        cols = line.split()
+        nums = [c for c in cols if c.replace(".", "", 1).isdigit()]
+        try:   # n, FETCH_KiB, WRITE_KiB, read_MB, write_MB, ...
+            return (float(nums[3]) + float(nums[4])) * 1e6
+        except (IndexError, ValueError):
+            return None
     return None
 
 
@@ -322,6 +344,26 @@ def main():
                        "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": SUBSTEP_BYTES_PER_PX * m / t1 / HBM_PEAK,
                        "us_per_launch": t1 * 1e6}
 
+    # the fused sweep kernel at the largest scale, sigma = 16 (radius 48, 8
+    # chunks of 16 inputs): a one-scale selection is that kernel plus a
+    # per-pixel argmax over one scale (S, blob read; index written), so the
+    # rate below is a lower bound on the kernel's own
+    p16 = mf4d.Params([16.0], mode=w.mode, lam=w.lam, rho=w.rho, beta=w.beta)
+    sel16 = lambda: mf4d.mf4d_scale_select(u_in, p16, idx, None, None, ws)
+    sel16()
+    t16 = time_stream(torch, sel16, reps) * 1e-3
+    R16 = 49                                  # ceil(3 sigma) + 1: support of the difference taps
+    sweep_flops_px = 8 * (2 * R16 + 1) * 2    # 3 horizontal + 5 vertical filters
+    mfma_flops_px = 8 * 128 * 2               # the banded Toeplitz products as issued (K = 128)
+    roofline_sweep = {"bound": "mfma", "kernel": "sweep_fused_kernel<8> (both passes of sigma = 16) + one-scale argmax",
+                      "achieved": sweep_flops_px * m / t16 / 1e12, "peak": MFMA_F32_PEAK / 1e12, "unit": "TFLOP/s",
+                      "frac": sweep_flops_px * m / t16 / MFMA_F32_PEAK,
+                      "traffic": counter_traffic("sweep_fused_kernel<8>", "sweep_fused_kernel<8> [select]"),
+                      "us_per_launch": t16 * 1e6, "flops_per_px": sweep_flops_px,
+                      "mfma_issued_TFLOPs": mfma_flops_px * m / t16 / 1e12,
+                      # a selection does not form N: u read 4, S and blob written 8
+                      "hbm_bytes_per_px": 12, "hbm_achieved_GBs": 12 * m / t16 / 1e9}
+
     # a one-substep cycle from H_rho: that substep plus the plain copy of H*W
     # floats back into u (4 B read + 4 B write per pixel), the reference for
     # HBM counters
@@ -375,6 +417,7 @@ def main():
                    "nscales": len(w.sigmas), "mode": "both", "path": "plain"},
         "roofline": roofline,
         "roofline_single_substep": roofline_single,
+        "roofline_sweep": roofline_sweep,
         "cpu_baseline": cpu,
         "stages": stages,
         "extensions": extensions,
