@@ -210,7 +210,7 @@ __global__ __launch_bounds__(256) void batch_rho_kernel(const BImg *imgs, const 
                       (lt / tx) * kBTH);
 }
 
-template <int S>
+template <int S, int C>
 __global__ __launch_bounds__(256) void batch_stream_kernel(const BImg *imgs, const int *pre, int nact, FedTaus taus,
                                                            int j, int per_xcd)
 {
@@ -222,7 +222,30 @@ __global__ __launch_bounds__(256) void batch_stream_kernel(const BImg *imgs, con
     const int wave = (b - pre[i]) * 4 + (threadIdx.x >> 6);
     const int strip = wave % im.strips[S], seg = wave / im.strips[S];
     if (seg >= im.segs[S]) return;
-    fed_stream_wave<S>(state_src(im, j), state_dst(im, j), im.tens, im.H, im.W, taus, strip, seg, im.seg_rows[S]);
+    if (C == 2)
+        fed_stream_wave2<S>(state_src(im, j), state_dst(im, j), im.tens, im.H, im.W, taus, strip, seg,
+                            im.seg_rows[S]);
+    else
+        fed_stream_wave<S>(state_src(im, j), state_dst(im, j), im.tens, im.H, im.W, taus, strip, seg,
+                           im.seg_rows[S]);
+}
+
+void launch_batch_stream(int cols, int steps, dim3 grid, hipStream_t s, const BImg *imgs, const int *pt, int nact,
+                         const FedTaus &ft, int j, int per)
+{
+#define MF4D_BS(K)                                                                                            \
+    case K:                                                                                                   \
+        if (cols == 2)                                                                                        \
+            hipLaunchKernelGGL((batch_stream_kernel<K, 2>), grid, dim3(256), 0, s, imgs, pt, nact, ft, j, per);  \
+        else                                                                                                  \
+            hipLaunchKernelGGL((batch_stream_kernel<K, 1>), grid, dim3(256), 0, s, imgs, pt, nact, ft, j, per);  \
+        break;
+    switch (steps) {
+        MF4D_BS(1) MF4D_BS(2) MF4D_BS(3)
+    default:
+        MF4D_BS(4)
+    }
+#undef MF4D_BS
 }
 
 }  // namespace
@@ -251,6 +274,7 @@ struct mf4d_batch {
     int n = 0, max_cycles = 0;
     std::vector<float> tau32;
     int spl = 4;                     // substeps per launch
+    int cols = 2;                    // columns per lane of the streaming kernel (fixed at table build)
     int rows[5] = {0, 0, 0, 0, 0};   // rows per wave (0: default)
     size_t table_bytes = 0, ws_total = 0;
     std::vector<size_t> img_ws;      // per image (sorted order) workspace offset
@@ -309,7 +333,7 @@ void build_tables(mf4d_batch *b, const float *in, float *out, char *ws, std::vec
         im.copy_out = (L == 0 && im.user_in != im.out) ? 1 : 0;
         im.in = im.copy_in ? im.tmp : im.user_in;
         for (int s = 1; s <= 4; ++s) {
-            const int outw = 64 - 4 * s;
+            const int outw = 64 * b->cols - 4 * s;
             im.strips[s] = (W + outw - 1) / outw;
             im.seg_rows[s] = rows_for(b, H, W, s);
             im.segs[s] = (H + im.seg_rows[s] - 1) / im.seg_rows[s];
@@ -437,12 +461,7 @@ int enqueue_batch(mf4d_batch *b, char *ws, const std::vector<int> pre[PT_COUNT],
             const int total = pre[PT_ST1 + steps - 1][nact];
             const int per = (total + 7) / 8;
             const int *pt = P(PT_ST1 + steps - 1);
-            switch (steps) {
-            case 1: hipLaunchKernelGGL(batch_stream_kernel<1>, dim3(8 * per), dim3(256), 0, s, imgs, pt, nact, ft, j, per); break;
-            case 2: hipLaunchKernelGGL(batch_stream_kernel<2>, dim3(8 * per), dim3(256), 0, s, imgs, pt, nact, ft, j, per); break;
-            case 3: hipLaunchKernelGGL(batch_stream_kernel<3>, dim3(8 * per), dim3(256), 0, s, imgs, pt, nact, ft, j, per); break;
-            default: hipLaunchKernelGGL(batch_stream_kernel<4>, dim3(8 * per), dim3(256), 0, s, imgs, pt, nact, ft, j, per); break;
-            }
+            launch_batch_stream(b->cols, steps, dim3(8 * per), s, imgs, pt, nact, ft, j, per);
             BCHECK(hipGetLastError());
             i0 += steps;
             ++j;
@@ -524,6 +543,7 @@ int mf4d_batch_create(int nimg, const int64_t *offsets, const int *H, const int 
         b->cycles.push_back(per_image[i].cycles);
     }
     b->shared = per_image[0];
+    b->cols = stream_cols_per_lane();
     b->sigmas.assign(per_image[0].sigmas, per_image[0].sigmas + per_image[0].nscales);
     b->shared.sigmas = b->sigmas.data();
     b->max_cycles = *std::max_element(b->cycles.begin(), b->cycles.end());
@@ -634,12 +654,7 @@ int mf4d_batch_autotune(mf4d_batch *plan, void *ws, size_t ws_bytes, void *strea
             FedTaus ft{};
             for (int q = 0; q < steps; ++q) ft.t[q] = plan->tau32[q];
             auto launch = [&](int j) {
-                switch (steps) {
-                case 1: hipLaunchKernelGGL(batch_stream_kernel<1>, dim3(8 * per), dim3(256), 0, s, (const BImg *)w, pt, N, ft, j, per); break;
-                case 2: hipLaunchKernelGGL(batch_stream_kernel<2>, dim3(8 * per), dim3(256), 0, s, (const BImg *)w, pt, N, ft, j, per); break;
-                case 3: hipLaunchKernelGGL(batch_stream_kernel<3>, dim3(8 * per), dim3(256), 0, s, (const BImg *)w, pt, N, ft, j, per); break;
-                default: hipLaunchKernelGGL(batch_stream_kernel<4>, dim3(8 * per), dim3(256), 0, s, (const BImg *)w, pt, N, ft, j, per); break;
-                }
+                launch_batch_stream(plan->cols, steps, dim3(8 * per), s, (const BImg *)w, pt, N, ft, j, per);
             };
             launch(1);
             launch(2);

@@ -18,6 +18,8 @@
 //    neighbouring tiles with the same operations in the same order.
 #include "mf4d_internal.h"
 #include "tensor_math.h"
+#include <cstdlib>
+
 #include "fed_tiles.h"
 
 namespace mf4d {
@@ -249,6 +251,22 @@ __global__ __launch_bounds__(256) void fed_stream_kernel(const float *__restrict
     tiles::fed_stream_wave<S>(u, uo, coef, H, W, taus, strip, seg, seg_rows);
 }
 
+
+template <int S>
+__global__ __launch_bounds__(256) void fed_stream2_kernel(const float *__restrict__ u, float *__restrict__ uo,
+                                                          const float *__restrict__ coef, int H, int W,
+                                                          FedTaus taus, int strips, int segs, int seg_rows,
+                                                          int blocks_per_xcd, int nblocks)
+{
+    // XCD-aware: each XCD takes a contiguous run of blocks
+    const int blk = (blockIdx.x % 8) * blocks_per_xcd + blockIdx.x / 8;
+    if (blk >= nblocks) return;
+    const int wave = blk * 4 + (threadIdx.x >> 6);
+    const int strip = wave % strips, seg = wave / strips;
+    if (seg >= segs) return;
+    tiles::fed_stream_wave2<S>(u, uo, coef, H, W, taus, strip, seg, seg_rows);
+}
+
 }  // namespace
 
 hipError_t launch_fed_substep(const float *u_in, float *u_out, const float *hrho, int H, int W,
@@ -275,37 +293,68 @@ hipError_t launch_fed_substep(const float *u_in, float *u_out, const float *hrho
     return hipGetLastError();
 }
 
+// Blocks of the streaming kernel (for the current form and `steps`) that
+// one CU holds at once, and the device's CU count (cached per device).
+int stream_blocks_per_cu(int steps, int *cus)
+{
+    static int cache[16][3][5];   // [device][cols][steps]: 0 = not yet asked
+    static int ncu[16];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) dev = 0;
+    const int cols = stream_cols_per_lane();
+    if (steps < 1 || steps > 4) steps = 4;
+    if (!ncu[dev] && hipDeviceGetAttribute(&ncu[dev], hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        ncu[dev] = 256;
+    int &c = cache[dev][cols][steps];
+    if (!c) {
+        int nb = 0;
+        const void *fn = nullptr;
+        switch (steps) {
+        case 1: fn = cols == 2 ? (const void *)fed_stream2_kernel<1> : (const void *)fed_stream_kernel<1>; break;
+        case 2: fn = cols == 2 ? (const void *)fed_stream2_kernel<2> : (const void *)fed_stream_kernel<2>; break;
+        case 3: fn = cols == 2 ? (const void *)fed_stream2_kernel<3> : (const void *)fed_stream_kernel<3>; break;
+        default: fn = cols == 2 ? (const void *)fed_stream2_kernel<4> : (const void *)fed_stream_kernel<4>; break;
+        }
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, 0) != hipSuccess || nb < 1) nb = 1;
+        c = nb;
+    }
+    *cus = ncu[dev];
+    return c;
+}
+
+int stream_cols_per_lane()
+{
+    const char *e = std::getenv("MF4D_STREAM_COLS");
+    return (e && std::atoi(e) == 1) ? 1 : 2;
+}
+
 hipError_t launch_fed_stream(const float *u_in, float *u_out, const float *coef, int H, int W, int steps,
                              const float *taus, int seg_rows, hipStream_t s)
 {
     FedTaus t{};
     for (int k = 0; k < steps; ++k) t.t[k] = taus[k];
-    const int outw = 64 - 4 * steps;
+    const int cols = stream_cols_per_lane();
+    const int outw = 64 * cols - 4 * steps;
     const int strips = (W + outw - 1) / outw;
     const int segs = (H + seg_rows - 1) / seg_rows;
     const int nblocks = (strips * segs + 3) / 4;
     const int per = (nblocks + 7) / 8;
     dim3 grid(8 * per), block(256);
+#define MF4D_ST(K)                                                                                            \
+    case K:                                                                                                   \
+        if (cols == 2)                                                                                        \
+            hipLaunchKernelGGL(fed_stream2_kernel<K>, grid, block, 0, s, u_in, u_out, coef, H, W, t, strips, segs, \
+                               seg_rows, per, nblocks);                                                       \
+        else                                                                                                  \
+            hipLaunchKernelGGL(fed_stream_kernel<K>, grid, block, 0, s, u_in, u_out, coef, H, W, t, strips, segs,  \
+                               seg_rows, per, nblocks);                                                       \
+        break;
     switch (steps) {
-    case 1:
-        hipLaunchKernelGGL(fed_stream_kernel<1>, grid, block, 0, s, u_in, u_out, coef, H, W, t, strips, segs,
-                           seg_rows, per, nblocks);
-        break;
-    case 2:
-        hipLaunchKernelGGL(fed_stream_kernel<2>, grid, block, 0, s, u_in, u_out, coef, H, W, t, strips, segs,
-                           seg_rows, per, nblocks);
-        break;
-    case 3:
-        hipLaunchKernelGGL(fed_stream_kernel<3>, grid, block, 0, s, u_in, u_out, coef, H, W, t, strips, segs,
-                           seg_rows, per, nblocks);
-        break;
-    case 4:
-        hipLaunchKernelGGL(fed_stream_kernel<4>, grid, block, 0, s, u_in, u_out, coef, H, W, t, strips, segs,
-                           seg_rows, per, nblocks);
-        break;
+        MF4D_ST(1) MF4D_ST(2) MF4D_ST(3) MF4D_ST(4)
     default:
         return hipErrorInvalidValue;
     }
+#undef MF4D_ST
     return hipGetLastError();
 }
 

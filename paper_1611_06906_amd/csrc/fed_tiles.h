@@ -140,5 +140,154 @@ __device__ __forceinline__ void fed_stream_wave(const float *__restrict__ u, flo
     }
 }
 
+
+// fed_stream_wave2<S>: the same S substeps with two adjacent columns per
+// lane (lane l owns columns 2l and 2l+1 of a 128-column strip), so a wave
+// owns 128 - 4 S output columns. Each column's neighbour inside the lane is
+// a register; only the outer neighbours cross lanes, which halves the lane
+// shifts per pixel and the share of halo columns. Every column runs the
+// arithmetic of fed_stream_wave in the same order, so both forms give the
+// same values bit for bit.
+template <int S>
+__device__ __forceinline__ void fed_stream_wave2(const float *__restrict__ u, float *__restrict__ uo,
+                                                 const float *__restrict__ coef, int H, int W,
+                                                 const FedTaus &taus, int strip, int seg, int seg_rows)
+{
+#pragma clang fp contract(off)   // fused multiply-adds are written out: every launch shape rounds alike
+    constexpr int HALO = 2 * S;                           // columns
+    constexpr int OUTW = 128 - 2 * HALO;
+    constexpr int D = 4;                                  // rows loaded ahead
+    constexpr int NC = 2 * S;                             // tensor rows kept
+    constexpr int U = 24;                                 // unroll: multiple of 3, NC and D
+    const int lane = threadIdx.x & 63;
+    const int xa = strip * OUTW - HALO + 2 * lane, xb = xa + 1;
+    const int ys = seg * seg_rows;
+    const int ye = min(ys + seg_rows, H);
+    const bool ina = xa >= 0 && xa < W, inb = xb >= 0 && xb < W;
+    const bool inta = xa >= 1 && xa <= W - 2, intb = xb >= 1 && xb <= W - 2;
+    const bool own = lane >= S && lane < 64 - S;          // both columns are outputs of this strip
+    const bool sta = own && xa < W, stb = own && xb < W;
+    const size_t plane = (size_t)H * W;
+    const int xca = min(max(xa, 0), W - 1), xcb = min(max(xb, 0), W - 1);
+
+    // u_k rows, k < S: column a, its left neighbour, column b, its right neighbour
+    float ua[S][3], ual[S][3], ub[S][3], ubr[S][3];
+    float txa[S][3], tya[S][3], tza[S][3];   // T_k rows (xx, xy, yy), column a
+    float txb[S][3], tyb[S][3], tzb[S][3];   // column b
+    float cma[NC], caa[NC], cba[NC], cmb[NC], cab[NC], cbb[NC];
+    float qa0[D], qa1[D], qa2[D], qa3[D], qb0[D], qb1[D], qb2[D], qb3[D];   // rows in flight
+#pragma unroll
+    for (int k = 0; k < S; ++k)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            ua[k][j] = ual[k][j] = ub[k][j] = ubr[k][j] = 0.f;
+            txa[k][j] = tya[k][j] = tza[k][j] = txb[k][j] = tyb[k][j] = tzb[k][j] = 0.f;
+        }
+#pragma unroll
+    for (int j = 0; j < NC; ++j) cma[j] = caa[j] = cba[j] = cmb[j] = cab[j] = cbb[j] = 0.f;
+
+    const int y0 = ys - 2 * S;          // first row loaded
+    const int y1 = ye + 2 * S;          // one past the last row needed
+    auto issue = [&](int y, int d) {
+        const size_t r = (size_t)min(max(y, 0), H - 1) * W;
+        const size_t oa = r + xca, ob = r + xcb;
+        qa0[d] = u[oa];
+        qb0[d] = u[ob];
+        qa1[d] = coef[oa];
+        qb1[d] = coef[ob];
+        qa2[d] = coef[plane + oa];
+        qb2[d] = coef[plane + ob];
+        qa3[d] = coef[2 * plane + oa];
+        qb3[d] = coef[2 * plane + ob];
+    };
+#pragma unroll
+    for (int d = 0; d < D; ++d) issue(y0 + d, d);
+
+    // flux of one column from its u_{k-1} rows (left, centre, right) and tensor
+    auto flux = [&](float lo, float co, float ro, float ln, float cn, float rn, float lc, float cc, float rc,
+                    float mb, float al, float be, bool on, float &txx, float &txy, float &tyy) {
+#pragma clang fp contract(off)
+        const float hxx = fmaf(-2.f, cc, lc + rc);
+        const float hyy = fmaf(-2.f, cc, co + cn);
+        const float hxy = 0.25f * ((lo + rn) - (ln + ro));
+        const float bxy = be * hxy;
+        txx = on ? fmaf(mb + al, hxx, bxy) : 0.f;
+        txy = on ? fmaf(mb, hxy, (be * 0.5f) * (hxx + hyy)) : 0.f;
+        tyy = on ? fmaf(mb - al, hyy, bxy) : 0.f;
+    };
+
+    for (int yb = y0; yb < y1; yb += U) {
+#pragma unroll
+        for (int t = 0; t < U; ++t) {
+            const int y = yb + t;
+            const int qs = t % D;
+            const bool yin = y >= 0 && y < H;
+            const float na = (ina && yin) ? qa0[qs] : 0.f;
+            const float nb = (inb && yin) ? qb0[qs] : 0.f;
+            cma[t % NC] = qa1[qs];
+            cmb[t % NC] = qb1[qs];
+            caa[t % NC] = qa2[qs];
+            cab[t % NC] = qb2[qs];
+            cba[t % NC] = qa3[qs];
+            cbb[t % NC] = qb3[qs];
+            issue(y + D, qs);
+            {
+                const int w0 = t % 3;
+                ua[0][w0] = na;
+                ub[0][w0] = nb;
+                ual[0][w0] = from_left(nb);
+                ubr[0][w0] = from_right(na);
+            }
+#pragma unroll
+            for (int k = 1; k <= S; ++k) {
+                const int q = y - (2 * k - 1);
+                const int wn = (t - 2 * (k - 1) + 300) % 3;        // u_{k-1} row q+1
+                const int wc = (t - 2 * (k - 1) - 1 + 300) % 3;    // row q
+                const int wo = (t - 2 * (k - 1) - 2 + 300) % 3;    // row q-1
+                const int ci = (t - (2 * k - 1) + 2 * NC * 50) % NC;
+                const bool qin = q >= 1 && q <= H - 2;
+                const int tw = (t - (2 * k - 1) + 300) % 3;
+                // column a: left neighbour ual, right neighbour ub; column b: left ua, right ubr
+                flux(ual[k - 1][wo], ua[k - 1][wo], ub[k - 1][wo], ual[k - 1][wn], ua[k - 1][wn], ub[k - 1][wn],
+                     ual[k - 1][wc], ua[k - 1][wc], ub[k - 1][wc], cma[ci], caa[ci], cba[ci], inta && qin,
+                     txa[k - 1][tw], tya[k - 1][tw], tza[k - 1][tw]);
+                flux(ua[k - 1][wo], ub[k - 1][wo], ubr[k - 1][wo], ua[k - 1][wn], ub[k - 1][wn], ubr[k - 1][wn],
+                     ua[k - 1][wc], ub[k - 1][wc], ubr[k - 1][wc], cmb[ci], cab[ci], cbb[ci], intb && qin,
+                     txb[k - 1][tw], tyb[k - 1][tw], tzb[k - 1][tw]);
+                // u_k at row p = y - 2k
+                const int p = y - 2 * k;
+                const int sn = tw;
+                const int sc = (t - 2 * k + 300) % 3;
+                const int so = (t - 2 * k - 1 + 300) % 3;
+                const float dxa = tya[k - 1][so] - tya[k - 1][sn];
+                const float dxb = tyb[k - 1][so] - tyb[k - 1][sn];
+                const float ela = fmaf(0.5f, dxa, txa[k - 1][sc]);
+                const float era = fmaf(-0.5f, dxa, txa[k - 1][sc]);
+                const float elb = fmaf(0.5f, dxb, txb[k - 1][sc]);
+                const float erb = fmaf(-0.5f, dxb, txb[k - 1][sc]);
+                // column a: el at x-1 is column b of the lane to the left, er at x+1 is column b
+                const float rxa = fmaf(-2.f, txa[k - 1][sc], from_left(elb) + erb);
+                const float rxb = fmaf(-2.f, txb[k - 1][sc], ela + from_right(era));
+                const float rya = fmaf(-2.f, tza[k - 1][sc], tza[k - 1][so] + tza[k - 1][sn]);
+                const float ryb = fmaf(-2.f, tzb[k - 1][sc], tzb[k - 1][so] + tzb[k - 1][sn]);
+                const float ra = rxa + rya, rb = rxb + ryb;
+                const int wp = (t - 2 * k + 300) % 3;
+                const float nva = fmaf(-taus.t[k - 1], ra, ua[k - 1][wp]);
+                const float nvb = fmaf(-taus.t[k - 1], rb, ub[k - 1][wp]);
+                if (k < S) {
+                    ua[k][wp] = nva;
+                    ub[k][wp] = nvb;
+                    ual[k][wp] = from_left(nvb);
+                    ubr[k][wp] = from_right(nva);
+                } else if (p >= ys && p < ye) {
+                    const size_t r = (size_t)p * W;
+                    if (sta) uo[r + xa] = nva;
+                    if (stb) uo[r + xb] = nvb;
+                }
+            }
+        }
+    }
+}
+
 }  // namespace tiles
 }  // namespace mf4d

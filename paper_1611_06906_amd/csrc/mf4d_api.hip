@@ -205,17 +205,22 @@ int hip_status(hipError_t e) { return e == hipSuccess ? MF4D_OK : MF4D_EHIP; }
 // MF4D_STREAM_ROWS overrides (tuning).
 int stream_rows(int H, int W, int steps)
 {
-    static const int env = [] {
-        const char *e = std::getenv("MF4D_STREAM_ROWS");
-        return e ? std::atoi(e) : 0;
-    }();
+    const char *e = std::getenv("MF4D_STREAM_ROWS");
+    const int env = e ? std::atoi(e) : 0;
     if (env > 0) return env;
-    const int outw = 64 - 4 * steps;
+    // the longest segments (least row halo) whose waves still fit in one
+    // round of resident blocks (with some slack, as blocks do not spread
+    // perfectly evenly over the CUs); a partial second round would idle most
+    // of the chip
+    int cus = 256;
+    const int per_cu = stream_blocks_per_cu(steps, &cus);
+    const int cols = stream_cols_per_lane();
+    const int outw = 64 * cols - 4 * steps;
     const long long strips = (W + outw - 1) / outw;
-    const int target = steps >= 3 ? 96 : 160;
-    long long segs = (4096 + strips - 1) / strips;
+    const long long waves = (4LL * per_cu * cus * 23) / 25;
+    long long segs = waves / strips;
+    if (segs < 1) segs = 1;
     int rows = (int)((H + segs - 1) / segs);
-    if (rows > target) rows = target;
     return rows < 16 ? 16 : rows;
 }
 

@@ -109,7 +109,11 @@ hipError_t launch_fed_coef(const float *u_in, float *u_out, const float *coef, i
                            float tau0, float tau1, hipStream_t s);
 
 // `steps` (1..4) consecutive substeps with taus[0..steps-1], one wave per
-// 64 - 4 steps columns x seg_rows rows, intermediate images in registers.
+// 64 c - 4 steps columns x seg_rows rows (c = stream_cols_per_lane()),
+// intermediate images in registers.
+int stream_cols_per_lane();   // 2, or 1 with MF4D_STREAM_COLS=1 (same values)
+// Resident blocks per CU of that kernel for `steps`, and the CU count.
+int stream_blocks_per_cu(int steps, int *cus);
 hipError_t launch_fed_stream(const float *u_in, float *u_out, const float *coef, int H, int W, int steps,
                              const float *taus, int seg_rows, hipStream_t s);
 

@@ -413,3 +413,35 @@ def test_fed_cycle_tensor_parity(env, mode, shape):
             e, r = _err(outs[-1], ref)
             assert e <= MAXABS and r <= RELL2, (shape, mode, n, spl, e, r)
         assert np.array_equal(outs[0], outs[1])   # temporal blocking changes no value
+
+
+@pytest.mark.parametrize("shape", [(67, 131), (130, 70), (5, 200), (3, 3), (300, 257)])
+def test_stream_forms_bitwise(env, shape, monkeypatch):
+    """The streaming substep kernel with two columns per lane equals the
+    one-column form bit for bit, for 1-4 substeps per launch and any
+    number of rows per wave."""
+    o, m, torch, synth = env["o"], env["m"], env["torch"], env["synth"]
+    H, W = shape
+    _log(f"stream forms {shape}")
+    u = synth.creases(H, W, 3, seed=H + W)
+    sig = [1.0, 2.0]
+    idx = o.scale_select(u, sig, 2)["idx"]
+    p = m.Params(sig, mode=2)
+    hr = torch.empty((3, H, W), dtype=torch.float32, device=env["dev"])
+    dp = torch.empty_like(hr)
+    m.mf4d_tensor(_to(env, u), _to(env, idx), p, hr, dp)
+    taus, _, _ = m.mf4d_fed_schedule(20, 0.05)
+    outs = {}
+    for cols in ("1", "2"):
+        for rows in ("", "16", "40"):
+            for spl in (1, 2, 3, 4):
+                monkeypatch.setenv("MF4D_STREAM_COLS", cols)
+                monkeypatch.setenv("MF4D_STREAM_ROWS", rows)
+                ug = _to(env, u)
+                tmp = torch.empty_like(ug)
+                m.mf4d_fed_cycle_tensor(ug, tmp, dp, taus, spl)
+                torch.cuda.synchronize()
+                outs[(cols, rows, spl)] = ug.cpu().numpy()
+    ref = outs[("1", "", 1)]
+    for k, v in outs.items():
+        assert np.array_equal(v, ref), k
