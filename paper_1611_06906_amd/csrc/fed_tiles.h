@@ -43,7 +43,7 @@ __device__ __forceinline__ void fed_stream_wave(const float *__restrict__ u, flo
     constexpr int OUTW = 64 - 2 * HALO;
     constexpr int D = 8;                                  // rows loaded ahead
     constexpr int NC = 2 * S;                             // tensor rows kept
-    constexpr int U = 24;                                 // unroll: multiple of 3, NC and D
+    constexpr int U = kStreamUnroll;                      // unroll: multiple of 3, NC and D
     const int lane = threadIdx.x & 63;
     const int x = strip * OUTW - HALO + lane;
     const int ys = seg * seg_rows;
@@ -158,7 +158,7 @@ __device__ __forceinline__ void fed_stream_wave2(const float *__restrict__ u, fl
     constexpr int OUTW = 128 - 2 * HALO;
     constexpr int D = 4;                                  // rows loaded ahead
     constexpr int NC = 2 * S;                             // tensor rows kept
-    constexpr int U = 24;                                 // unroll: multiple of 3, NC and D
+    constexpr int U = kStreamUnroll;                      // unroll: multiple of 3, NC and D
     const int lane = threadIdx.x & 63;
     const int xa = strip * OUTW - HALO + 2 * lane, xb = xa + 1;
     const int ys = seg * seg_rows;

@@ -221,7 +221,14 @@ int stream_rows(int H, int W, int steps)
     long long segs = waves / strips;
     if (segs < 1) segs = 1;
     int rows = (int)((H + segs - 1) / segs);
-    return rows < 16 ? 16 : rows;
+    // a wave walks rows + 4 steps rows in blocks of kStreamUnroll; a partial
+    // last block is computed in full, so round to whole blocks: down, unless
+    // that would overflow one round of resident blocks
+    const int halo = 4 * steps;
+    int r = ((rows + halo) / kStreamUnroll) * kStreamUnroll - halo;
+    if (r < 16 || strips * ((H + r - 1) / r) > 4LL * per_cu * cus)
+        r = ((rows + halo + kStreamUnroll - 1) / kStreamUnroll) * kStreamUnroll - halo;
+    return r < 16 ? 16 : r;
 }
 
 // Substeps of one cycle in launches of up to `spl` substeps.

@@ -114,6 +114,7 @@ hipError_t launch_fed_coef(const float *u_in, float *u_out, const float *coef, i
 int stream_cols_per_lane();   // 2, or 1 with MF4D_STREAM_COLS=1 (same values)
 // Resident blocks per CU of that kernel for `steps`, and the CU count.
 int stream_blocks_per_cu(int steps, int *cus);
+constexpr int kStreamUnroll = 24;   // rows per unrolled block of the streaming kernels
 hipError_t launch_fed_stream(const float *u_in, float *u_out, const float *coef, int H, int W, int steps,
                              const float *taus, int seg_rows, hipStream_t s);
 
