@@ -148,16 +148,46 @@ __device__ __forceinline__ float vessel_store(float uxx, float uxy, float uyy, f
     return Sv;
 }
 
+// The same per-pixel values for a runtime mode, without branches: the mode's
+// sign test is a select, so one copy of the code serves every mode.
+struct VesselPx {
+    float S, blob, n0, n1, n2;
+};
+
+__device__ __forceinline__ VesselPx vessel_px(int mode, float uxx, float uxy, float uyy, float gx, float gy,
+                                              float sigma2, float inv2beta2)
+{
+#pragma clang fp contract(off)   // fused multiply-adds are written out
+    constexpr float kLog2e = 1.4426950408889634f;
+    const float hxx = sigma2 * uxx, hxy = sigma2 * uxy, hyy = sigma2 * uyy;
+    const float m = 0.5f * (hxx + hyy);
+    const float hd = 0.5f * (hxx - hyy);
+    const float r = __builtin_amdgcn_sqrtf(fmaf(hd, hd, hxy * hxy));
+    const float Sv = __builtin_amdgcn_sqrtf(fmaf(2.f * hxy, hxy, fmaf(hxx, hxx, hyy * hyy)));
+    const float am = fabsf(m);
+    const float big = am + r;
+    const bool sign_ok = mode == MF4D_RIDGE ? !(m > 0.f) : (mode == MF4D_VALLEY ? !(m < 0.f) : true);
+    const bool pass = big > 0.f && sign_ok;
+    const float rb = (am - r) * __builtin_amdgcn_rcpf(big);
+    const float e = __builtin_amdgcn_exp2f(-(rb * rb) * inv2beta2 * kLog2e);
+    const float f = __builtin_amdgcn_rsqf(1.f + __builtin_amdgcn_sqrtf(fmaf(gx, gx, gy * gy)));
+    return VesselPx{Sv, pass ? e : 0.f, uxx * f, uxy * f, uyy * f};
+}
+
 __device__ __forceinline__ float vessel_store_mode(int mode, float uxx, float uxy, float uyy, float gx, float gy,
                                                    float sigma2, float inv2beta2, float *__restrict__ So,
                                                    float *__restrict__ Ao, float *__restrict__ No, size_t o,
                                                    size_t plane)
 {
-    if (mode == MF4D_RIDGE)
-        return vessel_store<MF4D_RIDGE>(uxx, uxy, uyy, gx, gy, sigma2, inv2beta2, So, Ao, No, o, plane);
-    if (mode == MF4D_VALLEY)
-        return vessel_store<MF4D_VALLEY>(uxx, uxy, uyy, gx, gy, sigma2, inv2beta2, So, Ao, No, o, plane);
-    return vessel_store<MF4D_BOTH>(uxx, uxy, uyy, gx, gy, sigma2, inv2beta2, So, Ao, No, o, plane);
+    const VesselPx v = vessel_px(mode, uxx, uxy, uyy, gx, gy, sigma2, inv2beta2);
+    So[o] = v.S;
+    Ao[o] = v.blob;
+    if (No) {
+        No[o] = v.n0;
+        No[plane + o] = v.n1;
+        No[2 * plane + o] = v.n2;
+    }
+    return v.S;
 }
 
 // ------------------------------------------------------------------ vertical
