@@ -219,7 +219,7 @@ __global__ __launch_bounds__(256) void batch_stream_kernel(const BImg *imgs, con
     if (b >= pre[nact]) return;
     const int i = image_of(pre, nact, b);
     const BImg &im = imgs[i];
-    const int wave = (b - pre[i]) * 4 + (threadIdx.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane((b - pre[i]) * 4 + (threadIdx.x >> 6));   // uniform per wave
     const int strip = wave % im.strips[S], seg = wave / im.strips[S];
     if (seg >= im.segs[S]) return;
     if (C == 2)

@@ -245,7 +245,7 @@ __global__ __launch_bounds__(256) void fed_stream_kernel(const float *__restrict
     // XCD-aware: each XCD takes a contiguous run of blocks
     const int blk = (blockIdx.x % 8) * blocks_per_xcd + blockIdx.x / 8;
     if (blk >= nblocks) return;
-    const int wave = blk * 4 + (threadIdx.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane(blk * 4 + (threadIdx.x >> 6));   // uniform per wave
     const int strip = wave % strips, seg = wave / strips;
     if (seg >= segs) return;
     tiles::fed_stream_wave<S>(u, uo, coef, H, W, taus, strip, seg, seg_rows);
@@ -261,7 +261,7 @@ __global__ __launch_bounds__(256) void fed_stream2_kernel(const float *__restric
     // XCD-aware: each XCD takes a contiguous run of blocks
     const int blk = (blockIdx.x % 8) * blocks_per_xcd + blockIdx.x / 8;
     if (blk >= nblocks) return;
-    const int wave = blk * 4 + (threadIdx.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane(blk * 4 + (threadIdx.x >> 6));   // uniform per wave
     const int strip = wave % strips, seg = wave / strips;
     if (seg >= segs) return;
     tiles::fed_stream_wave2<S>(u, uo, coef, H, W, taus, strip, seg, seg_rows);

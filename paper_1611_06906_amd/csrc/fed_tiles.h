@@ -33,6 +33,11 @@ __device__ __forceinline__ float from_right(float v)
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 
+// v where m is all ones, +0 where m is 0 (a bitwise select the compiler
+// cannot turn into a branch; for finite v the same values as a conditional)
+__device__ __forceinline__ float keep(float v, unsigned m) { return __uint_as_float(__float_as_uint(v) & m); }
+__device__ __forceinline__ unsigned mask_of(bool b) { return b ? 0xffffffffu : 0u; }
+
 template <int S>
 __device__ __forceinline__ void fed_stream_wave(const float *__restrict__ u, float *__restrict__ uo,
                                                 const float *__restrict__ coef, int H, int W, const FedTaus &taus,
@@ -80,15 +85,17 @@ __device__ __forceinline__ void fed_stream_wave(const float *__restrict__ u, flo
     for (int d = 0; d < D; ++d) issue(y0 + d, qu[d], qm[d], qa[d], qb[d]);
 
     for (int yb = y0; yb < y1; yb += U) {
-#pragma unroll
+#pragma clang loop unroll(full)
         for (int t = 0; t < U; ++t) {
             const int y = yb + t;
             // arrival of row y of u_0 and of the tensor planes
             const int qs = t % D;
-            const float nu = (xin && y >= 0 && y < H) ? qu[qs] : 0.f;
-            cm[t % NC] = qm[qs];
-            ca[t % NC] = qa[qs];
-            cb[t % NC] = qb[qs];
+            const float nu = keep(qu[qs], mask_of(xin && y >= 0 && y < H));
+            // zero tensor off the interior: the flux T = D h vanishes there
+            const unsigned on = mask_of(xint && y >= 1 && y <= H - 2);
+            cm[t % NC] = keep(qm[qs], on);
+            ca[t % NC] = keep(qa[qs], on);
+            cb[t % NC] = keep(qb[qs], on);
             issue(y + D, qu[qs], qm[qs], qa[qs], qb[qs]);
             {
                 const int w0 = t % 3;
@@ -109,12 +116,11 @@ __device__ __forceinline__ void fed_stream_wave(const float *__restrict__ u, flo
                 const float hyy = fmaf(-2.f, v, uC[k - 1][wo] + uC[k - 1][wn]);
                 const float hxy = 0.25f * ((uL[k - 1][wo] + uR[k - 1][wn]) - (uL[k - 1][wn] + uR[k - 1][wo]));
                 const float mb = cm[ci], al = ca[ci], be = cb[ci];
-                const bool on = xint && q >= 1 && q <= H - 2;
                 const int tw = (t - (2 * k - 1) + 300) % 3;
                 const float bxy = be * hxy;
-                txx[k - 1][tw] = on ? fmaf(mb + al, hxx, bxy) : 0.f;
-                txy[k - 1][tw] = on ? fmaf(mb, hxy, (be * 0.5f) * (hxx + hyy)) : 0.f;
-                tyy[k - 1][tw] = on ? fmaf(mb - al, hyy, bxy) : 0.f;
+                txx[k - 1][tw] = fmaf(mb + al, hxx, bxy);
+                txy[k - 1][tw] = fmaf(mb, hxy, (be * 0.5f) * (hxx + hyy));
+                tyy[k - 1][tw] = fmaf(mb - al, hyy, bxy);
                 // u_k at row p = y - 2k from T_k rows p-1, p, p+1 and u_{k-1} row p
                 const int p = y - 2 * k;
                 const int sn = tw;                            // T_k row p+1
@@ -205,31 +211,34 @@ __device__ __forceinline__ void fed_stream_wave2(const float *__restrict__ u, fl
 
     // flux of one column from its u_{k-1} rows (left, centre, right) and tensor
     auto flux = [&](float lo, float co, float ro, float ln, float cn, float rn, float lc, float cc, float rc,
-                    float mb, float al, float be, bool on, float &txx, float &txy, float &tyy) {
+                    float mb, float al, float be, float &txx, float &txy, float &tyy) {
 #pragma clang fp contract(off)
         const float hxx = fmaf(-2.f, cc, lc + rc);
         const float hyy = fmaf(-2.f, cc, co + cn);
         const float hxy = 0.25f * ((lo + rn) - (ln + ro));
         const float bxy = be * hxy;
-        txx = on ? fmaf(mb + al, hxx, bxy) : 0.f;
-        txy = on ? fmaf(mb, hxy, (be * 0.5f) * (hxx + hyy)) : 0.f;
-        tyy = on ? fmaf(mb - al, hyy, bxy) : 0.f;
+        txx = fmaf(mb + al, hxx, bxy);
+        txy = fmaf(mb, hxy, (be * 0.5f) * (hxx + hyy));
+        tyy = fmaf(mb - al, hyy, bxy);
     };
 
     for (int yb = y0; yb < y1; yb += U) {
-#pragma unroll
+#pragma clang loop unroll(full)
         for (int t = 0; t < U; ++t) {
             const int y = yb + t;
             const int qs = t % D;
             const bool yin = y >= 0 && y < H;
-            const float na = (ina && yin) ? qa0[qs] : 0.f;
-            const float nb = (inb && yin) ? qb0[qs] : 0.f;
-            cma[t % NC] = qa1[qs];
-            cmb[t % NC] = qb1[qs];
-            caa[t % NC] = qa2[qs];
-            cab[t % NC] = qb2[qs];
-            cba[t % NC] = qa3[qs];
-            cbb[t % NC] = qb3[qs];
+            const float na = keep(qa0[qs], mask_of(ina && yin));
+            const float nb = keep(qb0[qs], mask_of(inb && yin));
+            // zero tensor off the interior: the flux T = D h vanishes there
+            const bool yint = y >= 1 && y <= H - 2;
+            const unsigned ona = mask_of(inta && yint), onb = mask_of(intb && yint);
+            cma[t % NC] = keep(qa1[qs], ona);
+            cmb[t % NC] = keep(qb1[qs], onb);
+            caa[t % NC] = keep(qa2[qs], ona);
+            cab[t % NC] = keep(qb2[qs], onb);
+            cba[t % NC] = keep(qa3[qs], ona);
+            cbb[t % NC] = keep(qb3[qs], onb);
             issue(y + D, qs);
             {
                 const int w0 = t % 3;
@@ -245,14 +254,13 @@ __device__ __forceinline__ void fed_stream_wave2(const float *__restrict__ u, fl
                 const int wc = (t - 2 * (k - 1) - 1 + 300) % 3;    // row q
                 const int wo = (t - 2 * (k - 1) - 2 + 300) % 3;    // row q-1
                 const int ci = (t - (2 * k - 1) + 2 * NC * 50) % NC;
-                const bool qin = q >= 1 && q <= H - 2;
                 const int tw = (t - (2 * k - 1) + 300) % 3;
                 // column a: left neighbour ual, right neighbour ub; column b: left ua, right ubr
                 flux(ual[k - 1][wo], ua[k - 1][wo], ub[k - 1][wo], ual[k - 1][wn], ua[k - 1][wn], ub[k - 1][wn],
-                     ual[k - 1][wc], ua[k - 1][wc], ub[k - 1][wc], cma[ci], caa[ci], cba[ci], inta && qin,
+                     ual[k - 1][wc], ua[k - 1][wc], ub[k - 1][wc], cma[ci], caa[ci], cba[ci],
                      txa[k - 1][tw], tya[k - 1][tw], tza[k - 1][tw]);
                 flux(ua[k - 1][wo], ub[k - 1][wo], ubr[k - 1][wo], ua[k - 1][wn], ub[k - 1][wn], ubr[k - 1][wn],
-                     ua[k - 1][wc], ub[k - 1][wc], ubr[k - 1][wc], cmb[ci], cab[ci], cbb[ci], intb && qin,
+                     ua[k - 1][wc], ub[k - 1][wc], ubr[k - 1][wc], cmb[ci], cab[ci], cbb[ci],
                      txb[k - 1][tw], tyb[k - 1][tw], tzb[k - 1][tw]);
                 // u_k at row p = y - 2k
                 const int p = y - 2 * k;
