@@ -231,6 +231,39 @@ int stream_rows(int H, int W, int steps)
     return r < 16 ? 16 : r;
 }
 
+
+// Side streams (default priority) and events for running independent
+// launches concurrently with the caller's stream; one set per host thread and
+// device, created on first use and kept until the process ends. MF4D_FORK=0
+// turns the concurrency off.
+constexpr int kForkStreams = 3;
+struct ForkStreams {
+    hipStream_t side[kForkStreams];
+    hipEvent_t fork, join[kForkStreams];
+};
+
+ForkStreams *fork_streams()
+{
+    if (const char *e = std::getenv("MF4D_FORK"))
+        if (std::atoi(e) == 0) return nullptr;
+    thread_local ForkStreams *sets[16] = {};
+    thread_local bool failed[16] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return nullptr;
+    if (sets[dev] || failed[dev]) return sets[dev];
+    ForkStreams *f = new ForkStreams();
+    bool ok = hipEventCreateWithFlags(&f->fork, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i < kForkStreams && ok; ++i)
+        ok = hipStreamCreateWithFlags(&f->side[i], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&f->join[i], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        failed[dev] = true;   // the caller's stream alone still works
+        return nullptr;
+    }
+    sets[dev] = f;
+    return f;
+}
+
 // Substeps of one cycle in launches of up to `spl` substeps.
 int run_substeps(const float *u_first, float *const bufs[2], int &launch_index, const float *coef, int H,
                  int W, const float *tau32, int n, int spl, hipStream_t s, const float **last)
@@ -255,12 +288,34 @@ int run_sweep(const float *u, int H, int W, const mf4d_params *p, const Workspac
 {
     const size_t m = (size_t)H * W;
     CHECK_HIP(launch_fill_u32(w.smax, 0u, 1, s));
-    WinTaps t;
+    std::vector<WinTaps> taps(p->nscales);
+    bool fused = true;   // the fused kernels need no shared scratch: scales may run concurrently
     for (int k = 0; k < p->nscales; ++k) {
-        make_taps(p->sigmas[k], &t);
+        make_taps(p->sigmas[k], &taps[k]);
+        fused = fused && sweep_engine(taps[k]) == kSweepFused;
+    }
+    auto launch = [&](int k, hipStream_t st) {
         ScalePlanes planes{w.S + k * m, w.A + k * m, want_n ? w.N + 3 * k * m : nullptr};
-        CHECK_HIP(launch_sweep_scale(u, w.hA, w.hB, w.hC, H, W, t, p->sigmas[k], p->mode, p->beta, planes,
-                                     w.smax, s));
+        return launch_sweep_scale(u, w.hA, w.hB, w.hC, H, W, taps[k], p->sigmas[k], p->mode, p->beta, planes,
+                                  w.smax, st);
+    };
+    ForkStreams *fs = (fused && p->nscales > 1) ? fork_streams() : nullptr;
+    if (!fs) {
+        for (int k = 0; k < p->nscales; ++k) CHECK_HIP(launch(k, s));
+        return MF4D_OK;
+    }
+    // the largest scales (longest, matrix-core bound) first, spread over the
+    // caller's stream and the side streams so that small, memory-bound
+    // scales overlap them
+    CHECK_HIP(hipEventRecord(fs->fork, s));
+    for (int i = 0; i < kForkStreams; ++i) CHECK_HIP(hipStreamWaitEvent(fs->side[i], fs->fork, 0));
+    for (int k = p->nscales - 1, j = 0; k >= 0; --k, ++j) {
+        const int lane = j % (kForkStreams + 1);
+        CHECK_HIP(launch(k, lane == 0 ? s : fs->side[lane - 1]));
+    }
+    for (int i = 0; i < kForkStreams; ++i) {
+        CHECK_HIP(hipEventRecord(fs->join[i], fs->side[i]));
+        CHECK_HIP(hipStreamWaitEvent(s, fs->join[i], 0));
     }
     return MF4D_OK;
 }

@@ -445,3 +445,22 @@ def test_stream_forms_bitwise(env, shape, monkeypatch):
     ref = outs[("1", "", 1)]
     for k, v in outs.items():
         assert np.array_equal(v, ref), k
+
+
+def test_concurrent_scales_bitwise(env, monkeypatch):
+    """Scales swept concurrently on side streams give the same bits as one
+    after another on the caller's stream."""
+    w = env["synth"].ridges128(H=200, W=230)
+    w.sigmas = [1.0, 2.0, 4.0, 8.0, 12.0]
+    w.mode = 2
+    w.cycles = 2
+    u = _large_image(env, 200, 230, seed=9)
+    p = env["m"].Params.from_workload(w)
+    _log("concurrent scales")
+    a = _gpu_filter(env, u, p)
+    sa = _gpu_select(env, u, p)
+    monkeypatch.setenv("MF4D_FORK", "0")
+    b = _gpu_filter(env, u, p)
+    sb = _gpu_select(env, u, p)
+    assert np.array_equal(a, b)
+    assert np.array_equal(sa[0], sb[0]) and np.array_equal(sa[1], sb[1]) and sa[2] == sb[2]
