@@ -34,13 +34,13 @@ VALU_PEAK = 78.6e12        # FLOP/s
 MFMA_F32_PEAK = 157.3e12   # FLOP/s, dense FP32 matrix cores
 SUBSTEP_BYTES_PER_PX = 20  # per launch: u in 4 + tensor planes in 12 + u out 4
 SUBSTEP_FLOPS_PER_PX = 37  # per substep: L u 10, D L u 13, L^T and update 14
-SUBSTEPS_PER_LAUNCH = 4    # as mf4d_filter launches the fused substep kernel
+SUBSTEPS_PER_LAUNCH = 4    # as mf4d_filter launches the fused substep kernel (two columns per lane)
 
 
 CSRC = os.path.join(ROOT, "paper_1611_06906_amd", "csrc")
 # sources whose change invalidates a kernel's committed counter figures
 KERNEL_SOURCES = {
-    "fed_stream_kernel<4>": ["fed_kernels.hip", "fed_tiles.h", "mf4d_internal.h", "../build.py"],
+    "fed_stream2_kernel<4>": ["fed_kernels.hip", "fed_tiles.h", "mf4d_internal.h", "../build.py"],
     "sweep_fused_kernel<8>": ["scale_kernels.hip", "scale_mfma.h", "scale_tiles.h", "mf4d_internal.h", "../build.py"],
 }
 
@@ -329,9 +329,10 @@ def main():
     m = w.H * w.W
     flops = SUBSTEP_FLOPS_PER_PX * spl * m / t
     hbm = SUBSTEP_BYTES_PER_PX * m / t
-    roofline = {"bound": "alu", "kernel": f"fed_stream_kernel<{spl}> (fused FED substep, {spl} substeps per launch)",
+    roofline = {"bound": "alu",
+                "kernel": f"fed_stream2_kernel<{spl}> (fused FED substep, {spl} substeps per launch, two columns per lane)",
                 "achieved": flops / 1e12, "peak": VALU_PEAK / 1e12, "unit": "TFLOP/s",
-                "frac": flops / VALU_PEAK, "traffic": counter_traffic(f"fed_stream_kernel<{spl}>"),
+                "frac": flops / VALU_PEAK, "traffic": counter_traffic(f"fed_stream2_kernel<{spl}>"),
                 "traffic_unit": "B per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
                 "us_per_launch": us_launch,
                 "hbm_achieved_GBs": hbm / 1e9, "hbm_frac": hbm / HBM_PEAK,
@@ -340,7 +341,7 @@ def main():
     # the same kernel at one substep per launch is HBM-bound: report it too
     ms1 = time_stream(torch, lambda: mf4d.mf4d_fed_cycle_tensor(uc, ut, dpar, taus2, 1), reps)
     t1 = ms1 * 1e-3 / (2 * n)
-    roofline_single = {"bound": "hbm", "kernel": "fed_stream_kernel<1>", "achieved": SUBSTEP_BYTES_PER_PX * m / t1 / 1e9,
+    roofline_single = {"bound": "hbm", "kernel": "fed_stream_kernel<1> (one column per lane)", "achieved": SUBSTEP_BYTES_PER_PX * m / t1 / 1e9,
                        "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": SUBSTEP_BYTES_PER_PX * m / t1 / HBM_PEAK,
                        "us_per_launch": t1 * 1e6}
 

@@ -274,7 +274,7 @@ struct mf4d_batch {
     int n = 0, max_cycles = 0;
     std::vector<float> tau32;
     int spl = 4;                     // substeps per launch
-    int cols = 2;                    // columns per lane of the streaming kernel (fixed at table build)
+    int cols[5] = {1, 1, 1, 1, 2};   // columns per lane of the streaming kernel per substeps (fixed at creation)
     int rows[5] = {0, 0, 0, 0, 0};   // rows per wave (0: default)
     size_t table_bytes = 0, ws_total = 0;
     std::vector<size_t> img_ws;      // per image (sorted order) workspace offset
@@ -333,7 +333,7 @@ void build_tables(mf4d_batch *b, const float *in, float *out, char *ws, std::vec
         im.copy_out = (L == 0 && im.user_in != im.out) ? 1 : 0;
         im.in = im.copy_in ? im.tmp : im.user_in;
         for (int s = 1; s <= 4; ++s) {
-            const int outw = 64 * b->cols - 4 * s;
+            const int outw = 64 * b->cols[s] - 4 * s;
             im.strips[s] = (W + outw - 1) / outw;
             im.seg_rows[s] = rows_for(b, H, W, s);
             im.segs[s] = (H + im.seg_rows[s] - 1) / im.seg_rows[s];
@@ -461,7 +461,7 @@ int enqueue_batch(mf4d_batch *b, char *ws, const std::vector<int> pre[PT_COUNT],
             const int total = pre[PT_ST1 + steps - 1][nact];
             const int per = (total + 7) / 8;
             const int *pt = P(PT_ST1 + steps - 1);
-            launch_batch_stream(b->cols, steps, dim3(8 * per), s, imgs, pt, nact, ft, j, per);
+            launch_batch_stream(b->cols[steps], steps, dim3(8 * per), s, imgs, pt, nact, ft, j, per);
             BCHECK(hipGetLastError());
             i0 += steps;
             ++j;
@@ -543,7 +543,7 @@ int mf4d_batch_create(int nimg, const int64_t *offsets, const int *H, const int 
         b->cycles.push_back(per_image[i].cycles);
     }
     b->shared = per_image[0];
-    b->cols = stream_cols_per_lane();
+    for (int q = 1; q <= 4; ++q) b->cols[q] = stream_cols_per_lane(q);
     b->sigmas.assign(per_image[0].sigmas, per_image[0].sigmas + per_image[0].nscales);
     b->shared.sigmas = b->sigmas.data();
     b->max_cycles = *std::max_element(b->cycles.begin(), b->cycles.end());
@@ -654,7 +654,7 @@ int mf4d_batch_autotune(mf4d_batch *plan, void *ws, size_t ws_bytes, void *strea
             FedTaus ft{};
             for (int q = 0; q < steps; ++q) ft.t[q] = plan->tau32[q];
             auto launch = [&](int j) {
-                launch_batch_stream(plan->cols, steps, dim3(8 * per), s, (const BImg *)w, pt, N, ft, j, per);
+                launch_batch_stream(plan->cols[steps], steps, dim3(8 * per), s, (const BImg *)w, pt, N, ft, j, per);
             };
             launch(1);
             launch(2);

@@ -301,8 +301,8 @@ int stream_blocks_per_cu(int steps, int *cus)
     static int ncu[16];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) dev = 0;
-    const int cols = stream_cols_per_lane();
     if (steps < 1 || steps > 4) steps = 4;
+    const int cols = stream_cols_per_lane(steps);
     if (!ncu[dev] && hipDeviceGetAttribute(&ncu[dev], hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         ncu[dev] = 256;
     int &c = cache[dev][cols][steps];
@@ -322,10 +322,14 @@ int stream_blocks_per_cu(int steps, int *cus)
     return c;
 }
 
-int stream_cols_per_lane()
+int stream_cols_per_lane(int steps)
 {
-    const char *e = std::getenv("MF4D_STREAM_COLS");
-    return (e && std::atoi(e) == 1) ? 1 : 2;
+    if (const char *e = std::getenv("MF4D_STREAM_COLS")) {
+        const int c = std::atoi(e);
+        if (c == 1 || c == 2) return c;
+    }
+    // measured at 4096^2: two columns per lane win only at four substeps
+    return steps >= 4 ? 2 : 1;
 }
 
 hipError_t launch_fed_stream(const float *u_in, float *u_out, const float *coef, int H, int W, int steps,
@@ -333,7 +337,7 @@ hipError_t launch_fed_stream(const float *u_in, float *u_out, const float *coef,
 {
     FedTaus t{};
     for (int k = 0; k < steps; ++k) t.t[k] = taus[k];
-    const int cols = stream_cols_per_lane();
+    const int cols = stream_cols_per_lane(steps);
     const int outw = 64 * cols - 4 * steps;
     const int strips = (W + outw - 1) / outw;
     const int segs = (H + seg_rows - 1) / seg_rows;

@@ -214,7 +214,7 @@ int stream_rows(int H, int W, int steps)
     // of the chip
     int cus = 256;
     const int per_cu = stream_blocks_per_cu(steps, &cus);
-    const int cols = stream_cols_per_lane();
+    const int cols = stream_cols_per_lane(steps);
     const int outw = 64 * cols - 4 * steps;
     const long long strips = (W + outw - 1) / outw;
     const long long waves = (4LL * per_cu * cus * 23) / 25;

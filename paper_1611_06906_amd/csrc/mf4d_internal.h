@@ -109,9 +109,10 @@ hipError_t launch_fed_coef(const float *u_in, float *u_out, const float *coef, i
                            float tau0, float tau1, hipStream_t s);
 
 // `steps` (1..4) consecutive substeps with taus[0..steps-1], one wave per
-// 64 c - 4 steps columns x seg_rows rows (c = stream_cols_per_lane()),
-// intermediate images in registers.
-int stream_cols_per_lane();   // 2, or 1 with MF4D_STREAM_COLS=1 (same values)
+// 64 c - 4 steps columns x seg_rows rows (c = stream_cols_per_lane(steps)),
+// intermediate images in registers. Both forms give the same values;
+// MF4D_STREAM_COLS=1 or 2 forces one.
+int stream_cols_per_lane(int steps);
 // Resident blocks per CU of that kernel for `steps`, and the CU count.
 int stream_blocks_per_cu(int steps, int *cus);
 constexpr int kStreamUnroll = 24;   // rows per unrolled block of the streaming kernels
