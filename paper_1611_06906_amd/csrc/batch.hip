@@ -29,7 +29,7 @@ struct BImg {
     const float *user_in;   // caller's input
     const float *in;        // source of the first launch (user_in, or its copy in tmp)
     float *out, *tmp;       // launch j writes (j + parity) odd ? tmp : out
-    float *hA;              // 3 planes: horizontal pass, then N at the chosen scale
+    float *hA;              // 3 planes: horizontal pass of the split and register-window sweep forms
     float *S, *A, *N;
     uint8_t *idx;
     float *tens;
@@ -176,37 +176,28 @@ __global__ __launch_bounds__(256, 2) void batch_sweep_fused_kernel(const BImg *i
 }
 
 __global__ __launch_bounds__(256) void batch_argmax_kernel(const BImg *imgs, const int *pre, int nact, int ns,
-                                                           float c_param, int keep_idx)
+                                                           float c_param)
 {
     const int i = image_of(pre, nact, blockIdx.x);
     const BImg &im = imgs[i];
     const size_t m = (size_t)im.H * im.W;
     const size_t o = (size_t)(blockIdx.x - pre[i]) * 256 + threadIdx.x;
     if (o >= m) return;
-    int best;
-    if (keep_idx) {
-        best = im.idx[o];
-    } else {
-        const float c = c_param > 0.f ? c_param : 0.5f * __uint_as_float(*im.smax);
-        float bv;
-        best = argmax_px(im.S, im.A, ns, m, o, c, &bv);
-        im.idx[o] = (uint8_t)best;
-    }
-    const float *Nb = im.N + (size_t)best * 3 * m;
-    im.hA[o] = Nb[o];
-    im.hA[m + o] = Nb[m + o];
-    im.hA[2 * m + o] = Nb[2 * m + o];
+    const float c = c_param > 0.f ? c_param : 0.5f * __uint_as_float(*im.smax);
+    float bv;
+    im.idx[o] = (uint8_t)argmax_px(im.S, im.A, ns, m, o, c, &bv);
 }
 
+// H_rho of each image, N gathered through its scale indices
 template <int HR>
-__global__ __launch_bounds__(256) void batch_rho_kernel(const BImg *imgs, const int *pre, int nact, RhoTaps t,
-                                                        float inv_lam2)
+__global__ __launch_bounds__(256) void batch_rho_kernel(const BImg *imgs, const int *pre, int nact, int ns,
+                                                        RhoTaps t, float inv_lam2)
 {
     const int i = image_of(pre, nact, blockIdx.x);
     const BImg &im = imgs[i];
     const int lt = blockIdx.x - pre[i];
     const int tx = (im.W + kBTW - 1) / kBTW;
-    rho_blur_tile<HR>(im.hA, nullptr, im.tens, im.mode, inv_lam2, im.H, im.W, t, (lt % tx) * kBTW,
+    rho_blur_tile<HR>(im.N, im.idx, ns, nullptr, im.tens, im.mode, inv_lam2, im.H, im.W, t, (lt % tx) * kBTW,
                       (lt / tx) * kBTH);
 }
 
@@ -438,14 +429,15 @@ int enqueue_batch(mf4d_batch *b, char *ws, const std::vector<int> pre[PT_COUNT],
             }
             BCHECK(hipGetLastError());
         }
-        const int keep = (k > 0 && !p.reselect_each_cycle) ? 1 : 0;
-        hipLaunchKernelGGL(batch_argmax_kernel, dim3(pre[PT_PX][nact]), dim3(256), 0, s, imgs, P(PT_PX), nact, ns,
-                           p.c, keep);
-        BCHECK(hipGetLastError());
+        if (k == 0 || p.reselect_each_cycle) {   // otherwise the indices of the first cycle are kept
+            hipLaunchKernelGGL(batch_argmax_kernel, dim3(pre[PT_PX][nact]), dim3(256), 0, s, imgs, P(PT_PX), nact, ns,
+                               p.c);
+            BCHECK(hipGetLastError());
+        }
         switch (rt.r) {
 #define MF4D_BRHO(R)                                                                                           \
     case R:                                                                                                    \
-        hipLaunchKernelGGL(batch_rho_kernel<R>, dim3(pre[PT_RHO][nact]), dim3(256), 0, s, imgs, P(PT_RHO), nact, \
+        hipLaunchKernelGGL(batch_rho_kernel<R>, dim3(pre[PT_RHO][nact]), dim3(256), 0, s, imgs, P(PT_RHO), nact, ns, \
                            rt, inv_lam2);                                                                      \
         break;
             MF4D_BRHO(0) MF4D_BRHO(1) MF4D_BRHO(2) MF4D_BRHO(3) MF4D_BRHO(4) MF4D_BRHO(5) MF4D_BRHO(6)

@@ -359,10 +359,12 @@ __global__ __launch_bounds__(256) void learned_select_kernel(const float *__rest
             atomicAdd(&cnt, 1u);
         }
         idx[o] = (uint8_t)best;
-        const float *Nb = N + (size_t)best * 3 * plane;
-        nsel[o] = Nb[o];
-        nsel[plane + o] = Nb[plane + o];
-        nsel[2 * plane + o] = Nb[2 * plane + o];
+        if (nsel) {   // otherwise the integration gathers N through idx
+            const float *Nb = N + (size_t)best * 3 * plane;
+            nsel[o] = Nb[o];
+            nsel[plane + o] = Nb[plane + o];
+            nsel[2 * plane + o] = Nb[2 * plane + o];
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0 && cnt) atomicAdd(fallback, cnt);

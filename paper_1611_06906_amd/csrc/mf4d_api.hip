@@ -639,6 +639,7 @@ int mf4d_filter_learned(const float *u_in, float *u_out, int H, int W, const mf4
     SelectArgs a = select_args(p, w);
     a.coef = w.tens;
     a.idx_out = w.idx;
+    a.nsel = nullptr;   // the integration gathers N through the indices
     int li = 0;
     for (int k = 0; k < p->cycles; ++k) {
         const float *z = nullptr;

@@ -92,7 +92,7 @@ struct SelectArgs {
     float *c_out;
     float *hrho;
     float *coef;
-    float *nsel;         // [3][H][W] scratch: N at the chosen scale
+    float *nsel;         // [3][H][W] N at the chosen scale, or nullptr: the integration gathers N through the indices
     int mode;
     float inv_lam2;
     RhoTaps rho;
@@ -119,7 +119,8 @@ constexpr int kStreamUnroll = 24;   // rows per unrolled block of the streaming 
 hipError_t launch_fed_stream(const float *u_in, float *u_out, const float *coef, int H, int W, int steps,
                              const float *taus, int seg_rows, hipStream_t s);
 
-// Integration with G_rho and tensor planes only (nsel already gathered).
+// Integration with G_rho and tensor planes only: N from nsel, or gathered
+// from N through idx_in (else idx_out).
 hipError_t launch_rho(const SelectArgs &a, int H, int W, hipStream_t s);
 
 // Learned surrogate (learned.hip): network forward on one H x W image into

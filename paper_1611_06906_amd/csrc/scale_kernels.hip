@@ -123,11 +123,11 @@ __global__ __launch_bounds__(256) void argmax_kernel(SelectArgs a, size_t plane)
 }
 
 template <int HR>
-__global__ __launch_bounds__(256) void rho_blur_kernel(const float *__restrict__ N, float *__restrict__ Hr,
-                                                       float *__restrict__ coef, int mode, float inv_lam2,
-                                                       int H, int W, RhoTaps t, int tiles_x)
+__global__ __launch_bounds__(256) void rho_blur_kernel(const float *__restrict__ N, const uint8_t *__restrict__ idx,
+                                                       int ns, float *__restrict__ Hr, float *__restrict__ coef,
+                                                       int mode, float inv_lam2, int H, int W, RhoTaps t, int tiles_x)
 {
-    rho_blur_tile<HR>(N, Hr, coef, mode, inv_lam2, H, W, t, (blockIdx.x % tiles_x) * kBTW,
+    rho_blur_tile<HR>(N, idx, ns, Hr, coef, mode, inv_lam2, H, W, t, (blockIdx.x % tiles_x) * kBTW,
                       (blockIdx.x / tiles_x) * kBTH);
 }
 
@@ -285,11 +285,15 @@ hipError_t launch_rho(const SelectArgs &a, int H, int W, hipStream_t s)
 {
     const int tiles_x = (W + kBTW - 1) / kBTW, tiles_y = (H + kBTH - 1) / kBTH;
     dim3 grid(tiles_x * tiles_y), block(256);
+    // N at the chosen scale: gathered through the indices, or staged in nsel
+    const uint8_t *gidx = a.nsel ? nullptr : (a.idx_in ? a.idx_in : a.idx_out);
+    const float *src = a.nsel ? a.nsel : a.N;
+    if (!a.nsel && !gidx) return hipErrorInvalidValue;
     switch (a.rho.r) {
 #define MF4D_RHO_ONLY(R)                                                                                       \
     case R:                                                                                                    \
-        hipLaunchKernelGGL(rho_blur_kernel<R>, grid, block, 0, s, a.nsel, a.hrho, a.coef, a.mode, a.inv_lam2, H, \
-                           W, a.rho, tiles_x);                                                                 \
+        hipLaunchKernelGGL(rho_blur_kernel<R>, grid, block, 0, s, src, gidx, a.ns, a.hrho, a.coef, a.mode,       \
+                           a.inv_lam2, H, W, a.rho, tiles_x);                                                  \
         break;
         MF4D_RHO_ONLY(0) MF4D_RHO_ONLY(1) MF4D_RHO_ONLY(2) MF4D_RHO_ONLY(3) MF4D_RHO_ONLY(4)
         MF4D_RHO_ONLY(5) MF4D_RHO_ONLY(6) MF4D_RHO_ONLY(7) MF4D_RHO_ONLY(8)
@@ -302,26 +306,20 @@ hipError_t launch_rho(const SelectArgs &a, int H, int W, hipStream_t s)
 hipError_t launch_select(const SelectArgs &a, int H, int W, hipStream_t s)
 {
     const size_t plane = (size_t)H * W;
-    SelectArgs b = a;
     const bool tensor = a.hrho || a.coef;
-    if (!tensor) b.nsel = nullptr;
-    hipLaunchKernelGGL(argmax_kernel, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, s, b, plane);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !tensor) return e;
-    const int tiles_x = (W + kBTW - 1) / kBTW, tiles_y = (H + kBTH - 1) / kBTH;
-    dim3 grid(tiles_x * tiles_y), block(256);
-    switch (a.rho.r) {
-#define MF4D_RHO_CASE(R)                                                                               \
-    case R:                                                                                            \
-        hipLaunchKernelGGL(rho_blur_kernel<R>, grid, block, 0, s, a.nsel, a.hrho, a.coef, a.mode,          \
-                           a.inv_lam2, H, W, a.rho, tiles_x);                                          \
-        break;
-        MF4D_RHO_CASE(0) MF4D_RHO_CASE(1) MF4D_RHO_CASE(2) MF4D_RHO_CASE(3) MF4D_RHO_CASE(4)
-        MF4D_RHO_CASE(5) MF4D_RHO_CASE(6) MF4D_RHO_CASE(7) MF4D_RHO_CASE(8)
-#undef MF4D_RHO_CASE
-    default: return hipErrorInvalidValue;
+    // the argmax writes only indices; the integration gathers N through them
+    if (!a.idx_in || a.c_out) {   // with given indices the kernel only reports c
+        SelectArgs b = a;
+        b.nsel = nullptr;
+        hipLaunchKernelGGL(argmax_kernel, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, s, b, plane);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
     }
-    return hipGetLastError();
+    if (!tensor) return hipSuccess;
+    if (!a.idx_in && !a.idx_out) return hipErrorInvalidValue;
+    SelectArgs r = a;
+    r.nsel = nullptr;
+    return launch_rho(r, H, W, s);
 }
 
 }  // namespace mf4d

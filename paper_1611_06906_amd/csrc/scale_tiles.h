@@ -281,19 +281,29 @@ __device__ __forceinline__ float frangi_v(float S, float blob, float inv2c2)
 }
 
 // argmax over scales at pixel o (smallest index among equal maxima); writes
-// the maximum to *vbest. c = 0 makes every V zero (index 0).
+// the maximum to *vbest. c = 0 makes every V zero (index 0). Every scale's
+// loads are issued before the comparisons.
 __device__ __forceinline__ int argmax_px(const float *__restrict__ S, const float *__restrict__ A, int ns,
                                          size_t plane, size_t o, float c, float *vbest)
 {
     int best = 0;
     float bv = 0.f;
     if (c > 0.f) {
+        float sv[MF4D_MAX_SCALES], av[MF4D_MAX_SCALES];
+#pragma unroll
+        for (int s = 0; s < MF4D_MAX_SCALES; ++s)
+            if (s < ns) {
+                sv[s] = S[s * plane + o];
+                av[s] = A[s * plane + o];
+            }
         const float inv2c2 = 1.f / (2.f * c * c);
-        bv = frangi_v(S[o], A[o], inv2c2);
-        for (int s = 1; s < ns; ++s) {
-            const float v = frangi_v(S[s * plane + o], A[s * plane + o], inv2c2);
-            if (v > bv) { bv = v; best = s; }
-        }
+        bv = frangi_v(sv[0], av[0], inv2c2);
+#pragma unroll
+        for (int s = 1; s < MF4D_MAX_SCALES; ++s)
+            if (s < ns) {
+                const float v = frangi_v(sv[s], av[s], inv2c2);
+                if (v > bv) { bv = v; best = s; }
+            }
     }
     *vbest = bv;
     return best;
@@ -304,10 +314,13 @@ __device__ __forceinline__ int argmax_px(const float *__restrict__ S, const floa
 // tile's inputs (with a halo of HR) are staged in LDS; thread (x, g) blurs
 // rows 8g - HR .. 8g + 7 + HR of column x horizontally into registers and
 // then vertically, so only one LDS buffer is needed.
+// With idx != nullptr, N holds the planes of all ns scales ([ns][3][H][W])
+// and each staged pixel takes the three planes of its scale idx (clamped to
+// ns - 1); otherwise N holds three planes.
 template <int HR>
-__device__ __forceinline__ void rho_blur_tile(const float *__restrict__ N, float *__restrict__ Hr,
-                                              float *__restrict__ coef, int mode, float inv_lam2, int H, int W,
-                                              const RhoTaps &t, int x0, int y0)
+__device__ __forceinline__ void rho_blur_tile(const float *__restrict__ N, const uint8_t *__restrict__ idx, int ns,
+                                              float *__restrict__ Hr, float *__restrict__ coef, int mode,
+                                              float inv_lam2, int H, int W, const RhoTaps &t, int x0, int y0)
 {
 #pragma clang fp contract(off)   // fused multiply-adds are written out
     constexpr int PW = kBTW + 2 * HR, PH = kBTH + 2 * HR;
@@ -316,14 +329,38 @@ __device__ __forceinline__ void rho_blur_tile(const float *__restrict__ N, float
     __shared__ float sN[3][PH][PW + 1];
     const size_t plane = (size_t)H * W;
     const bool interior = x0 - HR >= 0 && y0 - HR >= 0 && x0 + kBTW + HR <= W && y0 + kBTH + HR <= H;
-    for (int i = threadIdx.x; i < PW * PH; i += 256) {
+    // all loads of the staged tile are issued before any LDS store (the
+    // scale indices first when N is gathered)
+    constexpr int NI = (PW * PH + 255) / 256;
+    float v0[NI], v1[NI], v2[NI];
+    size_t off[NI];
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const int i = min((int)threadIdx.x + 256 * it, PW * PH - 1);
         const int ly = i / PW, lx = i - ly * PW;
         const int gy = interior ? y0 - HR + ly : reflect(y0 - HR + ly, H);
         const int gx = interior ? x0 - HR + lx : reflect(x0 - HR + lx, W);
-        const size_t o = (size_t)gy * W + gx;
-        sN[0][ly][lx] = N[o];
-        sN[1][ly][lx] = N[plane + o];
-        sN[2][ly][lx] = N[2 * plane + o];
+        off[it] = (size_t)gy * W + gx;
+    }
+    int sc[NI];
+#pragma unroll
+    for (int it = 0; it < NI; ++it) sc[it] = idx ? min((int)idx[off[it]], ns - 1) : 0;
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const float *Nb = N + (size_t)sc[it] * 3 * plane;
+        v0[it] = Nb[off[it]];
+        v1[it] = Nb[plane + off[it]];
+        v2[it] = Nb[2 * plane + off[it]];
+    }
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const int i = (int)threadIdx.x + 256 * it;
+        if (i < PW * PH) {
+            const int ly = i / PW, lx = i - ly * PW;
+            sN[0][ly][lx] = v0[it];
+            sN[1][ly][lx] = v1[it];
+            sN[2][ly][lx] = v2[it];
+        }
     }
     __syncthreads();
     const int lx = threadIdx.x & 63, g = threadIdx.x >> 6;
