@@ -333,13 +333,13 @@ __global__ void adam_kernel(float *__restrict__ th, const float *__restrict__ g,
 }
 
 // learned selection: the network's scale where its confidence reaches the
-// threshold, the exact argmax elsewhere; then N at that scale
+// threshold, the exact argmax elsewhere (the integration then gathers N at
+// that scale through idx)
 __global__ __launch_bounds__(256) void learned_select_kernel(const float *__restrict__ z, float thr,
                                                              const float *__restrict__ S, const float *__restrict__ A,
-                                                             const float *__restrict__ N, int ns, size_t plane,
+                                                             int ns, size_t plane,
                                                              const unsigned *__restrict__ smax_bits, float c_param,
-                                                             uint8_t *__restrict__ idx, float *__restrict__ nsel,
-                                                             unsigned *__restrict__ fallback)
+                                                             uint8_t *__restrict__ idx, unsigned *__restrict__ fallback)
 {
     __shared__ unsigned cnt;
     if (threadIdx.x == 0) cnt = 0;
@@ -359,12 +359,6 @@ __global__ __launch_bounds__(256) void learned_select_kernel(const float *__rest
             atomicAdd(&cnt, 1u);
         }
         idx[o] = (uint8_t)best;
-        if (nsel) {   // otherwise the integration gathers N through idx
-            const float *Nb = N + (size_t)best * 3 * plane;
-            nsel[o] = Nb[o];
-            nsel[plane + o] = Nb[plane + o];
-            nsel[2 * plane + o] = Nb[2 * plane + o];
-        }
     }
     __syncthreads();
     if (threadIdx.x == 0 && cnt) atomicAdd(fallback, cnt);
@@ -477,7 +471,7 @@ hipError_t launch_learned_select(const float *z, float thr, const SelectArgs &a,
 {
     const size_t plane = (size_t)H * W;
     hipLaunchKernelGGL(net::learned_select_kernel, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, s, z, thr, a.S,
-                       a.A, a.N, a.ns, plane, a.smax_bits, a.c_param, a.idx_out, a.nsel, fallback);
+                       a.A, a.ns, plane, a.smax_bits, a.c_param, a.idx_out, fallback);
     return hipGetLastError();
 }
 

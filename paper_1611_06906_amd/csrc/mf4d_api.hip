@@ -329,7 +329,6 @@ SelectArgs select_args(const mf4d_params *p, const Workspace &w)
     a.N = w.N;
     a.ns = p->nscales;
     a.smax_bits = w.smax;
-    a.nsel = w.hA;
     a.c_param = p->c;
     a.mode = p->mode;
     a.inv_lam2 = 1.f / (p->lambda * p->lambda);
@@ -639,7 +638,6 @@ int mf4d_filter_learned(const float *u_in, float *u_out, int H, int W, const mf4
     SelectArgs a = select_args(p, w);
     a.coef = w.tens;
     a.idx_out = w.idx;
-    a.nsel = nullptr;   // the integration gathers N through the indices
     int li = 0;
     for (int k = 0; k < p->cycles; ++k) {
         const float *z = nullptr;

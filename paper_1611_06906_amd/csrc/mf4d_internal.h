@@ -39,7 +39,7 @@ struct RhoTaps {
 struct ScalePlanes {
     float *S;   // [H][W] Frobenius norm of sigma^2 H(u_sigma)
     float *A;   // [H][W] blob factor exp(-R_B^2 / 2 beta^2), 0 if the sign test fails
-    float *N;   // [3][H][W] H(u_sigma) / sqrt(1 + |grad u_sigma|), or nullptr
+    float *N;   // [H][W][3] H(u_sigma) / sqrt(1 + |grad u_sigma|) per pixel, or nullptr
 };
 
 // Horizontal pass of one scale: A = G u, B = D1G u, C = D2G u along x.
@@ -82,7 +82,7 @@ hipError_t launch_copy_f32(const float *src, float *dst, size_t n, hipStream_t s
 struct SelectArgs {
     const float *S;      // [ns][H][W]
     const float *A;      // [ns][H][W]
-    const float *N;      // [ns][3][H][W]
+    const float *N;      // [ns][H][W][3]
     int ns;
     const unsigned *smax_bits;
     float c_param;
@@ -92,7 +92,6 @@ struct SelectArgs {
     float *c_out;
     float *hrho;
     float *coef;
-    float *nsel;         // [3][H][W] N at the chosen scale, or nullptr: the integration gathers N through the indices
     int mode;
     float inv_lam2;
     RhoTaps rho;
@@ -119,8 +118,8 @@ constexpr int kStreamUnroll = 24;   // rows per unrolled block of the streaming 
 hipError_t launch_fed_stream(const float *u_in, float *u_out, const float *coef, int H, int W, int steps,
                              const float *taus, int seg_rows, hipStream_t s);
 
-// Integration with G_rho and tensor planes only: N from nsel, or gathered
-// from N through idx_in (else idx_out).
+// Integration with G_rho and tensor planes only: N at the chosen scale is
+// gathered through idx_in (else idx_out).
 hipError_t launch_rho(const SelectArgs &a, int H, int W, hipStream_t s);
 
 // Learned surrogate (learned.hip): network forward on one H x W image into

@@ -114,12 +114,7 @@ __global__ __launch_bounds__(256) void argmax_kernel(SelectArgs a, size_t plane)
         if (a.idx_out) a.idx_out[o] = (uint8_t)best;
         if (a.vmax_out) a.vmax_out[o] = bv;
     }
-    if (a.nsel) {
-        const float *Nb = a.N + (size_t)best * 3 * plane;
-        a.nsel[o] = Nb[o];
-        a.nsel[plane + o] = Nb[plane + o];
-        a.nsel[2 * plane + o] = Nb[2 * plane + o];
-    }
+    (void)best;
 }
 
 template <int HR>
@@ -285,10 +280,10 @@ hipError_t launch_rho(const SelectArgs &a, int H, int W, hipStream_t s)
 {
     const int tiles_x = (W + kBTW - 1) / kBTW, tiles_y = (H + kBTH - 1) / kBTH;
     dim3 grid(tiles_x * tiles_y), block(256);
-    // N at the chosen scale: gathered through the indices, or staged in nsel
-    const uint8_t *gidx = a.nsel ? nullptr : (a.idx_in ? a.idx_in : a.idx_out);
-    const float *src = a.nsel ? a.nsel : a.N;
-    if (!a.nsel && !gidx) return hipErrorInvalidValue;
+    // N at the chosen scale is gathered through the indices
+    const uint8_t *gidx = a.idx_in ? a.idx_in : a.idx_out;
+    const float *src = a.N;
+    if (!gidx) return hipErrorInvalidValue;
     switch (a.rho.r) {
 #define MF4D_RHO_ONLY(R)                                                                                       \
     case R:                                                                                                    \
@@ -309,17 +304,13 @@ hipError_t launch_select(const SelectArgs &a, int H, int W, hipStream_t s)
     const bool tensor = a.hrho || a.coef;
     // the argmax writes only indices; the integration gathers N through them
     if (!a.idx_in || a.c_out) {   // with given indices the kernel only reports c
-        SelectArgs b = a;
-        b.nsel = nullptr;
-        hipLaunchKernelGGL(argmax_kernel, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, s, b, plane);
+        hipLaunchKernelGGL(argmax_kernel, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, s, a, plane);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (!tensor) return hipSuccess;
     if (!a.idx_in && !a.idx_out) return hipErrorInvalidValue;
-    SelectArgs r = a;
-    r.nsel = nullptr;
-    return launch_rho(r, H, W, s);
+    return launch_rho(a, H, W, s);
 }
 
 }  // namespace mf4d

@@ -141,9 +141,9 @@ __device__ __forceinline__ float vessel_store(float uxx, float uxy, float uyy, f
     Ao[o] = blob;
     if (No) {
         const float f = __builtin_amdgcn_rsqf(1.f + __builtin_amdgcn_sqrtf(fmaf(gx, gx, gy * gy)));
-        No[o] = uxx * f;
-        No[plane + o] = uxy * f;
-        No[2 * plane + o] = uyy * f;
+        No[3 * o] = uxx * f;   // N is stored per pixel: [H][W][3]
+        No[3 * o + 1] = uxy * f;
+        No[3 * o + 2] = uyy * f;
     }
     return Sv;
 }
@@ -183,9 +183,9 @@ __device__ __forceinline__ float vessel_store_mode(int mode, float uxx, float ux
     So[o] = v.S;
     Ao[o] = v.blob;
     if (No) {
-        No[o] = v.n0;
-        No[plane + o] = v.n1;
-        No[2 * plane + o] = v.n2;
+        No[3 * o] = v.n0;   // N is stored per pixel: [H][W][3]
+        No[3 * o + 1] = v.n1;
+        No[3 * o + 2] = v.n2;
     }
     return v.S;
 }
@@ -314,9 +314,8 @@ __device__ __forceinline__ int argmax_px(const float *__restrict__ S, const floa
 // tile's inputs (with a halo of HR) are staged in LDS; thread (x, g) blurs
 // rows 8g - HR .. 8g + 7 + HR of column x horizontally into registers and
 // then vertically, so only one LDS buffer is needed.
-// With idx != nullptr, N holds the planes of all ns scales ([ns][3][H][W])
-// and each staged pixel takes the three planes of its scale idx (clamped to
-// ns - 1); otherwise N holds three planes.
+// N holds all ns scales, per pixel ([ns][H][W][3]); each staged pixel takes
+// the three values of its scale idx (clamped to ns - 1).
 template <int HR>
 __device__ __forceinline__ void rho_blur_tile(const float *__restrict__ N, const uint8_t *__restrict__ idx, int ns,
                                               float *__restrict__ Hr, float *__restrict__ coef, int mode,
@@ -330,7 +329,7 @@ __device__ __forceinline__ void rho_blur_tile(const float *__restrict__ N, const
     const size_t plane = (size_t)H * W;
     const bool interior = x0 - HR >= 0 && y0 - HR >= 0 && x0 + kBTW + HR <= W && y0 + kBTH + HR <= H;
     // all loads of the staged tile are issued before any LDS store (the
-    // scale indices first when N is gathered)
+    // scale indices first)
     constexpr int NI = (PW * PH + 255) / 256;
     float v0[NI], v1[NI], v2[NI];
     size_t off[NI];
@@ -344,13 +343,13 @@ __device__ __forceinline__ void rho_blur_tile(const float *__restrict__ N, const
     }
     int sc[NI];
 #pragma unroll
-    for (int it = 0; it < NI; ++it) sc[it] = idx ? min((int)idx[off[it]], ns - 1) : 0;
+    for (int it = 0; it < NI; ++it) sc[it] = min((int)idx[off[it]], ns - 1);
 #pragma unroll
     for (int it = 0; it < NI; ++it) {
-        const float *Nb = N + (size_t)sc[it] * 3 * plane;
-        v0[it] = Nb[off[it]];
-        v1[it] = Nb[plane + off[it]];
-        v2[it] = Nb[2 * plane + off[it]];
+        const float *Np = N + 3 * ((size_t)sc[it] * plane + off[it]);
+        v0[it] = Np[0];
+        v1[it] = Np[1];
+        v2[it] = Np[2];
     }
 #pragma unroll
     for (int it = 0; it < NI; ++it) {
