@@ -30,7 +30,7 @@ struct BImg {
     const float *in;        // source of the first launch (user_in, or its copy in tmp)
     float *out, *tmp;       // launch j writes (j + parity) odd ? tmp : out
     float *hA;              // 3 planes: horizontal pass of the split and register-window sweep forms
-    float *S, *A, *N;
+    float *SA, *N;          // per-scale (S, blob) pairs and N
     uint8_t *idx;
     float *tens;
     unsigned *smax;
@@ -110,12 +110,12 @@ __global__ __launch_bounds__(256) void batch_vpass_kernel(const BImg *imgs, cons
     const int tx = (im.W + 63) / 64;
     const size_t m = (size_t)im.H * im.W;
     const float *A = im.hA, *B = im.hA + m, *C = im.hA + 2 * m;
-    float *So = im.S + s * m, *Ao = im.A + s * m, *No = im.N + 3 * s * m;
+    float *SA = im.SA + 2 * s * m, *No = im.N + 3 * s * m;
     const int x0 = (lt % tx) * 64, y0 = (lt / tx) * 64;
     float v;
-    if (im.mode == MF4D_RIDGE) v = vpass_tile<MF4D_RIDGE>(A, B, C, im.H, im.W, t, sigma2, inv2beta2, So, Ao, No, x0, y0);
-    else if (im.mode == MF4D_VALLEY) v = vpass_tile<MF4D_VALLEY>(A, B, C, im.H, im.W, t, sigma2, inv2beta2, So, Ao, No, x0, y0);
-    else v = vpass_tile<MF4D_BOTH>(A, B, C, im.H, im.W, t, sigma2, inv2beta2, So, Ao, No, x0, y0);
+    if (im.mode == MF4D_RIDGE) v = vpass_tile<MF4D_RIDGE>(A, B, C, im.H, im.W, t, sigma2, inv2beta2, SA, No, x0, y0);
+    else if (im.mode == MF4D_VALLEY) v = vpass_tile<MF4D_VALLEY>(A, B, C, im.H, im.W, t, sigma2, inv2beta2, SA, No, x0, y0);
+    else v = vpass_tile<MF4D_BOTH>(A, B, C, im.H, im.W, t, sigma2, inv2beta2, SA, No, x0, y0);
     block_max_to(v, im.smax);
 }
 
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256) void batch_vpass_mfma_kernel(const BImg *imgs,
     const int ys = seg * kBatchVSegRows, ye = min(im.H, ys + kBatchVSegRows);
     const size_t m = (size_t)im.H * im.W;
     const float v = vpass_mfma_tile<NC>(im.hA, im.hA + m, im.hA + 2 * m, im.H, im.W, t, sigma2, inv2beta2, im.mode,
-                                        im.S + s * m, im.A + s * m, im.N + 3 * s * m, strip * kVMW, ys, ye,
+                                        im.SA + 2 * s * m, im.N + 3 * s * m, strip * kVMW, ys, ye,
                                         (float *)lds4);
     block_max_to(v, im.smax);
 }
@@ -170,8 +170,8 @@ __global__ __launch_bounds__(256, 2) void batch_sweep_fused_kernel(const BImg *i
     const int strip = lt / segs, seg = lt - strip * segs;
     const int ys = seg * kBatchFusedSegRows, ye = min(im.H, ys + kBatchFusedSegRows);
     const size_t m = (size_t)im.H * im.W;
-    const float v = sweep_fused_tile<NC>(state_src(im, jsrc), im.H, im.W, t, sigma2, inv2beta2, im.mode, im.S + s * m,
-                                         im.A + s * m, im.N + 3 * s * m, strip * kVMW, ys, ye, (float *)lds4);
+    const float v = sweep_fused_tile<NC>(state_src(im, jsrc), im.H, im.W, t, sigma2, inv2beta2, im.mode,
+                                         im.SA + 2 * s * m, im.N + 3 * s * m, strip * kVMW, ys, ye, (float *)lds4);
     block_max_to(v, im.smax);
 }
 
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(256) void batch_argmax_kernel(const BImg *imgs, con
     if (o >= m) return;
     const float c = c_param > 0.f ? c_param : 0.5f * __uint_as_float(*im.smax);
     float bv;
-    im.idx[o] = (uint8_t)argmax_px(im.S, im.A, ns, m, o, c, &bv);
+    im.idx[o] = (uint8_t)argmax_px(im.SA, ns, m, o, c, &bv);
 }
 
 // H_rho of each image, N gathered through its scale indices
@@ -244,7 +244,7 @@ void launch_batch_stream(int cols, int steps, dim3 grid, hipStream_t s, const BI
 // host helpers shared with mf4d_api.hip
 int validate_params(int H, int W, const mf4d_params *p);
 size_t image_workspace_bytes(int H, int W, int ns);
-void image_workspace(int H, int W, int ns, char *base, float **hA, float **S, float **A, float **N,
+void image_workspace(int H, int W, int ns, char *base, float **hA, float **SA, float **N,
                      uint8_t **idx, float **tens, float **utmp, unsigned **smax);
 void window_taps(double sigma, WinTaps *t);
 void rho_taps(double rho, RhoTaps *t);
@@ -313,7 +313,7 @@ void build_tables(mf4d_batch *b, const float *in, float *out, char *ws, std::vec
         im.W = W;
         im.mode = b->mode[i];
         float *utmp;
-        image_workspace(H, W, ns, ws + b->img_ws[r], &im.hA, &im.S, &im.A, &im.N, &im.idx, &im.tens, &utmp,
+        image_workspace(H, W, ns, ws + b->img_ws[r], &im.hA, &im.SA, &im.N, &im.idx, &im.tens, &utmp,
                         &im.smax);
         im.user_in = in + b->off[i];
         im.out = out + b->off[i];

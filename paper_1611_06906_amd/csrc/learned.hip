@@ -336,7 +336,7 @@ __global__ void adam_kernel(float *__restrict__ th, const float *__restrict__ g,
 // threshold, the exact argmax elsewhere (the integration then gathers N at
 // that scale through idx)
 __global__ __launch_bounds__(256) void learned_select_kernel(const float *__restrict__ z, float thr,
-                                                             const float *__restrict__ S, const float *__restrict__ A,
+                                                             const float *__restrict__ SA,
                                                              int ns, size_t plane,
                                                              const unsigned *__restrict__ smax_bits, float c_param,
                                                              uint8_t *__restrict__ idx, unsigned *__restrict__ fallback)
@@ -355,7 +355,7 @@ __global__ __launch_bounds__(256) void learned_select_kernel(const float *__rest
         if (!(conf >= thr)) {
             const float c = c_param > 0.f ? c_param : 0.5f * __uint_as_float(*smax_bits);
             float bv;
-            best = tiles::argmax_px(S, A, ns, plane, o, c, &bv);
+            best = tiles::argmax_px(SA, ns, plane, o, c, &bv);
             atomicAdd(&cnt, 1u);
         }
         idx[o] = (uint8_t)best;
@@ -470,15 +470,15 @@ hipError_t launch_learned_select(const float *z, float thr, const SelectArgs &a,
                                  hipStream_t s)
 {
     const size_t plane = (size_t)H * W;
-    hipLaunchKernelGGL(net::learned_select_kernel, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, s, z, thr, a.S,
-                       a.A, a.ns, plane, a.smax_bits, a.c_param, a.idx_out, fallback);
+    hipLaunchKernelGGL(net::learned_select_kernel, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, s, z, thr, a.SA,
+                       a.ns, plane, a.smax_bits, a.c_param, a.idx_out, fallback);
     return hipGetLastError();
 }
 
 // learned-filter helpers defined in mf4d_api.hip
 int validate_params(int H, int W, const mf4d_params *p);
 size_t image_workspace_bytes(int H, int W, int ns);
-void image_workspace(int H, int W, int ns, char *base, float **hA, float **S, float **A, float **N,
+void image_workspace(int H, int W, int ns, char *base, float **hA, float **SA, float **N,
                      uint8_t **idx, float **tens, float **utmp, unsigned **smax);
 void window_taps(double sigma, WinTaps *t);
 void rho_taps(double rho, RhoTaps *t);

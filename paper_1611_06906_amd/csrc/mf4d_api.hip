@@ -157,7 +157,7 @@ std::vector<double> natural_steps(int n, double T_over_M)
 
 struct Workspace {
     float *hA, *hB, *hC;     // horizontal pass, one scale at a time; then N at the chosen scale
-    float *S, *A, *N;        // per-scale planes
+    float *SA, *N;           // per-scale planes: (S, blob) pairs [ns][H][W][2], N [ns][H][W][3]
     uint8_t *idx;
     float *tens;             // compact tensor planes of the current cycle
     float *utmp;
@@ -179,8 +179,7 @@ size_t layout(int H, int W, int ns, Workspace *w, char *base)
     t.hA = (float *)take(m * 12);
     t.hB = t.hA ? t.hA + m : nullptr;
     t.hC = t.hA ? t.hA + 2 * m : nullptr;
-    t.S = (float *)take(m * 4 * ns);
-    t.A = (float *)take(m * 4 * ns);
+    t.SA = (float *)take(m * 8 * ns);
     t.N = (float *)take(m * 12 * ns);
     t.idx = (uint8_t *)take(m);
     t.tens = (float *)take(m * 12);
@@ -295,7 +294,7 @@ int run_sweep(const float *u, int H, int W, const mf4d_params *p, const Workspac
         fused = fused && sweep_engine(taps[k]) == kSweepFused;
     }
     auto launch = [&](int k, hipStream_t st) {
-        ScalePlanes planes{w.S + k * m, w.A + k * m, want_n ? w.N + 3 * k * m : nullptr};
+        ScalePlanes planes{w.SA + 2 * k * m, want_n ? w.N + 3 * k * m : nullptr};
         return launch_sweep_scale(u, w.hA, w.hB, w.hC, H, W, taps[k], p->sigmas[k], p->mode, p->beta, planes,
                                   w.smax, st);
     };
@@ -324,8 +323,7 @@ SelectArgs select_args(const mf4d_params *p, const Workspace &w)
 {
     SelectArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.S = w.S;
-    a.A = w.A;
+    a.SA = w.SA;
     a.N = w.N;
     a.ns = p->nscales;
     a.smax_bits = w.smax;
@@ -360,14 +358,13 @@ namespace mf4d {
 // host helpers shared with the batch module (batch.hip)
 int validate_params(int H, int W, const mf4d_params *p) { return validate(H, W, p); }
 size_t image_workspace_bytes(int H, int W, int ns) { return layout(H, W, ns, nullptr, nullptr); }
-void image_workspace(int H, int W, int ns, char *base, float **hA, float **S, float **A, float **N,
+void image_workspace(int H, int W, int ns, char *base, float **hA, float **SA, float **N,
                      uint8_t **idx, float **tens, float **utmp, unsigned **smax)
 {
     Workspace w;
     layout(H, W, ns, &w, base);
     *hA = w.hA;
-    *S = w.S;
-    *A = w.A;
+    *SA = w.SA;
     *N = w.N;
     *idx = w.idx;
     *tens = w.tens;

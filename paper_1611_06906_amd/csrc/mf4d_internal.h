@@ -37,8 +37,8 @@ struct RhoTaps {
 
 // Per-scale planes written by the scale sweep.
 struct ScalePlanes {
-    float *S;   // [H][W] Frobenius norm of sigma^2 H(u_sigma)
-    float *A;   // [H][W] blob factor exp(-R_B^2 / 2 beta^2), 0 if the sign test fails
+    float *SA;  // [H][W][2] per pixel: Frobenius norm S of sigma^2 H(u_sigma), blob factor
+                //   exp(-R_B^2 / 2 beta^2) (0 if the sign test fails)
     float *N;   // [H][W][3] H(u_sigma) / sqrt(1 + |grad u_sigma|) per pixel, or nullptr
 };
 
@@ -80,8 +80,7 @@ hipError_t launch_copy_f32(const float *src, float *dst, size_t n, hipStream_t s
 //   hrho    != nullptr: write H_rho
 //   coef    != nullptr: write the compact tensor planes (m, al, be) of H_rho
 struct SelectArgs {
-    const float *S;      // [ns][H][W]
-    const float *A;      // [ns][H][W]
+    const float *SA;     // [ns][H][W][2]: S and the blob factor per pixel
     const float *N;      // [ns][H][W][3]
     int ns;
     const unsigned *smax_bits;

@@ -23,11 +23,11 @@ __global__ __launch_bounds__(256) void hpass_kernel(const float *__restrict__ u,
 template <int MODE>
 __global__ __launch_bounds__(256) void vpass_kernel(const float *__restrict__ A, const float *__restrict__ B,
                                                     const float *__restrict__ C, int H, int W, WinTaps t,
-                                                    float sigma2, float inv2beta2, float *__restrict__ So,
-                                                    float *__restrict__ Ao, float *__restrict__ No,
+                                                    float sigma2, float inv2beta2, float *__restrict__ SA,
+                                                    float *__restrict__ No,
                                                     unsigned *__restrict__ smax_bits)
 {
-    const float v = vpass_tile<MODE>(A, B, C, H, W, t, sigma2, inv2beta2, So, Ao, No, blockIdx.x * 64,
+    const float v = vpass_tile<MODE>(A, B, C, H, W, t, sigma2, inv2beta2, SA, No, blockIdx.x * 64,
                                      blockIdx.y * 64);
     block_max_to(v, smax_bits);
 }
@@ -49,8 +49,8 @@ template <int NC>
 __global__ __launch_bounds__(256) void vpass_mfma_kernel(const float *__restrict__ A, const float *__restrict__ B,
                                                          const float *__restrict__ C, int H, int W, WinTaps t,
                                                          float sigma2, float inv2beta2, int mode,
-                                                         float *__restrict__ So, float *__restrict__ Ao,
-                                                         float *__restrict__ No, unsigned *__restrict__ smax_bits,
+                                                         float *__restrict__ SA, float *__restrict__ No,
+                                                         unsigned *__restrict__ smax_bits,
                                                          int segs, int seg_rows, int nblk, int per_xcd)
 {
     extern __shared__ f4 lds4[];
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(256) void vpass_mfma_kernel(const float *__restrict
     if (b >= nblk) return;
     const int strip = b / segs, seg = b - strip * segs;
     const int ys = seg * seg_rows, ye = min(H, ys + seg_rows);
-    const float v = vpass_mfma_tile<NC>(A, B, C, H, W, t, sigma2, inv2beta2, mode, So, Ao, No, strip * kVMW, ys, ye,
+    const float v = vpass_mfma_tile<NC>(A, B, C, H, W, t, sigma2, inv2beta2, mode, SA, No, strip * kVMW, ys, ye,
                                         (float *)lds4);
     block_max_to(v, smax_bits);
 }
@@ -66,8 +66,8 @@ __global__ __launch_bounds__(256) void vpass_mfma_kernel(const float *__restrict
 template <int NC>
 __global__ __launch_bounds__(256, 2) void sweep_fused_kernel(const float *__restrict__ u, int H, int W, WinTaps t,
                                                           float sigma2, float inv2beta2, int mode,
-                                                          float *__restrict__ So, float *__restrict__ Ao,
-                                                          float *__restrict__ No, unsigned *__restrict__ smax_bits,
+                                                          float *__restrict__ SA, float *__restrict__ No,
+                                                          unsigned *__restrict__ smax_bits,
                                                           int segs, int seg_rows, int nblk, int per_xcd)
 {
     extern __shared__ f4 lds4[];
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256, 2) void sweep_fused_kernel(const float *__rest
     if (b >= nblk) return;
     const int strip = b / segs, seg = b - strip * segs;
     const int ys = seg * seg_rows, ye = min(H, ys + seg_rows);
-    const float v = sweep_fused_tile<NC>(u, H, W, t, sigma2, inv2beta2, mode, So, Ao, No, strip * kVMW, ys, ye,
+    const float v = sweep_fused_tile<NC>(u, H, W, t, sigma2, inv2beta2, mode, SA, No, strip * kVMW, ys, ye,
                                          (float *)lds4);
     block_max_to(v, smax_bits);
 }
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256) void argmax_kernel(SelectArgs a, size_t plane)
         if (best >= a.ns) best = a.ns - 1;   // out-of-range caller indices are clamped
     } else {
         float bv;
-        best = argmax_px(a.S, a.A, a.ns, plane, o, c, &bv);
+        best = argmax_px(a.SA, a.ns, plane, o, c, &bv);
         if (a.idx_out) a.idx_out[o] = (uint8_t)best;
         if (a.vmax_out) a.vmax_out[o] = bv;
     }
@@ -178,7 +178,7 @@ hipError_t launch_sweep_scale(const float *u, float *hA, float *hB, float *hC, i
 #define MF4D_FU(NC)                                                                                           \
     case NC:                                                                                                  \
         hipLaunchKernelGGL(sweep_fused_kernel<NC>, dim3(8 * per), dim3(256), fused_lds(NC), s, u, H, W, t, sigma2, \
-                           inv2beta2, mode, out.S, out.A, out.N, smax_bits, segs, seg_rows, nblk, per);      \
+                           inv2beta2, mode, out.SA, out.N, smax_bits, segs, seg_rows, nblk, per);      \
         break;
         MF4D_FU(2) MF4D_FU(3) MF4D_FU(4) MF4D_FU(5) MF4D_FU(6) MF4D_FU(7) MF4D_FU(8)
 #undef MF4D_FU
@@ -238,7 +238,7 @@ hipError_t launch_vpass(const float *A, const float *B, const float *C, int H, i
 #define MF4D_VM(NC)                                                                                            \
     case NC:                                                                                                   \
         hipLaunchKernelGGL(vpass_mfma_kernel<NC>, dim3(8 * per), dim3(256), vpass_mfma_lds(NC), s, A, B, C, H, W, \
-                           t, sigma2, inv2beta2, mode, out.S, out.A, out.N, smax_bits, segs, seg_rows, nblk, per); \
+                           t, sigma2, inv2beta2, mode, out.SA, out.N, smax_bits, segs, seg_rows, nblk, per); \
         break;
             MF4D_VM(2) MF4D_VM(3) MF4D_VM(4) MF4D_VM(5) MF4D_VM(6) MF4D_VM(7) MF4D_VM(8) MF4D_VM(9)
 #undef MF4D_VM
@@ -250,15 +250,15 @@ hipError_t launch_vpass(const float *A, const float *B, const float *C, int H, i
     switch (mode) {
     case MF4D_RIDGE:
         hipLaunchKernelGGL(vpass_kernel<MF4D_RIDGE>, grid, dim3(256), 0, s, A, B, C, H, W, t, sigma2,
-                           inv2beta2, out.S, out.A, out.N, smax_bits);
+                           inv2beta2, out.SA, out.N, smax_bits);
         break;
     case MF4D_VALLEY:
         hipLaunchKernelGGL(vpass_kernel<MF4D_VALLEY>, grid, dim3(256), 0, s, A, B, C, H, W, t, sigma2,
-                           inv2beta2, out.S, out.A, out.N, smax_bits);
+                           inv2beta2, out.SA, out.N, smax_bits);
         break;
     default:
         hipLaunchKernelGGL(vpass_kernel<MF4D_BOTH>, grid, dim3(256), 0, s, A, B, C, H, W, t, sigma2,
-                           inv2beta2, out.S, out.A, out.N, smax_bits);
+                           inv2beta2, out.SA, out.N, smax_bits);
         break;
     }
     return hipGetLastError();

@@ -161,8 +161,8 @@ __device__ __forceinline__ void hpass_mfma_tile(const float *__restrict__ u, flo
 template <int NC>
 __device__ __forceinline__ float vpass_mfma_tile(const float *__restrict__ A, const float *__restrict__ B,
                                                  const float *__restrict__ C, int H, int W, const WinTaps &t,
-                                                 float sigma2, float inv2beta2, int mode, float *__restrict__ So,
-                                                 float *__restrict__ Ao, float *__restrict__ No, int x0, int ys,
+                                                 float sigma2, float inv2beta2, int mode, float *__restrict__ SA,
+                                                 float *__restrict__ No, int x0, int ys,
                                                  int ye, float *lds)
 {
 #pragma clang fp contract(off)   // fused multiply-adds are written out
@@ -250,7 +250,7 @@ __device__ __forceinline__ float vpass_mfma_tile(const float *__restrict__ A, co
             const int y = y0 + 4 * kq + i;
             if (x < W && y < ye) {
                 const float Sv = vessel_store_mode(mode, cuxx[i], cuxy[i], cuyy[i], cux[i] + bsum, cuy[i], sigma2,
-                                                   inv2beta2, So, Ao, No, (size_t)y * W + x, plane);
+                                                   inv2beta2, SA, No, (size_t)y * W + x, plane);
                 smax = fmaxf(smax, Sv);
             }
         }
@@ -274,8 +274,8 @@ __host__ __device__ constexpr size_t fused_lds(int nc) { return sizeof(float) * 
 
 template <int NC>
 __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, int H, int W, const WinTaps &t,
-                                                  float sigma2, float inv2beta2, int mode, float *__restrict__ So,
-                                                  float *__restrict__ Ao, float *__restrict__ No, int x0, int ys,
+                                                  float sigma2, float inv2beta2, int mode, float *__restrict__ SA,
+                                                  float *__restrict__ No, int x0, int ys,
                                                   int ye, float *lds)
 {
 #pragma clang fp contract(off)   // fused multiply-adds are written out
@@ -416,7 +416,7 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
             const int y = y0 + 4 * kq + i;
             if (x < W && y < ye) {
                 const float Sv = vessel_store_mode(mode, cuxx[i], cuxy[i], cuyy[i], cux[i] + bsum, cuy[i], sigma2,
-                                                   inv2beta2, So, Ao, No, (size_t)y * W + x, plane);
+                                                   inv2beta2, SA, No, (size_t)y * W + x, plane);
                 smax = fmaxf(smax, Sv);
             }
         }

@@ -115,8 +115,8 @@ __device__ __forceinline__ void hpass_tile(const float *__restrict__ u, float *_
 // stored at pixel o. Returns S.
 template <int MODE>
 __device__ __forceinline__ float vessel_store(float uxx, float uxy, float uyy, float gx, float gy, float sigma2,
-                                              float inv2beta2, float *__restrict__ So, float *__restrict__ Ao,
-                                              float *__restrict__ No, size_t o, size_t plane)
+                                              float inv2beta2, float *__restrict__ SA, float *__restrict__ No,
+                                              size_t o, size_t plane)
 {
 #pragma clang fp contract(off)   // fused multiply-adds are written out
     // The hardware square root, reciprocal, reciprocal square root and 2^x
@@ -137,8 +137,7 @@ __device__ __forceinline__ float vessel_store(float uxx, float uxy, float uyy, f
     const float rb = (am - r) * __builtin_amdgcn_rcpf(big);   // |R_B| = |nu~1| / |nu~2|
     const float e = __builtin_amdgcn_exp2f(-(rb * rb) * inv2beta2 * kLog2e);
     const float blob = pass ? e : 0.f;
-    So[o] = Sv;
-    Ao[o] = blob;
+    *(float2 *)(SA + 2 * o) = make_float2(Sv, blob);   // S and the blob factor per pixel: [H][W][2]
     if (No) {
         const float f = __builtin_amdgcn_rsqf(1.f + __builtin_amdgcn_sqrtf(fmaf(gx, gx, gy * gy)));
         No[3 * o] = uxx * f;   // N is stored per pixel: [H][W][3]
@@ -175,13 +174,11 @@ __device__ __forceinline__ VesselPx vessel_px(int mode, float uxx, float uxy, fl
 }
 
 __device__ __forceinline__ float vessel_store_mode(int mode, float uxx, float uxy, float uyy, float gx, float gy,
-                                                   float sigma2, float inv2beta2, float *__restrict__ So,
-                                                   float *__restrict__ Ao, float *__restrict__ No, size_t o,
-                                                   size_t plane)
+                                                   float sigma2, float inv2beta2, float *__restrict__ SA,
+                                                   float *__restrict__ No, size_t o, size_t plane)
 {
     const VesselPx v = vessel_px(mode, uxx, uxy, uyy, gx, gy, sigma2, inv2beta2);
-    So[o] = v.S;
-    Ao[o] = v.blob;
+    *(float2 *)(SA + 2 * o) = make_float2(v.S, v.blob);
     if (No) {
         No[3 * o] = v.n0;   // N is stored per pixel: [H][W][3]
         No[3 * o + 1] = v.n1;
@@ -197,8 +194,8 @@ __device__ __forceinline__ float vessel_store_mode(int mode, float uxx, float ux
 template <int MODE>
 __device__ __forceinline__ float vpass_tile(const float *__restrict__ A, const float *__restrict__ B,
                                             const float *__restrict__ C, int H, int W, const WinTaps &t,
-                                            float sigma2, float inv2beta2, float *__restrict__ So,
-                                            float *__restrict__ Ao, float *__restrict__ No, int x0, int ty0)
+                                            float sigma2, float inv2beta2, float *__restrict__ SA,
+                                            float *__restrict__ No, int x0, int ty0)
 {
 #pragma clang fp contract(off)   // fused multiply-adds are written out
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -250,7 +247,7 @@ __device__ __forceinline__ float vpass_tile(const float *__restrict__ A, const f
         const int y = y0 + k;
         if (x < W && y < H) {
             const float Sv = vessel_store<MODE>(uxx[k], uxy[k], uyy[k], ux[k] + bsum, uy[k], sigma2, inv2beta2,
-                                                So, Ao, No, (size_t)y * W + x, plane);
+                                                SA, No, (size_t)y * W + x, plane);
             smax = fmaxf(smax, Sv);
         }
     }
@@ -283,25 +280,22 @@ __device__ __forceinline__ float frangi_v(float S, float blob, float inv2c2)
 // argmax over scales at pixel o (smallest index among equal maxima); writes
 // the maximum to *vbest. c = 0 makes every V zero (index 0). Every scale's
 // loads are issued before the comparisons.
-__device__ __forceinline__ int argmax_px(const float *__restrict__ S, const float *__restrict__ A, int ns,
-                                         size_t plane, size_t o, float c, float *vbest)
+__device__ __forceinline__ int argmax_px(const float *__restrict__ SA, int ns, size_t plane, size_t o, float c,
+                                         float *vbest)
 {
     int best = 0;
     float bv = 0.f;
     if (c > 0.f) {
-        float sv[MF4D_MAX_SCALES], av[MF4D_MAX_SCALES];
+        float2 sa[MF4D_MAX_SCALES];   // (S, blob) of every scale, loaded before the comparisons
 #pragma unroll
         for (int s = 0; s < MF4D_MAX_SCALES; ++s)
-            if (s < ns) {
-                sv[s] = S[s * plane + o];
-                av[s] = A[s * plane + o];
-            }
+            if (s < ns) sa[s] = *(const float2 *)(SA + 2 * (s * plane + o));
         const float inv2c2 = 1.f / (2.f * c * c);
-        bv = frangi_v(sv[0], av[0], inv2c2);
+        bv = frangi_v(sa[0].x, sa[0].y, inv2c2);
 #pragma unroll
         for (int s = 1; s < MF4D_MAX_SCALES; ++s)
             if (s < ns) {
-                const float v = frangi_v(sv[s], av[s], inv2c2);
+                const float v = frangi_v(sa[s].x, sa[s].y, inv2c2);
                 if (v > bv) { bv = v; best = s; }
             }
     }
