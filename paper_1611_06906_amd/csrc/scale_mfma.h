@@ -285,11 +285,13 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
     constexpr int PL = kVMW * P;
     constexpr int UW = K + 16;        // staged u columns x0 - R .. x0 - R + UW - 1
     constexpr int UP = UW + 4;        // staged row pitch (4 mod 8 floats)
-    constexpr int NU = 32 * UW / 256; // staged values per thread
+    constexpr int NG = UW / 16;       // 16-column groups of a staged row
+    constexpr int NU = 2 * NG;        // staged values per thread: row 16 h + tid / 16, column 16 g + tid % 16
     float *ring = lds, *us = lds + 3 * PL;
     const int R = t.R;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int n = lane & 15, kq = lane >> 4;
+    const int tr = tid >> 4, tc = tid & 15;               // staging: row and column of value 0
     const int cb = 16 * (wv & 1), rb = 16 * (wv >> 1);   // this wave's block: columns cb.., rows rb..
     const bool xin = (x0 - R >= 0) && (x0 - R + UW <= W);
     float ag[NC][4], a1[NC][4], a2[NC][4];
@@ -297,25 +299,35 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
     toeplitz_lane<NC>(t.d1, R, a1);
     toeplitz_lane<NC>(t.d2, R, a2);
     const float gsum = t.gsum;
-    // 32 rows of u from row r0 on (reflected), all loads before any LDS store
+    // 32 rows of u from row r0 on (reflected), all loads before any LDS store;
+    // value 2 g + h is row r0 + 16 h + tr, column x0 - R + 16 g + tc, so inside
+    // the image every load is one base address plus a constant
     auto load_u = [&](int r0, float (&v)[NU]) {
-        const bool yin = r0 >= 0 && r0 + 32 <= H;
+        if (xin && r0 >= 0 && r0 + 32 <= H) {   // uniform over the block
+            const float *p0 = u + (size_t)(r0 + tr) * W + (x0 - R + tc);
+            const float *p1 = p0 + (size_t)16 * W;
 #pragma unroll
-        for (int it = 0; it < NU; ++it) {
-            const int e = tid + 256 * it;
-            const int r = e / UW, c = e - r * UW;
-            const int gy = yin ? r0 + r : reflect_any(r0 + r, H);
-            const int gx = x0 - R + c;
-            v[it] = u[(size_t)gy * W + (xin ? gx : reflect_any(gx, W))];
+            for (int g = 0; g < NG; ++g) {
+                v[2 * g] = p0[16 * g];
+                v[2 * g + 1] = p1[16 * g];
+            }
+        } else {
+#pragma unroll
+            for (int g = 0; g < NG; ++g)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int gy = reflect_any(r0 + 16 * h + tr, H);
+                    const int gx = reflect_any(x0 - R + 16 * g + tc, W);
+                    v[2 * g + h] = u[(size_t)gy * W + gx];
+                }
         }
     };
     auto store_u = [&](const float (&v)[NU]) {
+        float *q = us + tr * UP + tc;
 #pragma unroll
-        for (int it = 0; it < NU; ++it) {
-            const int e = tid + 256 * it;
-            const int r = e / UW, c = e - r * UW;
-            us[r * UP + c] = v[it];
-        }
+        for (int g = 0; g < NG; ++g)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) q[16 * h * UP + 16 * g] = v[2 * g + h];
     };
     // horizontal products of this wave's block of the staged rows; lane holds
     // columns cb + 4 kq + i of staged row rb + n
