@@ -293,22 +293,24 @@ int run_sweep(const float *u, int H, int W, const mf4d_params *p, const Workspac
         make_taps(p->sigmas[k], &taps[k]);
         fused = fused && sweep_engine(taps[k]) == kSweepFused;
     }
+    ForkStreams *fs = (fused && p->nscales > 1) ? fork_streams() : nullptr;
     auto launch = [&](int k, hipStream_t st) {
         ScalePlanes planes{w.SA + 2 * k * m, want_n ? w.N + 3 * k * m : nullptr};
         return launch_sweep_scale(u, w.hA, w.hB, w.hC, H, W, taps[k], p->sigmas[k], p->mode, p->beta, planes,
-                                  w.smax, st);
+                                  w.smax, fs != nullptr, st);
     };
-    ForkStreams *fs = (fused && p->nscales > 1) ? fork_streams() : nullptr;
     if (!fs) {
         for (int k = 0; k < p->nscales; ++k) CHECK_HIP(launch(k, s));
         return MF4D_OK;
     }
-    // the largest scales (longest, matrix-core bound) first, spread over the
-    // caller's stream and the side streams so that small, memory-bound
-    // scales overlap them
+    // scales in the order largest, smallest, second largest, second smallest,
+    // ..., spread round-robin over the caller's stream and the side streams,
+    // so that each matrix-core bound large scale runs beside a memory-bound
+    // small one (the scale index order is that of the sigmas)
     CHECK_HIP(hipEventRecord(fs->fork, s));
     for (int i = 0; i < kForkStreams; ++i) CHECK_HIP(hipStreamWaitEvent(fs->side[i], fs->fork, 0));
-    for (int k = p->nscales - 1, j = 0; k >= 0; --k, ++j) {
+    for (int j = 0, lo = 0, hi = p->nscales - 1; j < p->nscales; ++j) {
+        const int k = j % 2 == 0 ? hi-- : lo++;
         const int lane = j % (kForkStreams + 1);
         CHECK_HIP(launch(k, lane == 0 ? s : fs->side[lane - 1]));
     }

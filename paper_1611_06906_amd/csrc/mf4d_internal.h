@@ -61,12 +61,13 @@ int sweep_chunks(const WinTaps &t);
 enum { kSweepFused = 0, kSweepSplit = 1, kSweepValu = 2 };
 int sweep_engine(const WinTaps &t);
 // Both passes of one scale (the planes hA, hB, hC are used by the split and
-// register-window forms only).
+// register-window forms only); `shared`: other scales run concurrently.
 hipError_t launch_sweep_scale(const float *u, float *hA, float *hB, float *hC, int H, int W, const WinTaps &t,
-                              float sigma, int mode, float beta, ScalePlanes out, unsigned *smax_bits, hipStream_t s);
+                              float sigma, int mode, float beta, ScalePlanes out, unsigned *smax_bits, bool shared,
+                              hipStream_t s);
 // Rows per workgroup of the single-image fused kernel (MF4D_VSEG_ROWS
-// overrides it; values do not change).
-int fused_seg_rows(int H, int W, int nc);
+// overrides it; values do not change). `shared`: other scales run concurrently.
+int fused_seg_rows(int H, int W, int nc, bool shared);
 // Rows per workgroup of the single-image matrix-core vertical pass (the
 // environment variable MF4D_VSEG_ROWS overrides it; values do not change).
 int vpass_seg_rows(int H, int W);

@@ -146,22 +146,26 @@ int sweep_engine(const WinTaps &t)
     return nc <= kFusedMaxChunks ? kSweepFused : kSweepSplit;
 }
 
-int fused_seg_rows(int H, int W, int nc)
+int fused_seg_rows(int H, int W, int nc, bool shared)
 {
     if (const char *e = std::getenv("MF4D_VSEG_ROWS")) {   // any multiple of the step gives the same values
         const int r = std::atoi(e);
         if (r > 0) return kVMStep * ((r + kVMStep - 1) / kVMStep);
     }
     // one round of workgroups at the kernel's occupancy (workgroups per CU
-    // by its registers and LDS); longer strips amortise each one's first window
-    const int per_cu = nc <= 3 ? 4 : (nc == 4 ? 3 : 2);
+    // by its registers and LDS); longer strips amortise each one's first
+    // window. When the scales of a cycle run concurrently, the kernels bound
+    // by the matrix cores (6 chunks or more) take one workgroup per CU, which
+    // leaves registers and LDS on every CU to the memory-bound small scales.
+    const int per_cu = (shared && nc >= 6) ? 1 : nc <= 3 ? 4 : (nc == 4 ? 3 : 2);
     const int strips = (W + kVMW - 1) / kVMW, steps = (H + kVMStep - 1) / kVMStep;
     const int segs = std::max(1, std::min(steps, (256 * per_cu + strips - 1) / strips));
     return kVMStep * ((steps + segs - 1) / segs);
 }
 
 hipError_t launch_sweep_scale(const float *u, float *hA, float *hB, float *hC, int H, int W, const WinTaps &t,
-                              float sigma, int mode, float beta, ScalePlanes out, unsigned *smax_bits, hipStream_t s)
+                              float sigma, int mode, float beta, ScalePlanes out, unsigned *smax_bits, bool shared,
+                              hipStream_t s)
 {
     if (sweep_engine(t) != kSweepFused) {
         hipError_t e = launch_hpass(u, hA, hB, hC, H, W, t, s);
@@ -170,7 +174,7 @@ hipError_t launch_sweep_scale(const float *u, float *hA, float *hB, float *hC, i
     }
     const float sigma2 = sigma * sigma;
     const float inv2beta2 = 1.f / (2.f * beta * beta);
-    const int seg_rows = fused_seg_rows(H, W, sweep_chunks(t));
+    const int seg_rows = fused_seg_rows(H, W, sweep_chunks(t), shared);
     const int segs = (H + seg_rows - 1) / seg_rows;
     const int nblk = segs * ((W + kVMW - 1) / kVMW);
     const int per = (nblk + 7) / 8;

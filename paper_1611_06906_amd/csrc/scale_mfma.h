@@ -387,10 +387,13 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
     const float *rA = ring + col * P, *rB = rA + PL, *rC = rA + 2 * PL;
     const size_t plane = (size_t)H * W;
     float smax = 0.f;
+    // u rows entering the window two steps ahead: loaded at the end of the
+    // previous step (loop-carried), so they are in flight during the epilogue
+    // and this step's products (loaded even when unused)
+    float v[NU];
+    load_u(ys + kVMStep - R + RS, v);
     for (int yb = ys; yb < ye; yb += kVMStep) {
         const bool more = yb + kVMStep < ye;
-        float v[NU];   // u rows entering the window two steps ahead (loaded even when unused)
-        load_u(yb + kVMStep - R + RS, v);
         // vertical products of this step's window
         const int y0 = yb + rb;
         const int s0 = (y0 - ys) % RS;           // slot of row y0 - R
@@ -421,6 +424,7 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
             ring_put((yb - ys + rb + n) % RS, hg, h1, h2);   // slots of rows yb - R .. yb - R + 31
             store_u(v);
         }
+        load_u(yb + 2 * kVMStep - R + RS, v);
         // this lane holds rows y0 + 4 kq + i of column x
         const float bsum = bref * gsum;
 #pragma unroll
