@@ -11,7 +11,10 @@
 // all three filters (Gaussian, central difference, second difference) in
 // registers. The order of the K terms is free, so lane group q supplies the
 // four consecutive inputs 4q .. 4q+3 of each 16-input chunk over the four
-// products of the chunk, which one 16-byte LDS read delivers.
+// products of the chunk, which one 16-byte LDS read delivers. The last chunk
+// is taken in contiguous 4-input slices instead (lane group q supplies input
+// 4j + q of slice j): inputs from 16 + 2R on meet zero taps in every row, so
+// the slices made only of them are skipped (last_slices).
 //
 // Inputs are shifted by the value at the block's first output before the
 // products (as in the register-window passes), so locally constant lines
@@ -53,7 +56,8 @@ __device__ __forceinline__ f4 mfma_f32(float a, float b, f4 c)
 }
 
 // This lane's entries of the Toeplitz slices: a[c][j] = tap[k - m] for row
-// m = lane % 16 and input k = 16c + 4(lane / 16) + j (zero outside 0..2R).
+// m = lane % 16 and input k = 16c + 4(lane / 16) + j (zero outside 0..2R);
+// in the last chunk k = 16c + 4j + lane / 16.
 template <int NC>
 __device__ __forceinline__ void toeplitz_lane(const float *tap, int R, float (&a)[NC][4])
 {
@@ -62,9 +66,18 @@ __device__ __forceinline__ void toeplitz_lane(const float *tap, int R, float (&a
     for (int c = 0; c < NC; ++c)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int t = 16 * c + 4 * kq + j - m;
+            const int t = (c < NC - 1 ? 16 * c + 4 * kq + j : 16 * c + 4 * j + kq) - m;
             a[c][j] = (t >= 0 && t <= 2 * R) ? tap[t] : 0.f;
         }
+}
+
+// Slices of the last chunk that hold inputs inside the band (0..4): the
+// chunk's inputs 16 + 2R - 16 (NC - 1) on have zero taps for every row.
+template <int NC>
+__host__ __device__ __forceinline__ int last_slices(int R)
+{
+    const int z = 16 + 2 * R - 16 * (NC - 1);
+    return z <= 0 ? 0 : (z >= 16 ? 4 : (z + 3) / 4);
 }
 
 // ------------------------------------------------------------------ horizontal
@@ -108,6 +121,7 @@ __device__ __forceinline__ void hpass_mfma_tile(const float *__restrict__ u, flo
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int n = lane & 15, kq = lane >> 4;
+    const int JL = last_slices<NC>(R);
     const float *row = lds + n * P;   // image row y0 + n
     const int y = y0 + n;
     const float gsum = t.gsum;
@@ -118,7 +132,7 @@ __device__ __forceinline__ void hpass_mfma_tile(const float *__restrict__ u, flo
         const float ref = row[xb + R];       // input at the block's first output
         f4 cg = {0.f, 0.f, 0.f, 0.f}, c1 = cg, c2 = cg;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
+        for (int c = 0; c < NC - 1; ++c) {
             const f4 b = *(const f4 *)(row + xb + 16 * c + 4 * kq) - ref;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -127,6 +141,14 @@ __device__ __forceinline__ void hpass_mfma_tile(const float *__restrict__ u, flo
                 c2 = mfma_f32(a2[c][j], b[j], c2);
             }
         }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (j < JL) {
+                const float b = row[xb + 16 * (NC - 1) + 4 * j + kq] - ref;
+                cg = mfma_f32(ag[NC - 1][j], b, cg);
+                c1 = mfma_f32(a1[NC - 1][j], b, c1);
+                c2 = mfma_f32(a2[NC - 1][j], b, c2);
+            }
         // this lane holds outputs x0 + xb + 4 kq + i of row y
         const int xo = x0 + xb + 4 * kq;
         if (y < H && xo < W) {
@@ -174,6 +196,7 @@ __device__ __forceinline__ float vpass_mfma_tile(const float *__restrict__ A, co
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int n = lane & 15, kq = lane >> 4;
     const int fc = tid & 31, fq = tid >> 5;   // loader: column, quad of rows
+    const int JL = last_slices<NC>(R);
     const size_t fx = (size_t)min(x0 + fc, W - 1);
     float *fA = lds + fc * P;
     float ag[NC][4], a1[NC][4], a2[NC][4];
@@ -222,7 +245,7 @@ __device__ __forceinline__ float vpass_mfma_tile(const float *__restrict__ A, co
         const float aref = rA[sr], bref = rB[sr];
         f4 cuy = {0.f, 0.f, 0.f, 0.f}, cuyy = cuy, cux = cuy, cuxy = cuy, cuxx = cuy;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
+        for (int c = 0; c < NC - 1; ++c) {
             int s = s0 + 16 * c + 4 * kq;
             s = s >= RS ? s - RS : s;
             const f4 va = *(const f4 *)(rA + s) - aref;
@@ -237,6 +260,18 @@ __device__ __forceinline__ float vpass_mfma_tile(const float *__restrict__ A, co
                 cuxx = mfma_f32(ag[c][j], vc[j], cuxx);
             }
         }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (j < JL) {   // last chunk, contiguous slices
+                int s = s0 + 16 * (NC - 1) + 4 * j + kq;
+                s = s >= RS ? s - RS : s;
+                const float va = rA[s] - aref, vb = rB[s] - bref, vc = rC[s];
+                cuy = mfma_f32(a1[NC - 1][j], va, cuy);
+                cuyy = mfma_f32(a2[NC - 1][j], va, cuyy);
+                cux = mfma_f32(ag[NC - 1][j], vb, cux);
+                cuxy = mfma_f32(a1[NC - 1][j], vb, cuxy);
+                cuxx = mfma_f32(ag[NC - 1][j], vc, cuxx);
+            }
         if (more) {   // the next step's rows go to the slots no window of this step uses
             const int sn = (yb - ys + K + 16 + 4 * fq) % RS;
             *(f4 *)(fA + sn) = na;
@@ -292,6 +327,7 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int n = lane & 15, kq = lane >> 4;
     const int tr = tid >> 4, tc = tid & 15;               // staging: row and column of value 0
+    const int JL = last_slices<NC>(R);
     const int cb = 16 * (wv & 1), rb = 16 * (wv >> 1);   // this wave's block: columns cb.., rows rb..
     const bool xin = (x0 - R >= 0) && (x0 - R + UW <= W);
     float ag[NC][4], a1[NC][4], a2[NC][4];
@@ -339,7 +375,7 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
         h1 = hg;
         h2 = hg;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
+        for (int c = 0; c < NC - 1; ++c) {
             const f4 b = *(const f4 *)(row + cb + 16 * c + 4 * kq) - ref;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -348,6 +384,14 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
                 h2 = mfma_f32(a2[c][j], b[j], h2);
             }
         }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (j < JL) {   // last chunk, contiguous slices
+                const float b = row[cb + 16 * (NC - 1) + 4 * j + kq] - ref;
+                hg = mfma_f32(ag[NC - 1][j], b, hg);
+                h1 = mfma_f32(a1[NC - 1][j], b, h1);
+                h2 = mfma_f32(a2[NC - 1][j], b, h2);
+            }
         hg = hg + ref * gsum;
     };
     auto ring_put = [&](int slot, const f4 &hg, const f4 &h1, const f4 &h2) {
@@ -401,7 +445,7 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
         const float aref = rA[sr], bref = rB[sr];
         f4 cuy = {0.f, 0.f, 0.f, 0.f}, cuyy = cuy, cux = cuy, cuxy = cuy, cuxx = cuy;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
+        for (int c = 0; c < NC - 1; ++c) {
             int s = s0 + 16 * c + 4 * kq;
             s = s >= RS ? s - RS : s;
             const f4 va = *(const f4 *)(rA + s) - aref;
@@ -416,6 +460,18 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
                 cuxx = mfma_f32(ag[c][j], vc[j], cuxx);
             }
         }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (j < JL) {   // last chunk, contiguous slices
+                int s = s0 + 16 * (NC - 1) + 4 * j + kq;
+                s = s >= RS ? s - RS : s;
+                const float va = rA[s] - aref, vb = rB[s] - bref, vc = rC[s];
+                cuy = mfma_f32(a1[NC - 1][j], va, cuy);
+                cuyy = mfma_f32(a2[NC - 1][j], va, cuyy);
+                cux = mfma_f32(ag[NC - 1][j], vb, cux);
+                cuxy = mfma_f32(a1[NC - 1][j], vb, cuxy);
+                cuxx = mfma_f32(ag[NC - 1][j], vc, cuxx);
+            }
         // horizontal products of the rows entering the next window
         f4 hg, h1, h2;
         hpass_block(hg, h1, h2);
