@@ -176,21 +176,27 @@ __device__ __forceinline__ void fed_stream_wave2(const float *__restrict__ u, fl
     const size_t plane = (size_t)H * W;
     const int xca = min(max(xa, 0), W - 1), xcb = min(max(xb, 0), W - 1);
 
-    // u_k rows, k < S: column a, its left neighbour, column b, its right neighbour
-    float ua[S][3], ual[S][3], ub[S][3], ubr[S][3];
+    // u_k rows, k < S, of column a and column b; the outer neighbours (column
+    // b of the lane to the left, column a of the lane to the right) are lane
+    // shifts taken where they are used, which the compiler folds into the adds
+    float ua[S][3], ub[S][3];
     float txa[S][3], tya[S][3], tza[S][3];   // T_k rows (xx, xy, yy), column a
     float txb[S][3], tyb[S][3], tzb[S][3];   // column b
-    float cma[NC], caa[NC], cba[NC], cmb[NC], cab[NC], cbb[NC];
+    // tensor rows: m, be and the sums m + al, m - al and be / 2 the flux uses,
+    // formed once per pixel (the same roundings as forming them per substep)
+    float cma[NC], cea[NC], cpa[NC], cqa[NC], cha[NC];
+    float cmb[NC], ceb[NC], cpb[NC], cqb[NC], chb[NC];
     float qa0[D], qa1[D], qa2[D], qa3[D], qb0[D], qb1[D], qb2[D], qb3[D];   // rows in flight
 #pragma unroll
     for (int k = 0; k < S; ++k)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            ua[k][j] = ual[k][j] = ub[k][j] = ubr[k][j] = 0.f;
+            ua[k][j] = ub[k][j] = 0.f;
             txa[k][j] = tya[k][j] = tza[k][j] = txb[k][j] = tyb[k][j] = tzb[k][j] = 0.f;
         }
 #pragma unroll
-    for (int j = 0; j < NC; ++j) cma[j] = caa[j] = cba[j] = cmb[j] = cab[j] = cbb[j] = 0.f;
+    for (int j = 0; j < NC; ++j)
+        cma[j] = cea[j] = cpa[j] = cqa[j] = cha[j] = cmb[j] = ceb[j] = cpb[j] = cqb[j] = chb[j] = 0.f;
 
     const int y0 = ys - 2 * S;          // first row loaded
     const int y1 = ye + 2 * S;          // one past the last row needed
@@ -209,17 +215,20 @@ __device__ __forceinline__ void fed_stream_wave2(const float *__restrict__ u, fl
 #pragma unroll
     for (int d = 0; d < D; ++d) issue(y0 + d, d);
 
-    // flux of one column from its u_{k-1} rows (left, centre, right) and tensor
-    auto flux = [&](float lo, float co, float ro, float ln, float cn, float rn, float lc, float cc, float rc,
-                    float mb, float al, float be, float &txx, float &txy, float &tyy) {
+    // flux of one column from its u_{k-1} rows: the sums of the left and
+    // right neighbours of the old, centre and new rows (lco, lcn, lcc: left
+    // old + right new, left new + right old, left + right of the centre row),
+    // the centre column's old, centre and new values, and the tensor
+    auto flux = [&](float lorn, float lnro, float lcrc, float co, float cc, float cn, float mb, float be,
+                    float mpa, float mma, float beh, float &txx, float &txy, float &tyy) {
 #pragma clang fp contract(off)
-        const float hxx = fmaf(-2.f, cc, lc + rc);
+        const float hxx = fmaf(-2.f, cc, lcrc);
         const float hyy = fmaf(-2.f, cc, co + cn);
-        const float hxy = 0.25f * ((lo + rn) - (ln + ro));
+        const float hxy = 0.25f * (lorn - lnro);
         const float bxy = be * hxy;
-        txx = fmaf(mb + al, hxx, bxy);
-        txy = fmaf(mb, hxy, (be * 0.5f) * (hxx + hyy));
-        tyy = fmaf(mb - al, hyy, bxy);
+        txx = fmaf(mpa, hxx, bxy);
+        txy = fmaf(mb, hxy, beh * (hxx + hyy));
+        tyy = fmaf(mma, hyy, bxy);
     };
 
     for (int yb = y0; yb < y1; yb += U) {
@@ -233,35 +242,43 @@ __device__ __forceinline__ void fed_stream_wave2(const float *__restrict__ u, fl
             // zero tensor off the interior: the flux T = D h vanishes there
             const bool yint = y >= 1 && y <= H - 2;
             const unsigned ona = mask_of(inta && yint), onb = mask_of(intb && yint);
-            cma[t % NC] = keep(qa1[qs], ona);
-            cmb[t % NC] = keep(qb1[qs], onb);
-            caa[t % NC] = keep(qa2[qs], ona);
-            cab[t % NC] = keep(qb2[qs], onb);
-            cba[t % NC] = keep(qa3[qs], ona);
-            cbb[t % NC] = keep(qb3[qs], onb);
+            {
+                const int ci = t % NC;
+                const float ma = keep(qa1[qs], ona), aa = keep(qa2[qs], ona), ea = keep(qa3[qs], ona);
+                const float mb = keep(qb1[qs], onb), ab = keep(qb2[qs], onb), eb = keep(qb3[qs], onb);
+                cma[ci] = ma;
+                cea[ci] = ea;
+                cpa[ci] = ma + aa;
+                cqa[ci] = ma - aa;
+                cha[ci] = ea * 0.5f;
+                cmb[ci] = mb;
+                ceb[ci] = eb;
+                cpb[ci] = mb + ab;
+                cqb[ci] = mb - ab;
+                chb[ci] = eb * 0.5f;
+            }
             issue(y + D, qs);
             {
                 const int w0 = t % 3;
                 ua[0][w0] = na;
                 ub[0][w0] = nb;
-                ual[0][w0] = from_left(nb);
-                ubr[0][w0] = from_right(na);
             }
 #pragma unroll
             for (int k = 1; k <= S; ++k) {
-                const int q = y - (2 * k - 1);
                 const int wn = (t - 2 * (k - 1) + 300) % 3;        // u_{k-1} row q+1
                 const int wc = (t - 2 * (k - 1) - 1 + 300) % 3;    // row q
                 const int wo = (t - 2 * (k - 1) - 2 + 300) % 3;    // row q-1
                 const int ci = (t - (2 * k - 1) + 2 * NC * 50) % NC;
                 const int tw = (t - (2 * k - 1) + 300) % 3;
-                // column a: left neighbour ual, right neighbour ub; column b: left ua, right ubr
-                flux(ual[k - 1][wo], ua[k - 1][wo], ub[k - 1][wo], ual[k - 1][wn], ua[k - 1][wn], ub[k - 1][wn],
-                     ual[k - 1][wc], ua[k - 1][wc], ub[k - 1][wc], cma[ci], caa[ci], cba[ci],
-                     txa[k - 1][tw], tya[k - 1][tw], tza[k - 1][tw]);
-                flux(ua[k - 1][wo], ub[k - 1][wo], ubr[k - 1][wo], ua[k - 1][wn], ub[k - 1][wn], ubr[k - 1][wn],
-                     ua[k - 1][wc], ub[k - 1][wc], ubr[k - 1][wc], cmb[ci], cab[ci], cbb[ci],
-                     txb[k - 1][tw], tyb[k - 1][tw], tzb[k - 1][tw]);
+                const float *pa = ua[k - 1], *pb = ub[k - 1];
+                // column a: left neighbour from_left(b), right neighbour b;
+                // column b: left neighbour a, right neighbour from_right(a)
+                flux(from_left(pb[wo]) + pb[wn], from_left(pb[wn]) + pb[wo], from_left(pb[wc]) + pb[wc], pa[wo],
+                     pa[wc], pa[wn], cma[ci], cea[ci], cpa[ci], cqa[ci], cha[ci], txa[k - 1][tw], tya[k - 1][tw],
+                     tza[k - 1][tw]);
+                flux(pa[wo] + from_right(pa[wn]), pa[wn] + from_right(pa[wo]), pa[wc] + from_right(pa[wc]), pb[wo],
+                     pb[wc], pb[wn], cmb[ci], ceb[ci], cpb[ci], cqb[ci], chb[ci], txb[k - 1][tw], tyb[k - 1][tw],
+                     tzb[k - 1][tw]);
                 // u_k at row p = y - 2k
                 const int p = y - 2 * k;
                 const int sn = tw;
@@ -285,8 +302,6 @@ __device__ __forceinline__ void fed_stream_wave2(const float *__restrict__ u, fl
                 if (k < S) {
                     ua[k][wp] = nva;
                     ub[k][wp] = nvb;
-                    ual[k][wp] = from_left(nvb);
-                    ubr[k][wp] = from_right(nva);
                 } else if (p >= ys && p < ye) {
                     const size_t r = (size_t)p * W;
                     if (sta) uo[r + xa] = nva;

@@ -447,16 +447,18 @@ def test_stream_forms_bitwise(env, shape, monkeypatch):
         assert np.array_equal(v, ref), k
 
 
-def test_concurrent_scales_bitwise(env, monkeypatch):
+@pytest.mark.parametrize("shape", [(200, 230), (1100, 70)])
+def test_concurrent_scales_bitwise(env, monkeypatch, shape):
     """Scales swept concurrently on side streams give the same bits as one
-    after another on the caller's stream."""
-    w = env["synth"].ridges128(H=200, W=230)
+    after another on the caller's stream (filter and selection)."""
+    H, W = shape
+    w = env["synth"].ridges128(H=H, W=W)
     w.sigmas = [1.0, 2.0, 4.0, 8.0, 12.0]
     w.mode = 2
     w.cycles = 2
-    u = _large_image(env, 200, 230, seed=9)
+    u = _large_image(env, H, W, seed=9)
     p = env["m"].Params.from_workload(w)
-    _log("concurrent scales")
+    _log(f"concurrent scales {shape}")
     a = _gpu_filter(env, u, p)
     sa = _gpu_select(env, u, p)
     monkeypatch.setenv("MF4D_FORK", "0")
