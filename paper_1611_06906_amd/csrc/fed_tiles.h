@@ -154,10 +154,13 @@ __device__ __forceinline__ void fed_stream_wave(const float *__restrict__ u, flo
 // shifts per pixel and the share of halo columns. Every column runs the
 // arithmetic of fed_stream_wave in the same order, so both forms give the
 // same values bit for bit.
-template <int S>
-__device__ __forceinline__ void fed_stream_wave2(const float *__restrict__ u, float *__restrict__ uo,
-                                                 const float *__restrict__ coef, int H, int W,
-                                                 const FedTaus &taus, int strip, int seg, int seg_rows)
+// PAIR: the strip lies inside the image, W is even and the planes are 8-byte
+// aligned, so each lane loads and stores its two columns as one 8-byte pair
+// (the same values as two 4-byte accesses).
+template <int S, bool PAIR>
+__device__ __forceinline__ void fed_stream_wave2_body(const float *__restrict__ u, float *__restrict__ uo,
+                                                      const float *__restrict__ coef, int H, int W,
+                                                      const FedTaus &taus, int strip, int seg, int seg_rows)
 {
 #pragma clang fp contract(off)   // fused multiply-adds are written out: every launch shape rounds alike
     constexpr int HALO = 2 * S;                           // columns
@@ -202,15 +205,31 @@ __device__ __forceinline__ void fed_stream_wave2(const float *__restrict__ u, fl
     const int y1 = ye + 2 * S;          // one past the last row needed
     auto issue = [&](int y, int d) {
         const size_t r = (size_t)min(max(y, 0), H - 1) * W;
-        const size_t oa = r + xca, ob = r + xcb;
-        qa0[d] = u[oa];
-        qb0[d] = u[ob];
-        qa1[d] = coef[oa];
-        qb1[d] = coef[ob];
-        qa2[d] = coef[plane + oa];
-        qb2[d] = coef[plane + ob];
-        qa3[d] = coef[2 * plane + oa];
-        qb3[d] = coef[2 * plane + ob];
+        if (PAIR) {
+            const size_t oa = r + xa;
+            const float2 v0 = *(const float2 *)(u + oa);
+            const float2 v1 = *(const float2 *)(coef + oa);
+            const float2 v2 = *(const float2 *)(coef + plane + oa);
+            const float2 v3 = *(const float2 *)(coef + 2 * plane + oa);
+            qa0[d] = v0.x;
+            qb0[d] = v0.y;
+            qa1[d] = v1.x;
+            qb1[d] = v1.y;
+            qa2[d] = v2.x;
+            qb2[d] = v2.y;
+            qa3[d] = v3.x;
+            qb3[d] = v3.y;
+        } else {
+            const size_t oa = r + xca, ob = r + xcb;
+            qa0[d] = u[oa];
+            qb0[d] = u[ob];
+            qa1[d] = coef[oa];
+            qb1[d] = coef[ob];
+            qa2[d] = coef[plane + oa];
+            qb2[d] = coef[plane + ob];
+            qa3[d] = coef[2 * plane + oa];
+            qb3[d] = coef[2 * plane + ob];
+        }
     };
 #pragma unroll
     for (int d = 0; d < D; ++d) issue(y0 + d, d);
@@ -304,12 +323,28 @@ __device__ __forceinline__ void fed_stream_wave2(const float *__restrict__ u, fl
                     ub[k][wp] = nvb;
                 } else if (p >= ys && p < ye) {
                     const size_t r = (size_t)p * W;
-                    if (sta) uo[r + xa] = nva;
-                    if (stb) uo[r + xb] = nvb;
+                    if (PAIR) {
+                        if (own) *(float2 *)(uo + r + xa) = make_float2(nva, nvb);
+                    } else {
+                        if (sta) uo[r + xa] = nva;
+                        if (stb) uo[r + xb] = nvb;
+                    }
                 }
             }
         }
     }
+}
+
+template <int S>
+__device__ __forceinline__ void fed_stream_wave2(const float *__restrict__ u, float *__restrict__ uo,
+                                                 const float *__restrict__ coef, int H, int W,
+                                                 const FedTaus &taus, int strip, int seg, int seg_rows)
+{
+    const int x0 = strip * (128 - 4 * S) - 2 * S;   // first column of the strip
+    const bool pair = (W & 1) == 0 && x0 >= 0 && x0 + 128 <= W &&
+                      (((uintptr_t)u | (uintptr_t)uo | (uintptr_t)coef) & 7) == 0;
+    if (pair) fed_stream_wave2_body<S, true>(u, uo, coef, H, W, taus, strip, seg, seg_rows);
+    else fed_stream_wave2_body<S, false>(u, uo, coef, H, W, taus, strip, seg, seg_rows);
 }
 
 }  // namespace tiles
