@@ -6,16 +6,14 @@
 //   L_xx, L_yy: [1 -2 1] along x / y;  L_xy = L_yx: (+1 at (-1,-1), (1,1);
 //   -1 at (-1,1), (1,-1)) / 4, so  r = L^T T = D2x T_xx + 2 Dxy T_xy + D2y T_yy.
 //
-// Two kernels:
+// Two kinds of kernel:
 //  * fed_hrho_kernel: one substep from H_rho, rebuilding the fourth-order
 //    tensor (tensor_math.h) in registers at every position it needs.
-//  * fed_coef_kernel<STEPS>: STEPS consecutive substeps from the compact
-//    tensor planes (m, al, be) computed once per cycle; P is frozen over the
-//    cycle, so this produces bit-identical values with none of the per-substep
-//    eigen-solves. With STEPS = 2 a tile keeps the intermediate image in LDS
-//    (temporal blocking): u and the tensor planes are read once and u written
-//    once per two substeps; the halo positions are recomputed by
-//    neighbouring tiles with the same operations in the same order.
+//  * fed_stream_kernel<S> / fed_stream2_kernel<S>: S consecutive substeps
+//    from the compact tensor planes (m, al, be) computed once per cycle (P is
+//    frozen over the cycle, so no per-substep eigen-solves), one wave per
+//    column strip streaming down its rows with the intermediate images in
+//    registers (fed_tiles.h); one or two columns per lane, the same values.
 #include "mf4d_internal.h"
 #include "tensor_math.h"
 #include <cstdlib>
@@ -84,155 +82,6 @@ __global__ __launch_bounds__(256) void fed_hrho_kernel(const float *__restrict__
         const float ryy = sT[2][ly][lx + 1] - 2.f * sT[2][ly + 1][lx + 1] + sT[2][ly + 2][lx + 1];
         const float rxy = 0.5f * ((sT[1][ly][lx] + sT[1][ly + 2][lx + 2]) - (sT[1][ly + 2][lx] + sT[1][ly][lx + 2]));
         uo[(size_t)gy * W + gx] = su[ly + 2][lx + 2] - tau * (rxx + rxy + ryy);
-    }
-}
-
-// ----------------------------------------------------------------- compact
-constexpr int kCW = 64, kCH = 16;   // output tile of the coefficient kernel
-
-// T = D h at one position from the u tile (centre at su[cy][cx]).
-__device__ __forceinline__ void flux(const float *su, int pitch, int cy, int cx, float mb, float al,
-                                     float be, float &txx, float &txy, float &tyy)
-{
-    const float *c = su + cy * pitch + cx;
-    const float v = c[0];
-    const float hxx = c[-1] - 2.f * v + c[1];
-    const float hyy = c[-pitch] - 2.f * v + c[pitch];
-    const float hxy = 0.25f * ((c[-pitch - 1] + c[pitch + 1]) - (c[pitch - 1] + c[-pitch + 1]));
-    txx = (mb + al) * hxx + be * hxy;
-    txy = mb * hxy + be * 0.5f * (hxx + hyy);
-    tyy = (mb - al) * hyy + be * hxy;
-}
-
-// r = L^T T at one position (centre at sT[.][cy][cx]).
-__device__ __forceinline__ float divergence(const float *sxx, const float *sxy, const float *syy, int pitch,
-                                            int cy, int cx)
-{
-    const int o = cy * pitch + cx;
-    const float rxx = sxx[o - 1] - 2.f * sxx[o] + sxx[o + 1];
-    const float ryy = syy[o - pitch] - 2.f * syy[o] + syy[o + pitch];
-    const float rxy = 0.5f * ((sxy[o - pitch - 1] + sxy[o + pitch + 1]) - (sxy[o + pitch - 1] + sxy[o - pitch + 1]));
-    return rxx + rxy + ryy;
-}
-
-__device__ __forceinline__ bool interior(int gx, int gy, int W, int H)
-{
-    return gx >= 1 && gx <= W - 2 && gy >= 1 && gy <= H - 2;
-}
-
-template <int STEPS>
-__global__ __launch_bounds__(256) void fed_coef_kernel(const float *__restrict__ u, float *__restrict__ uo,
-                                                       const float *__restrict__ coef, int H, int W,
-                                                       float tau0, float tau1, int tiles_x, int ntiles,
-                                                       int per_xcd)
-{
-    constexpr int HALO = 2 * STEPS;                 // u halo
-    constexpr int UW = kCW + 2 * HALO, UH = kCH + 2 * HALO, UP = UW + 1;
-    constexpr int CW_ = kCW + 2 * HALO - 2, CH_ = kCH + 2 * HALO - 2, CP = CW_ + 1;   // T region
-    constexpr int VW = kCW + 2 * HALO - 4, VH = kCH + 2 * HALO - 4, VP = VW + 1;      // u1 region (STEPS = 2)
-    __shared__ float su[UH * UP];
-    __shared__ float sT[3][CH_ * CP];
-    __shared__ float sv[STEPS == 2 ? VH * VP : 1];
-
-    const int tile = xcd_tile(per_xcd);
-    if (tile >= ntiles) return;
-    const int x0 = (tile % tiles_x) * kCW, y0 = (tile / tiles_x) * kCH;
-    const size_t plane = (size_t)H * W;
-
-    // tensor planes of this thread's first-substep positions, loaded up front
-    constexpr int NC = (CH_ * CW_ + 255) / 256;
-    float cm[NC], ca[NC], cb[NC];
-#pragma unroll
-    for (int j = 0; j < NC; ++j) {
-        const int i = threadIdx.x + 256 * j;
-        const int ly = i / CW_, lx = i - ly * CW_;
-        const int gy = y0 - HALO + 1 + ly, gx = x0 - HALO + 1 + lx;
-        cm[j] = ca[j] = cb[j] = 0.f;
-        if (i < CH_ * CW_ && interior(gx, gy, W, H)) {
-            const size_t o = (size_t)gy * W + gx;
-            cm[j] = coef[o];
-            ca[j] = coef[plane + o];
-            cb[j] = coef[2 * plane + o];
-        }
-    }
-    // u on the tile plus HALO
-    for (int i = threadIdx.x; i < UH * UW; i += 256) {
-        const int ly = i / UW, lx = i - ly * UW;
-        const int gy = y0 - HALO + ly, gx = x0 - HALO + lx;
-        su[ly * UP + lx] = (gy >= 0 && gy < H && gx >= 0 && gx < W) ? u[(size_t)gy * W + gx] : 0.f;
-    }
-    __syncthreads();
-
-    // ---- substep 1: T on the T region (zero outside the interior)
-#pragma unroll
-    for (int j = 0; j < NC; ++j) {
-        const int i = threadIdx.x + 256 * j;
-        if (i < CH_ * CW_) {
-            const int ly = i / CW_, lx = i - ly * CW_;
-            const int gy = y0 - HALO + 1 + ly, gx = x0 - HALO + 1 + lx;
-            float txx = 0.f, txy = 0.f, tyy = 0.f;
-            if (interior(gx, gy, W, H)) flux(su, UP, ly + 1, lx + 1, cm[j], ca[j], cb[j], txx, txy, tyy);
-            sT[0][ly * CP + lx] = txx;
-            sT[1][ly * CP + lx] = txy;
-            sT[2][ly * CP + lx] = tyy;
-        }
-    }
-    __syncthreads();
-    if (STEPS == 1) {
-        for (int i = threadIdx.x; i < kCH * kCW; i += 256) {
-            const int ly = i / kCW, lx = i - ly * kCW;
-            const int gy = y0 + ly, gx = x0 + lx;
-            if (gy >= H || gx >= W) continue;
-            const float r = divergence(sT[0], sT[1], sT[2], CP, ly + 1, lx + 1);
-            uo[(size_t)gy * W + gx] = su[(ly + 2) * UP + lx + 2] - tau0 * r;
-        }
-        return;
-    }
-    // u1 on the tile plus 2 (positions outside the image are never read)
-    for (int i = threadIdx.x; i < VH * VW; i += 256) {
-        const int ly = i / VW, lx = i - ly * VW;
-        const float r = divergence(sT[0], sT[1], sT[2], CP, ly + 1, lx + 1);
-        sv[ly * VP + lx] = su[(ly + 2) * UP + lx + 2] - tau0 * r;
-    }
-    // tensor planes of the second-substep positions (L2-resident: just read)
-    constexpr int N2 = ((kCH + 2) * (kCW + 2) + 255) / 256;
-    float dm[N2], da[N2], db[N2];
-#pragma unroll
-    for (int j = 0; j < N2; ++j) {
-        const int i = threadIdx.x + 256 * j;
-        const int ly = i / (kCW + 2), lx = i - ly * (kCW + 2);
-        const int gy = y0 - 1 + ly, gx = x0 - 1 + lx;
-        dm[j] = da[j] = db[j] = 0.f;
-        if (i < (kCH + 2) * (kCW + 2) && interior(gx, gy, W, H)) {
-            const size_t o = (size_t)gy * W + gx;
-            dm[j] = coef[o];
-            da[j] = coef[plane + o];
-            db[j] = coef[2 * plane + o];
-        }
-    }
-    __syncthreads();
-    // ---- substep 2: T on the tile plus 1 from u1, then the output
-#pragma unroll
-    for (int j = 0; j < N2; ++j) {
-        const int i = threadIdx.x + 256 * j;
-        if (i < (kCH + 2) * (kCW + 2)) {
-            const int ly = i / (kCW + 2), lx = i - ly * (kCW + 2);
-            const int gy = y0 - 1 + ly, gx = x0 - 1 + lx;
-            float txx = 0.f, txy = 0.f, tyy = 0.f;
-            if (interior(gx, gy, W, H)) flux(sv, VP, ly + 1, lx + 1, dm[j], da[j], db[j], txx, txy, tyy);
-            const int co = (ly + 2) * CP + lx + 2;   // same position in the T region
-            sT[0][co] = txx;
-            sT[1][co] = txy;
-            sT[2][co] = tyy;
-        }
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < kCH * kCW; i += 256) {
-        const int ly = i / kCW, lx = i - ly * kCW;
-        const int gy = y0 + ly, gx = x0 + lx;
-        if (gy >= H || gx >= W) continue;
-        const float r = divergence(sT[0], sT[1], sT[2], CP, ly + 3, lx + 3);
-        uo[(size_t)gy * W + gx] = sv[(ly + 2) * VP + lx + 2] - tau1 * r;
     }
 }
 
@@ -359,22 +208,6 @@ hipError_t launch_fed_stream(const float *u_in, float *u_out, const float *coef,
         return hipErrorInvalidValue;
     }
 #undef MF4D_ST
-    return hipGetLastError();
-}
-
-hipError_t launch_fed_coef(const float *u_in, float *u_out, const float *coef, int H, int W, int steps,
-                           float tau0, float tau1, hipStream_t s)
-{
-    const int tiles_x = (W + kCW - 1) / kCW, tiles_y = (H + kCH - 1) / kCH;
-    const int ntiles = tiles_x * tiles_y;
-    const int per = (ntiles + 7) / 8;
-    dim3 grid(8 * per), block(256);
-    if (steps == 2)
-        hipLaunchKernelGGL(fed_coef_kernel<2>, grid, block, 0, s, u_in, u_out, coef, H, W, tau0, tau1,
-                           tiles_x, ntiles, per);
-    else
-        hipLaunchKernelGGL(fed_coef_kernel<1>, grid, block, 0, s, u_in, u_out, coef, H, W, tau0, tau0,
-                           tiles_x, ntiles, per);
     return hipGetLastError();
 }
 

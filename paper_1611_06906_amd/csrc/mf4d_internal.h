@@ -102,11 +102,6 @@ hipError_t launch_select(const SelectArgs &a, int H, int W, hipStream_t s);
 hipError_t launch_fed_substep(const float *u_in, float *u_out, const float *hrho, int H, int W,
                               float tau, int mode, float inv_lam2, hipStream_t s);
 
-// `steps` (1 or 2) consecutive substeps with steps tau0 (then tau1) from the
-// compact tensor planes (m, al, be) of the cycle.
-hipError_t launch_fed_coef(const float *u_in, float *u_out, const float *coef, int H, int W, int steps,
-                           float tau0, float tau1, hipStream_t s);
-
 // `steps` (1..4) consecutive substeps with taus[0..steps-1], one wave per
 // 64 c - 4 steps columns x seg_rows rows (c = stream_cols_per_lane(steps)),
 // intermediate images in registers. Both forms give the same values;
