@@ -30,6 +30,10 @@ namespace tiles {
 constexpr int K = kWin;
 constexpr int kBTW = 64, kBTH = 32;   // rho-blur output tile
 
+// vector types for the nontemporal accesses of the per-scale planes
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+typedef float nt_f3 __attribute__((ext_vector_type(3)));
+
 // half-sample symmetric extension (period 2n), cheap for small excursions
 __device__ __forceinline__ int reflect(int i, int n)
 {
@@ -137,12 +141,11 @@ __device__ __forceinline__ float vessel_store(float uxx, float uxy, float uyy, f
     const float rb = (am - r) * __builtin_amdgcn_rcpf(big);   // |R_B| = |nu~1| / |nu~2|
     const float e = __builtin_amdgcn_exp2f(-(rb * rb) * inv2beta2 * kLog2e);
     const float blob = pass ? e : 0.f;
-    *(float2 *)(SA + 2 * o) = make_float2(Sv, blob);   // S and the blob factor per pixel: [H][W][2]
+    // S and the blob factor per pixel ([H][W][2]), written once and read once
+    __builtin_nontemporal_store(nt_f2{Sv, blob}, (nt_f2 *)(SA + 2 * o));
     if (No) {
         const float f = __builtin_amdgcn_rsqf(1.f + __builtin_amdgcn_sqrtf(fmaf(gx, gx, gy * gy)));
-        No[3 * o] = uxx * f;   // N is stored per pixel: [H][W][3]
-        No[3 * o + 1] = uxy * f;
-        No[3 * o + 2] = uyy * f;
+        __builtin_nontemporal_store(nt_f3{uxx * f, uxy * f, uyy * f}, (nt_f3 *)(No + 3 * o));   // [H][W][3]
     }
     return Sv;
 }
@@ -178,12 +181,10 @@ __device__ __forceinline__ float vessel_store_mode(int mode, float uxx, float ux
                                                    float *__restrict__ No, size_t o, size_t plane)
 {
     const VesselPx v = vessel_px(mode, uxx, uxy, uyy, gx, gy, sigma2, inv2beta2);
-    *(float2 *)(SA + 2 * o) = make_float2(v.S, v.blob);
-    if (No) {
-        No[3 * o] = v.n0;   // N is stored per pixel: [H][W][3]
-        No[3 * o + 1] = v.n1;
-        No[3 * o + 2] = v.n2;
-    }
+    // every scale's planes are written once and read once, after all scales:
+    // nontemporal stores keep them from evicting the sweep's working set
+    __builtin_nontemporal_store(nt_f2{v.S, v.blob}, (nt_f2 *)(SA + 2 * o));
+    if (No) __builtin_nontemporal_store(nt_f3{v.n0, v.n1, v.n2}, (nt_f3 *)(No + 3 * o));   // N per pixel: [H][W][3]
     return v.S;
 }
 
@@ -286,10 +287,12 @@ __device__ __forceinline__ int argmax_px(const float *__restrict__ SA, int ns, s
     int best = 0;
     float bv = 0.f;
     if (c > 0.f) {
-        float2 sa[MF4D_MAX_SCALES];   // (S, blob) of every scale, loaded before the comparisons
+        // (S, blob) of every scale, loaded before the comparisons; each pair is
+        // read once, so the loads are nontemporal
+        nt_f2 sa[MF4D_MAX_SCALES];
 #pragma unroll
         for (int s = 0; s < MF4D_MAX_SCALES; ++s)
-            if (s < ns) sa[s] = *(const float2 *)(SA + 2 * (s * plane + o));
+            if (s < ns) sa[s] = __builtin_nontemporal_load((const nt_f2 *)(SA + 2 * (s * plane + o)));
         const float inv2c2 = 1.f / (2.f * c * c);
         bv = frangi_v(sa[0].x, sa[0].y, inv2c2);
 #pragma unroll
