@@ -355,7 +355,11 @@ def main():
     t16 = time_stream(torch, sel16, reps) * 1e-3
     R16 = 49                                  # ceil(3 sigma) + 1: support of the difference taps
     sweep_flops_px = 8 * (2 * R16 + 1) * 2    # 3 horizontal + 5 vertical filters
-    mfma_flops_px = 8 * 128 * 2               # the banded Toeplitz products as issued (K = 128)
+    # the banded Toeplitz products as issued: 16-input chunks of 4-input
+    # slices, the last chunk's slices beyond the band skipped (29 of 32 at R = 49)
+    nc16 = (16 + 2 * R16 + 15) // 16
+    slices16 = 4 * (nc16 - 1) + (16 + 2 * R16 - 16 * (nc16 - 1) + 3) // 4
+    mfma_flops_px = 8 * slices16 * 4 * 2      # 8 filters; each slice: 4 multiply-adds per output
     roofline_sweep = {"bound": "mfma", "kernel": "sweep_fused_kernel<8> (both passes of sigma = 16) + one-scale argmax",
                       "achieved": sweep_flops_px * m / t16 / 1e12, "peak": MFMA_F32_PEAK / 1e12, "unit": "TFLOP/s",
                       "frac": sweep_flops_px * m / t16 / MFMA_F32_PEAK,
