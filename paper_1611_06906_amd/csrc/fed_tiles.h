@@ -33,6 +33,8 @@ __device__ __forceinline__ float from_right(float v)
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 
+typedef float nt_f2 __attribute__((ext_vector_type(2)));   // 8-byte nontemporal loads
+
 // v where m is all ones, +0 where m is 0 (a bitwise select the compiler
 // cannot turn into a branch; for finite v the same values as a conditional)
 __device__ __forceinline__ float keep(float v, unsigned m) { return __uint_as_float(__float_as_uint(v) & m); }
@@ -76,7 +78,7 @@ __device__ __forceinline__ void fed_stream_wave(const float *__restrict__ u, flo
     // rows are loaded from a clamped address and masked when consumed
     auto issue = [&](int y, float &vu, float &vm, float &va, float &vb) {
         const size_t o = (size_t)min(max(y, 0), H - 1) * W + xc;
-        vu = u[o];
+        vu = __builtin_nontemporal_load(u + o);   // the launch's input image is read here for the last time
         vm = coef[o];
         va = coef[plane + o];
         vb = coef[2 * plane + o];
@@ -207,7 +209,9 @@ __device__ __forceinline__ void fed_stream_wave2_body(const float *__restrict__ 
         const size_t r = (size_t)min(max(y, 0), H - 1) * W;
         if (PAIR) {
             const size_t oa = r + xa;
-            const float2 v0 = *(const float2 *)(u + oa);
+            // the launch's input image is read here for the last time (the
+            // tensor planes are read again by the cycle's later launches)
+            const nt_f2 v0 = __builtin_nontemporal_load((const nt_f2 *)(u + oa));
             const float2 v1 = *(const float2 *)(coef + oa);
             const float2 v2 = *(const float2 *)(coef + plane + oa);
             const float2 v3 = *(const float2 *)(coef + 2 * plane + oa);
@@ -221,8 +225,8 @@ __device__ __forceinline__ void fed_stream_wave2_body(const float *__restrict__ 
             qb3[d] = v3.y;
         } else {
             const size_t oa = r + xca, ob = r + xcb;
-            qa0[d] = u[oa];
-            qb0[d] = u[ob];
+            qa0[d] = __builtin_nontemporal_load(u + oa);
+            qb0[d] = __builtin_nontemporal_load(u + ob);
             qa1[d] = coef[oa];
             qb1[d] = coef[ob];
             qa2[d] = coef[plane + oa];
