@@ -71,13 +71,24 @@ __global__ __launch_bounds__(256) void conv_kernel(const uint16_t *__restrict__ 
     const int tx = W / 16;
     const int x0 = (t % tx) * 16, y0 = (t / tx) * 16;
     const size_t base = (size_t)img * H * W;
-    for (int i = threadIdx.x; i < 18 * 18 * CH4; i += 256) {
+    // the 18 x 18 input patch (zero outside the image): every load is issued
+    // before the first LDS store, so the block waits for one memory round trip
+    constexpr int NST = (18 * 18 * CH4 + 255) / 256;
+    uint2 v[NST];
+#pragma unroll
+    for (int it = 0; it < NST; ++it) {
+        const int i = threadIdx.x + 256 * it;
         const int q = i / CH4, c4 = i % CH4;
         const int gy = y0 - 1 + q / 18, gx = x0 - 1 + q % 18;
-        uint2 v = make_uint2(0u, 0u);
-        if (gy >= 0 && gy < H && gx >= 0 && gx < W)
-            v = *(const uint2 *)(in + (base + (size_t)gy * W + gx) * CINP + c4 * 4);
-        *(uint2 *)(sIn + q * CINP + c4 * 4) = v;
+        v[it] = make_uint2(0u, 0u);
+        if (i < 18 * 18 * CH4 && gy >= 0 && gy < H && gx >= 0 && gx < W)
+            v[it] = *(const uint2 *)(in + (base + (size_t)gy * W + gx) * CINP + c4 * 4);
+    }
+#pragma unroll
+    for (int it = 0; it < NST; ++it) {
+        const int i = threadIdx.x + 256 * it;
+        const int q = i / CH4, c4 = i % CH4;
+        if (i < 18 * 18 * CH4) *(uint2 *)(sIn + q * CINP + c4 * 4) = v[it];
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;

@@ -28,7 +28,7 @@ namespace mf4d {
 namespace tiles {
 
 constexpr int K = kWin;
-constexpr int kBTW = 64, kBTH = 32;   // rho-blur output tile
+constexpr int kBTW = 64, kBTH = 16;   // rho-blur output tile
 
 // vector types for the nontemporal accesses of the per-scale planes
 typedef float nt_f2 __attribute__((ext_vector_type(2)));
@@ -306,11 +306,12 @@ __device__ __forceinline__ int argmax_px(const float *__restrict__ SA, int ns, s
     return best;
 }
 
-// H_rho = G_rho * N (separable, symmetric extension) on the 64 x 32 tile at
-// (x0, y0); writes H_rho and/or the compact tensor planes of H_rho. The
+// H_rho = G_rho * N (separable, symmetric extension) on the kBTW x kBTH tile
+// at (x0, y0); writes H_rho and/or the compact tensor planes of H_rho. The
 // tile's inputs (with a halo of HR) are staged in LDS; thread (x, g) blurs
-// rows 8g - HR .. 8g + 7 + HR of column x horizontally into registers and
-// then vertically, so only one LDS buffer is needed.
+// rows RG g - HR .. RG g + RG - 1 + HR (RG = kBTH / 4) of column x
+// horizontally into registers and then vertically, so only one LDS buffer
+// is needed.
 // N holds all ns scales, per pixel ([ns][H][W][3]); each staged pixel takes
 // the three values of its scale idx (clamped to ns - 1).
 template <int HR>
