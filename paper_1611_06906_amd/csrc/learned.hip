@@ -57,16 +57,24 @@ __device__ __forceinline__ uint16_t to_bf16(float f)
 }
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-enum { EPI_RELU = 0, EPI_LINEAR = 1, EPI_MASK = 2 };
+// EPI_SELECT: the logits of the last layer, reduced per pixel to one byte
+// (see conv_kernel) instead of being written out
+enum { EPI_RELU = 0, EPI_LINEAR = 1, EPI_MASK = 2, EPI_SELECT = 3 };
 
 // ------------------------------------------------------------------ forward
 template <int CINP, int COUTP, int EPI>
 __global__ __launch_bounds__(256) void conv_kernel(const uint16_t *__restrict__ in, const uint16_t *__restrict__ wt,
                                                    const float *__restrict__ bias, const uint16_t *__restrict__ mask,
-                                                   void *__restrict__ out, int H, int W, int tiles_per_img)
+                                                   void *__restrict__ out, int H, int W, int tiles_per_img,
+                                                   float thr = 0.f, int ns = 0)
 {
     constexpr int NT = COUTP / 16, KC = CINP / 16, CH4 = CINP / 4;
-    __shared__ uint16_t sIn[18 * 18 * CINP];
+    constexpr int ESZ = (EPI == EPI_LINEAR || EPI == EPI_SELECT) ? 4 : 2;   // output element bytes in LDS
+    constexpr int OUT_BYTES = 256 * COUTP * ESZ;                    // the tile's output, pixel-major
+    constexpr int IN_ELEMS = 18 * 18 * CINP;
+    static_assert(EPI != EPI_SELECT || IN_ELEMS * 2 >= 256 * (COUTP + 1) * 4, "padded logits tile exceeds the LDS");
+    // the input patch, then (after the products) the output tile on its way to HBM
+    __shared__ __align__(16) uint16_t sIn[IN_ELEMS > OUT_BYTES / 2 ? IN_ELEMS : OUT_BYTES / 2];
     const int img = blockIdx.x / tiles_per_img, t = blockIdx.x % tiles_per_img;
     const int tx = W / 16;
     const int x0 = (t % tx) * 16, y0 = (t / tx) * 16;
@@ -117,27 +125,63 @@ __global__ __launch_bounds__(256) void conv_kernel(const uint16_t *__restrict__ 
             }
         }
     }
-    // lane holds D[m = 4 lk + i][n = lr]: pixel x0 + 4 lk + i of row r, channel 16 nt + lr
+    // lane holds D[m = 4 lk + i][n = lr]: pixel x0 + 4 lk + i of row r, channel 16 nt + lr.
+    // The tile's outputs go to LDS in the global pixel-major order, then to
+    // HBM in 16-byte chunks (one tile row of 16 pixels is contiguous there).
+    __syncthreads();   // every wave has finished reading the input patch
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
-        const size_t prow = base + (size_t)(y0 + wv * 4 + mt) * W + x0 + lk * 4;
+        const int prow = (wv * 4 + mt) * 16 + lk * 4;   // pixel index inside the tile
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             const int c = nt * 16 + lr;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const size_t o = (prow + i) * COUTP + c;
-                float v = acc[mt][nt][i];
-                if (EPI == EPI_RELU) {
-                    v = fmaxf(v + bias[c], 0.f);
-                    ((uint16_t *)out)[o] = to_bf16(v);
-                } else if (EPI == EPI_LINEAR) {
-                    ((float *)out)[o] = v + bias[c];
-                } else {
-                    ((uint16_t *)out)[o] = from_bf16(mask[o]) > 0.f ? to_bf16(v) : (uint16_t)0;
-                }
+                // pixel-major; EPI_SELECT pads the pixel stride by one float so
+                // that thread t reading pixel t meets no bank conflict
+                const int o = (prow + i) * (EPI == EPI_SELECT ? COUTP + 1 : COUTP) + c;
+                const float v = acc[mt][nt][i];
+                if (EPI == EPI_RELU) sIn[o] = to_bf16(fmaxf(v + bias[c], 0.f));
+                else if (EPI == EPI_LINEAR || EPI == EPI_SELECT) ((float *)sIn)[o] = v + bias[c];
+                else sIn[o] = to_bf16(v);
             }
         }
+    }
+    __syncthreads();
+    if (EPI == EPI_SELECT) {
+        // thread t takes pixel t of the tile: the network's scale (argmax of the
+        // first min(ns, 8) logits, smallest index among equal maxima) in the low
+        // bits, bit 7 set where the confidence sigmoid(z_8) reaches thr
+        const float *zz = (const float *)sIn + threadIdx.x * (COUTP + 1);
+        int best = 0;
+        float mx = zz[0];
+        for (int k = 1; k < ns && k < 8; ++k)
+            if (zz[k] > mx) { mx = zz[k]; best = k; }
+        const float conf = 1.f / (1.f + expf(-zz[8]));
+        ((uint8_t *)out)[base + (size_t)(y0 + threadIdx.x / 16) * W + x0 + threadIdx.x % 16] =
+            (uint8_t)(best | (conf >= thr ? 0x80 : 0));
+        return;
+    }
+    constexpr int NCH = OUT_BYTES / 16, CPR = NCH / 16;   // 16-byte chunks, per tile row
+#pragma unroll
+    for (int it = 0; it < NCH / 256; ++it) {
+        const int c = threadIdx.x + 256 * it;
+        const int r = c / CPR, k = c - r * CPR;
+        const size_t go = ((base + (size_t)(y0 + r) * W + x0) * COUTP) * ESZ + (size_t)k * 16;   // bytes
+        uint4 val = ((const uint4 *)sIn)[c];
+        if (EPI == EPI_MASK) {   // zero where the forward activation (ReLU output) is not positive
+            const uint4 mk = *(const uint4 *)((const char *)mask + go);
+            const uint32_t mw[4] = {mk.x, mk.y, mk.z, mk.w};
+            uint32_t vw[4] = {val.x, val.y, val.z, val.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t lo = from_bf16((uint16_t)(mw[q] & 0xffffu)) > 0.f ? 0x0000ffffu : 0u;
+                const uint32_t hi = from_bf16((uint16_t)(mw[q] >> 16)) > 0.f ? 0xffff0000u : 0u;
+                vw[q] &= lo | hi;
+            }
+            val = make_uint4(vw[0], vw[1], vw[2], vw[3]);
+        }
+        *(uint4 *)((char *)out + go) = val;
     }
 }
 
@@ -346,7 +390,7 @@ __global__ void adam_kernel(float *__restrict__ th, const float *__restrict__ g,
 // learned selection: the network's scale where its confidence reaches the
 // threshold, the exact argmax elsewhere (the integration then gathers N at
 // that scale through idx)
-__global__ __launch_bounds__(256) void learned_select_kernel(const float *__restrict__ z, float thr,
+__global__ __launch_bounds__(256) void learned_select_kernel(const uint8_t *__restrict__ sel,
                                                              const float *__restrict__ SA,
                                                              int ns, size_t plane,
                                                              const unsigned *__restrict__ smax_bits, float c_param,
@@ -357,13 +401,9 @@ __global__ __launch_bounds__(256) void learned_select_kernel(const float *__rest
     __syncthreads();
     const size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (o < plane) {
-        const float *zz = z + o * 16;
-        int best = 0;
-        float mx = zz[0];
-        for (int k = 1; k < ns && k < 8; ++k)
-            if (zz[k] > mx) { mx = zz[k]; best = k; }
-        const float conf = 1.f / (1.f + expf(-zz[8]));
-        if (!(conf >= thr)) {
+        const unsigned code = sel[o];   // network scale, bit 7: confident
+        int best = (int)(code & 0x7fu);
+        if (!(code & 0x80u)) {
             const float c = c_param > 0.f ? c_param : 0.5f * __uint_as_float(*smax_bits);
             float bv;
             best = tiles::argmax_px(SA, ns, plane, o, c, &bv);
@@ -372,7 +412,19 @@ __global__ __launch_bounds__(256) void learned_select_kernel(const float *__rest
         idx[o] = (uint8_t)best;
     }
     __syncthreads();
-    if (threadIdx.x == 0 && cnt) atomicAdd(fallback, cnt);
+    // one of kFallbackSlots counters per block, so the blocks' atomics spread
+    // over that many addresses instead of all meeting on one
+    if (threadIdx.x == 0 && cnt) atomicAdd(fallback + blockIdx.x % kFallbackSlots, cnt);
+}
+
+// the total of the fallback counters
+__global__ void fallback_sum_kernel(const unsigned *__restrict__ slots, unsigned *__restrict__ total)
+{
+    if (threadIdx.x == 0) {
+        unsigned t = 0;
+        for (int i = 0; i < kFallbackSlots; ++i) t += slots[i];
+        *total = t;
+    }
 }
 
 // --------------------------------------------------------------- workspace
@@ -456,6 +508,26 @@ int forward_all(const float *u, int B, int H, int W, const NetWs &w, hipStream_t
     return MF4D_OK;
 }
 
+// forward_all with the last layer reduced to the selection byte per pixel
+// (EPI_SELECT) in sel
+int forward_select(const float *u, int H, int W, const NetWs &w, float thr, int ns, uint8_t *sel, hipStream_t s)
+{
+    const int B = 1;
+    const size_t P = (size_t)B * H * W;
+    const int tpi = (H / 16) * (W / 16);
+    const dim3 grid(B * tpi), blk(256);
+    hipLaunchKernelGGL(input_kernel, dim3((unsigned)((P + 255) / 256)), blk, 0, s, u, w.act[0], P);
+    hipLaunchKernelGGL((conv_kernel<16, 32, EPI_RELU>), grid, blk, 0, s, w.act[0], w.wf[0], w.bias[0], nullptr,
+                       (void *)w.act[1], H, W, tpi);
+    for (int l = 1; l < 4; ++l)
+        hipLaunchKernelGGL((conv_kernel<32, 32, EPI_RELU>), grid, blk, 0, s, w.act[l], w.wf[l], w.bias[l], nullptr,
+                           (void *)w.act[l + 1], H, W, tpi);
+    hipLaunchKernelGGL((conv_kernel<32, 16, EPI_SELECT>), grid, blk, 0, s, w.act[4], w.wf[4], w.bias[4], nullptr,
+                       (void *)sel, H, W, tpi, thr, ns);
+    NCHECK(hipGetLastError());
+    return MF4D_OK;
+}
+
 bool shape_ok(int B, int H, int W)
 {
     return B >= 1 && H >= 16 && W >= 16 && H % 16 == 0 && W % 16 == 0 && (long long)B * H * W < (1LL << 31);
@@ -464,24 +536,32 @@ bool shape_ok(int B, int H, int W)
 }  // namespace net
 
 // network forward for the learned filter: returns the logits [P][16]
-int net_forward_into(const float *theta, const float *u, int H, int W, char *ws, hipStream_t s, const float **z)
+int net_select_into(const float *theta, const float *u, int H, int W, char *ws, hipStream_t s, float thr, int ns,
+                    const uint8_t **sel, bool pack)
 {
     using namespace net;
     NetWs w;
     net_layout(1, H, W, false, &w, ws);
-    int st = pack_all(theta, w, s);
-    if (st == MF4D_OK) st = forward_all(u, 1, H, W, w, s);
-    *z = w.z;
+    int st = pack ? pack_all(theta, w, s) : MF4D_OK;
+    uint8_t *out = (uint8_t *)w.z;   // the logits' space holds the selection bytes
+    if (st == MF4D_OK) st = forward_select(u, H, W, w, thr, ns, out, s);
+    *sel = out;
     return st;
 }
 
 size_t net_forward_bytes(int H, int W) { return net::net_layout(1, H, W, false, nullptr, nullptr); }
 
-hipError_t launch_learned_select(const float *z, float thr, const SelectArgs &a, int H, int W, unsigned *fallback,
+hipError_t launch_fallback_sum(const unsigned *slots, unsigned *total, hipStream_t s)
+{
+    hipLaunchKernelGGL(net::fallback_sum_kernel, dim3(1), dim3(64), 0, s, slots, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_learned_select(const uint8_t *sel, const SelectArgs &a, int H, int W, unsigned *fallback,
                                  hipStream_t s)
 {
     const size_t plane = (size_t)H * W;
-    hipLaunchKernelGGL(net::learned_select_kernel, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, s, z, thr, a.SA,
+    hipLaunchKernelGGL(net::learned_select_kernel, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, s, sel, a.SA,
                        a.ns, plane, a.smax_bits, a.c_param, a.idx_out, fallback);
     return hipGetLastError();
 }

@@ -589,7 +589,8 @@ int mf4d_filter(const float *u_in, float *u_out, int H, int W, const mf4d_params
 size_t mf4d_learned_workspace_bytes(int H, int W, const mf4d_params *p)
 {
     if (validate(H, W, p) != MF4D_OK || p->nscales > 8 || H % 16 != 0 || W % 16 != 0) return 0;
-    return align256(layout(H, W, p->nscales, nullptr, nullptr)) + align256(net_forward_bytes(H, W)) + 256;
+    return align256(layout(H, W, p->nscales, nullptr, nullptr)) + align256(net_forward_bytes(H, W)) +
+           sizeof(unsigned) * kFallbackSlots;
 }
 
 int mf4d_filter_learned(const float *u_in, float *u_out, int H, int W, const mf4d_params *p, const float *theta,
@@ -606,11 +607,11 @@ int mf4d_filter_learned(const float *u_in, float *u_out, int H, int W, const mf4
     char *base = (char *)ws;
     const size_t img_bytes = align256(layout(H, W, p->nscales, nullptr, nullptr));
     char *net_ws = base + img_bytes;
-    unsigned *fb = (unsigned *)(net_ws + align256(net_forward_bytes(H, W)));
-    CHECK_HIP(launch_fill_u32(fb, 0u, 1, s));
+    unsigned *fb = (unsigned *)(net_ws + align256(net_forward_bytes(H, W)));   // kFallbackSlots counters
+    CHECK_HIP(launch_fill_u32(fb, 0u, kFallbackSlots, s));
     if (p->cycles == 0) {
         if (u_in != u_out) CHECK_HIP(launch_copy_f32(u_in, u_out, m, s));
-        if (fallback_count) CHECK_HIP(hipMemcpyAsync(fallback_count, fb, 4, hipMemcpyDeviceToDevice, s));
+        if (fallback_count) CHECK_HIP(launch_fallback_sum(fb, fallback_count, s));
         return MF4D_OK;
     }
     std::vector<double> ordered;
@@ -639,17 +640,18 @@ int mf4d_filter_learned(const float *u_in, float *u_out, int H, int W, const mf4
     a.idx_out = w.idx;
     int li = 0;
     for (int k = 0; k < p->cycles; ++k) {
-        const float *z = nullptr;
-        st = net_forward_into(theta, src, H, W, net_ws, s, &z);
+        const uint8_t *sel = nullptr;
+        st = net_select_into(theta, src, H, W, net_ws, s, conf_threshold, p->nscales, &sel,
+                             k == 0);   // weights packed once per call
         if (st != MF4D_OK) return st;
         st = run_sweep(src, H, W, p, w, true, s);
         if (st != MF4D_OK) return st;
-        CHECK_HIP(launch_learned_select(z, conf_threshold, a, H, W, fb, s));
+        CHECK_HIP(launch_learned_select(sel, a, H, W, fb, s));
         CHECK_HIP(launch_rho(a, H, W, s));
         st = run_substeps(src, bufs, li, w.tens, H, W, tau32.data(), n, spl, s, &src);
         if (st != MF4D_OK) return st;
     }
-    if (fallback_count) CHECK_HIP(hipMemcpyAsync(fallback_count, fb, 4, hipMemcpyDeviceToDevice, s));
+    if (fallback_count) CHECK_HIP(launch_fallback_sum(fb, fallback_count, s));
     return MF4D_OK;
 }
 

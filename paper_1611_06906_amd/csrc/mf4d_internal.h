@@ -118,12 +118,19 @@ hipError_t launch_fed_stream(const float *u_in, float *u_out, const float *coef,
 hipError_t launch_rho(const SelectArgs &a, int H, int W, hipStream_t s);
 
 // Learned surrogate (learned.hip): network forward on one H x W image into
-// `ws` (net_forward_bytes(H, W) bytes), logits [H*W][16] returned in *z; and
-// the learned selection (network scale where confident, exact argmax
-// elsewhere; counts the fallback pixels into *fallback).
-int net_forward_into(const float *theta, const float *u, int H, int W, char *ws, hipStream_t s, const float **z);
+// `ws` (net_forward_bytes(H, W) bytes) with the last layer reduced per pixel
+// to one byte in *sel: the network's scale among the first min(ns, 8), bit 7
+// set where its confidence reaches thr (the weights are packed from theta when
+// `pack`, else those of an earlier call with the same ws are used); and the
+// learned selection (that scale where confident, the exact argmax elsewhere;
+// counts the fallback pixels into *fallback).
+int net_select_into(const float *theta, const float *u, int H, int W, char *ws, hipStream_t s, float thr, int ns,
+                    const uint8_t **sel, bool pack);
 size_t net_forward_bytes(int H, int W);
-hipError_t launch_learned_select(const float *z, float thr, const SelectArgs &a, int H, int W, unsigned *fallback,
+// fallback: kFallbackSlots counters, summed into *total by launch_fallback_sum
+constexpr int kFallbackSlots = 64;
+hipError_t launch_learned_select(const uint8_t *sel, const SelectArgs &a, int H, int W, unsigned *fallback,
                                  hipStream_t s);
+hipError_t launch_fallback_sum(const unsigned *slots, unsigned *total, hipStream_t s);
 
 }  // namespace mf4d
