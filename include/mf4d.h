@@ -23,8 +23,14 @@
  *  - Every function returns an int status (MF4D_OK = 0 or a negative code).
  *    Arguments are validated on the host before anything is enqueued; on an
  *    error nothing is enqueued. No exceptions cross the ABI.
- *  - The library is stateless, hence thread-safe for distinct streams and
- *    workspaces.
+ *  - The only state the library keeps is, per host thread and device, three
+ *    non-blocking side streams and their events (default priority), created
+ *    on the first multi-scale call and kept until the process ends. The
+ *    scales of a cycle are forked onto them from `stream` with events and
+ *    joined back before anything else is enqueued, so the calls keep the
+ *    ordering of `stream`. Setting the
+ *    environment variable MF4D_FORK=0 keeps all work on `stream`. Calls are
+ *    thread-safe for distinct streams and workspaces.
  */
 #ifndef MF4D_H
 #define MF4D_H
