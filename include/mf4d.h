@@ -28,9 +28,9 @@
  *    on the first multi-scale call and kept until the process ends. The
  *    scales of a cycle are forked onto them from `stream` with events and
  *    joined back before anything else is enqueued, so the calls keep the
- *    ordering of `stream`. Setting the
- *    environment variable MF4D_FORK=0 keeps all work on `stream`. Calls are
- *    thread-safe for distinct streams and workspaces.
+ *    ordering of `stream`. The environment variable MF4D_FORK=0 keeps all
+ *    work on `stream`. Calls are thread-safe for distinct streams and
+ *    workspaces.
  */
 #ifndef MF4D_H
 #define MF4D_H
