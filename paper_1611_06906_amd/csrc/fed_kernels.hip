@@ -16,6 +16,7 @@
 //    registers (fed_tiles.h); one or two columns per lane, the same values.
 #include "mf4d_internal.h"
 #include "tensor_math.h"
+#include <atomic>
 #include <cstdlib>
 
 #include "fed_tiles.h"
@@ -146,17 +147,21 @@ hipError_t launch_fed_substep(const float *u_in, float *u_out, const float *hrho
 // one CU holds at once, and the device's CU count (cached per device).
 int stream_blocks_per_cu(int steps, int *cus)
 {
-    static int cache[16][3][5];   // [device][cols][steps]: 0 = not yet asked
-    static int ncu[16];
+    // filled on first use; threads that race here store the same values
+    static std::atomic<int> cache[16][3][5];   // [device][cols][steps]: 0 = not yet asked
+    static std::atomic<int> ncu[16];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) dev = 0;
     if (steps < 1 || steps > 4) steps = 4;
     const int cols = stream_cols_per_lane(steps);
-    if (!ncu[dev] && hipDeviceGetAttribute(&ncu[dev], hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        ncu[dev] = 256;
-    int &c = cache[dev][cols][steps];
-    if (!c) {
-        int nb = 0;
+    int n = ncu[dev].load(std::memory_order_relaxed);
+    if (!n) {
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 256;
+        ncu[dev].store(n, std::memory_order_relaxed);
+    }
+    std::atomic<int> &c = cache[dev][cols][steps];
+    int nb = c.load(std::memory_order_relaxed);
+    if (!nb) {
         const void *fn = nullptr;
         switch (steps) {
         case 1: fn = cols == 2 ? (const void *)fed_stream2_kernel<1> : (const void *)fed_stream_kernel<1>; break;
@@ -165,10 +170,10 @@ int stream_blocks_per_cu(int steps, int *cus)
         default: fn = cols == 2 ? (const void *)fed_stream2_kernel<4> : (const void *)fed_stream_kernel<4>; break;
         }
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, 0) != hipSuccess || nb < 1) nb = 1;
-        c = nb;
+        c.store(nb, std::memory_order_relaxed);
     }
-    *cus = ncu[dev];
-    return c;
+    *cus = n;
+    return nb;
 }
 
 int stream_cols_per_lane(int steps)
