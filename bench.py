@@ -4,7 +4,10 @@ A step is one mf4d_filter call over the roofline-scale workload: a 4096 x 4096
 float32 image with 64 bright and dark creases (widths 1-16 px, noise
 N(0, 0.05)), 8 log-spaced scales 1..16, ridge+valley mode, 30 FED cycles of
 20 substeps -- scale selection, normalised Hessian and every substep included,
-with the input already resident in HBM.
+with the input already resident in HBM. The call is recorded once into a
+hipGraph and each step replays it (the same kernels and launch shapes as the
+eager call, which gives the same bits); --eager times the call itself, and
+the graph run reports the eager time beside it.
 
 Prints one JSON line:
   value     Mpixel-FED-substeps/s of the whole filter (H W M n per step / time)
@@ -15,7 +18,7 @@ Prints one JSON line:
   roofline_sweep  the fused scale-sweep kernel at sigma = 16 (both separable
             passes of one scale on the matrix cores): algorithmic flops
             (8 filters x 99 taps x 2 per pixel) against the FP32 MFMA peak
-  cpu_baseline  the FP64 oracle on a bounded sample (one cycle of the same image)
+  cpu_baseline  the FP64 oracle on a bounded sample (the first 3 cycles of the same image)
 """
 from __future__ import annotations
 
@@ -35,6 +38,7 @@ MFMA_F32_PEAK = 157.3e12   # FLOP/s, dense FP32 matrix cores
 SUBSTEP_BYTES_PER_PX = 20  # per launch: u in 4 + tensor planes in 12 + u out 4
 SUBSTEP_FLOPS_PER_PX = 37  # per substep: L u 10, D L u 13, L^T and update 14
 SUBSTEPS_PER_LAUNCH = 4    # as mf4d_filter launches the fused substep kernel (two columns per lane)
+CPU_CYCLES = 3             # FED cycles of the oracle's bounded sample (about 15 s on 16 host cores)
 
 
 CSRC = os.path.join(ROOT, "paper_1611_06906_amd", "csrc")
@@ -271,6 +275,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stages", action="store_true")
     ap.add_argument("--no-extensions", action="store_true", help="skip the batched comparison")
+    ap.add_argument("--eager", action="store_true", help="time eager mf4d_filter calls instead of graph replays")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -293,7 +298,17 @@ def main():
     ws = mf4d.workspace(w.H, w.W, p, dev)
     torch.cuda.synchronize()
 
-    step = lambda: mf4d.mf4d_filter(u_in, u_out, p, ws)
+    eager = lambda: mf4d.mf4d_filter(u_in, u_out, p, ws)
+    eager()   # the side streams of the concurrent scales exist before a capture
+    torch.cuda.synchronize()
+    if args.eager:
+        step = eager
+    else:
+        # one whole filter call recorded into a hipGraph, replayed once per step
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            eager()
+        step = graph.replay
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -301,8 +316,10 @@ def main():
     ms = time_stream(torch, step, args.steps)
     px_sub = w.H * w.W * w.cycles * w.substeps
     value = px_sub / (ms * 1e-3) / 1e6
-    print(f"[bench] {args.steps} steps, {ms:.2f} ms/step, {value:.0f} Mpx-substeps/s", file=sys.stderr,
+    launch = "eager mf4d_filter calls" if args.eager else "hipGraph replays of one recorded mf4d_filter call"
+    print(f"[bench] {args.steps} steps ({launch}), {ms:.2f} ms/step, {value:.0f} Mpx-substeps/s", file=sys.stderr,
           flush=True)
+    ms_eager = ms if args.eager else time_stream(torch, eager, args.steps)
 
     # roofline of the fused FED substep kernel as the filter launches it: same
     # kernel, shapes, substeps per launch and tensor planes of the workload
@@ -395,13 +412,13 @@ def main():
         cores = len(os.sched_getaffinity(0))
         omp = int(os.environ.get("OMP_NUM_THREADS", cores))
         t1 = time.time()
-        oracle.filter(u_np, w.sigmas, w.mode, lam=w.lam, rho=w.rho, beta=w.beta, cycles=1,
+        oracle.filter(u_np, w.sigmas, w.mode, lam=w.lam, rho=w.rho, beta=w.beta, cycles=CPU_CYCLES,
                       substeps=w.substeps, tau_max=w.tau_max)
         dt = time.time() - t1
-        cpu = {"value": w.H * w.W * w.substeps / dt / 1e6, "unit": "Mpixel-FED-substeps/s",
+        cpu = {"value": w.H * w.W * w.substeps * CPU_CYCLES / dt / 1e6, "unit": "Mpixel-FED-substeps/s",
                "cores": min(omp, cores), "kind": "oracle",
-               "sample": f"1 of {w.cycles} cycles ({w.substeps} substeps) of the full {w.H}x{w.W} image, "
-                         f"FP64, {dt:.1f} s"}
+               "sample": f"the first {CPU_CYCLES} of {w.cycles} cycles ({w.substeps} substeps each) of the full "
+                         f"{w.H}x{w.W} image, FP64, {dt:.1f} s"}
 
     out = {
         "metric": "Mpixel-FED-substeps/s and % HBM roofline, plain vs batched/learned @ oracle tol",
@@ -411,6 +428,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "ms_per_step_eager": ms_eager,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -419,7 +437,7 @@ def main():
         "config": {"workload": f"{w.name}: {w.H}x{w.W} creases, {len(w.sigmas)} scales 1-16, "
                                f"ridge+valley, {w.cycles} FED cycles x {w.substeps} substeps, plain path",
                    "H": w.H, "W": w.W, "cycles": w.cycles, "substeps": w.substeps,
-                   "nscales": len(w.sigmas), "mode": "both", "path": "plain"},
+                   "nscales": len(w.sigmas), "mode": "both", "path": "plain", "launch": launch},
         "roofline": roofline,
         "roofline_single_substep": roofline_single,
         "roofline_sweep": roofline_sweep,
