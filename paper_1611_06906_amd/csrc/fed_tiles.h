@@ -108,7 +108,6 @@ __device__ __forceinline__ void fed_stream_wave(const float *__restrict__ u, flo
 #pragma unroll
             for (int k = 1; k <= S; ++k) {
                 // flux T_k at row q = y - (2k - 1) from u_{k-1} rows q-1, q, q+1
-                const int q = y - (2 * k - 1);
                 const int wn = (t - 2 * (k - 1) + 300) % 3;        // u_{k-1} row q+1
                 const int wc = (t - 2 * (k - 1) - 1 + 300) % 3;    // row q
                 const int wo = (t - 2 * (k - 1) - 2 + 300) % 3;    // row q-1

@@ -324,7 +324,8 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
     constexpr int NU = 2 * NG;        // staged values per thread: row 16 h + tid / 16, column 16 g + tid % 16
     float *ring = lds, *us = lds + 3 * PL;
     const int R = t.R;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: the ring slots below are scalar
     const int n = lane & 15, kq = lane >> 4;
     const int tr = tid >> 4, tc = tid & 15;               // staging: row and column of value 0
     const int JL = last_slices<NC>(R);
@@ -428,7 +429,13 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
     __syncthreads();
     const int col = cb + n;
     const int x = x0 + col;
-    const float *rA = ring + col * P, *rB = rA + PL, *rC = rA + 2 * PL;
+    const float *rA = ring + col * P, *rB = rA + PL;
+    // Window reads: slot s0 of a step's first window row is a multiple of 16
+    // (steps of 32 rows, blocks of 16) and RS = 16 (NC + 1), so each 16-slot
+    // chunk wraps around the ring as a whole and its wrap is wave-uniform;
+    // the lane's offset within the chunk (4 kq, or kq in the last chunk's
+    // slices) is added after the wrap.
+    const float *rAq = rA + 4 * kq, *rAk = rA + kq;
     const size_t plane = (size_t)H * W;
     float smax = 0.f;
     // u rows entering the window two steps ahead: loaded at the end of the
@@ -446,11 +453,12 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
         f4 cuy = {0.f, 0.f, 0.f, 0.f}, cuyy = cuy, cux = cuy, cuxy = cuy, cuxx = cuy;
 #pragma unroll
         for (int c = 0; c < NC - 1; ++c) {
-            int s = s0 + 16 * c + 4 * kq;
-            s = s >= RS ? s - RS : s;
-            const f4 va = *(const f4 *)(rA + s) - aref;
-            const f4 vb = *(const f4 *)(rB + s) - bref;
-            const f4 vc = *(const f4 *)(rC + s);
+            int sc = s0 + 16 * c;
+            sc = sc >= RS ? sc - RS : sc;
+            const float *q = rAq + sc;
+            const f4 va = *(const f4 *)q - aref;
+            const f4 vb = *(const f4 *)(q + PL) - bref;
+            const f4 vc = *(const f4 *)(q + 2 * PL);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 cuy = mfma_f32(a1[c][j], va[j], cuy);
@@ -460,12 +468,13 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
                 cuxx = mfma_f32(ag[c][j], vc[j], cuxx);
             }
         }
+        int sl = s0 + 16 * (NC - 1);
+        sl = sl >= RS ? sl - RS : sl;
+        const float *ql = rAk + sl;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             if (j < JL) {   // last chunk, contiguous slices
-                int s = s0 + 16 * (NC - 1) + 4 * j + kq;
-                s = s >= RS ? s - RS : s;
-                const float va = rA[s] - aref, vb = rB[s] - bref, vc = rC[s];
+                const float va = ql[4 * j] - aref, vb = ql[PL + 4 * j] - bref, vc = ql[2 * PL + 4 * j];
                 cuy = mfma_f32(a1[NC - 1][j], va, cuy);
                 cuyy = mfma_f32(a2[NC - 1][j], va, cuyy);
                 cux = mfma_f32(ag[NC - 1][j], vb, cux);
@@ -477,7 +486,8 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
         hpass_block(hg, h1, h2);
         __syncthreads();   // the window's first 32 rows and the staged rows have been read
         if (more) {
-            ring_put((yb - ys + rb + n) % RS, hg, h1, h2);   // slots of rows yb - R .. yb - R + 31
+            // slots of rows yb - R .. yb - R + 31: a wave-uniform multiple of 16 plus n
+            ring_put((yb - ys + rb) % RS + n, hg, h1, h2);
             store_u(v);
         }
         load_u(yb + 2 * kVMStep - R + RS, v);
