@@ -281,12 +281,13 @@ int run_substeps(const float *u_first, float *const bufs[2], int &launch_index, 
 }
 
 // Scale sweep over all scales: S and blob planes (when want_sa), N planes
-// (when want_n) and the image-wide maximum of S.
+// (when want_n) and the image-wide maximum of S (cleared first unless
+// clear_max is false: an earlier kernel on the stream has left it at 0).
 int run_sweep(const float *u, int H, int W, const mf4d_params *p, const Workspace &w,
-              bool want_n, hipStream_t s)
+              bool want_n, hipStream_t s, bool clear_max = true)
 {
     const size_t m = (size_t)H * W;
-    CHECK_HIP(launch_fill_u32(w.smax, 0u, 1, s));
+    if (clear_max) CHECK_HIP(launch_fill_u32(w.smax, 0u, 1, s));
     std::vector<WinTaps> taps(p->nscales);
     bool fused = true;   // the fused kernels need no shared scratch: scales may run concurrently
     for (int k = 0; k < p->nscales; ++k) {
@@ -571,10 +572,11 @@ int mf4d_filter(const float *u_in, float *u_out, int H, int W, const mf4d_params
     }
     SelectArgs a = select_args(p, w);
     a.coef = w.tens;
+    a.smax_reset = w.smax;   // each cycle's integration clears the max of S for the next cycle's sweep
     int li = 0;
     for (int k = 0; k < p->cycles; ++k) {
         const bool reselect = (k == 0) || p->reselect_each_cycle;
-        st = run_sweep(src, H, W, p, w, true, s);
+        st = run_sweep(src, H, W, p, w, true, s, k == 0);
         if (st != MF4D_OK) return st;
         SelectArgs ak = a;
         if (reselect) ak.idx_out = w.idx;

@@ -95,6 +95,7 @@ struct SelectArgs {
     int mode;
     float inv_lam2;
     RhoTaps rho;
+    unsigned *smax_reset;   // nullable: the integration kernel sets it to 0 (the argmax has read it by then)
 };
 hipError_t launch_select(const SelectArgs &a, int H, int W, hipStream_t s);
 

@@ -120,8 +120,12 @@ __global__ __launch_bounds__(256) void argmax_kernel(SelectArgs a, size_t plane)
 template <int HR>
 __global__ __launch_bounds__(256) void rho_blur_kernel(const float *__restrict__ N, const uint8_t *__restrict__ idx,
                                                        int ns, float *__restrict__ Hr, float *__restrict__ coef,
-                                                       int mode, float inv_lam2, int H, int W, RhoTaps t, int tiles_x)
+                                                       int mode, float inv_lam2, int H, int W, RhoTaps t, int tiles_x,
+                                                       unsigned *smax_reset)
 {
+    // the image-wide max of S starts the next cycle at 0 (the argmax before
+    // this kernel on the stream has read it)
+    if (smax_reset && blockIdx.x == 0 && threadIdx.x == 0) *smax_reset = 0u;
     rho_blur_tile<HR>(N, idx, ns, Hr, coef, mode, inv_lam2, H, W, t, (blockIdx.x % tiles_x) * kBTW,
                       (blockIdx.x / tiles_x) * kBTH);
 }
@@ -292,7 +296,7 @@ hipError_t launch_rho(const SelectArgs &a, int H, int W, hipStream_t s)
 #define MF4D_RHO_ONLY(R)                                                                                       \
     case R:                                                                                                    \
         hipLaunchKernelGGL(rho_blur_kernel<R>, grid, block, 0, s, src, gidx, a.ns, a.hrho, a.coef, a.mode,       \
-                           a.inv_lam2, H, W, a.rho, tiles_x);                                                  \
+                           a.inv_lam2, H, W, a.rho, tiles_x, a.smax_reset);                                    \
         break;
         MF4D_RHO_ONLY(0) MF4D_RHO_ONLY(1) MF4D_RHO_ONLY(2) MF4D_RHO_ONLY(3) MF4D_RHO_ONLY(4)
         MF4D_RHO_ONLY(5) MF4D_RHO_ONLY(6) MF4D_RHO_ONLY(7) MF4D_RHO_ONLY(8)
