@@ -29,8 +29,12 @@
  *    scales of a cycle are forked onto them from `stream` with events and
  *    joined back before anything else is enqueued, so the calls keep the
  *    ordering of `stream`. The environment variable MF4D_FORK=0 keeps all
- *    work on `stream`. Calls are thread-safe for distinct streams and
- *    workspaces.
+ *    work on `stream`; if the side streams cannot be created, the thread
+ *    keeps all work on `stream` from then on. A call enqueues only kernels
+ *    and event edges, so it can be recorded into a hipGraph; make one
+ *    eager multi-scale call on the thread first, so that the side streams
+ *    are not created during the capture. Calls are thread-safe for distinct
+ *    streams and workspaces.
  */
 #ifndef MF4D_H
 #define MF4D_H
