@@ -138,3 +138,44 @@ def test_batch_strided_offsets(env):
     got = torch.cat([pout[o:o + h * w] for o, (h, w) in zip(offs, SHAPES)])
     assert _same(got, ref)
     b.close()
+
+
+def test_batch_total_beyond_2e31_pixels(env):
+    """Two images of 46000 x 25000 (2.3 G px packed, past element 2^31 of the
+    packed buffers): the batch equals per-image calls bit for bit."""
+    m, synth, torch = env["m"], env["synth"], env["torch"]
+    dev = env["dev"]
+    H, W = 46000, 25000
+    n = H * W
+    assert n < 2 ** 31 < 2 * n
+
+    def folded(tile):   # the tile's half-sample-symmetric periodic extension, H x W
+        th, tw = tile.shape
+        iy = torch.arange(H, device=dev) % (2 * th)
+        iy = torch.where(iy < th, iy, 2 * th - 1 - iy)
+        ix = torch.arange(W, device=dev) % (2 * tw)
+        ix = torch.where(ix < tw, ix, 2 * tw - 1 - ix)
+        return torch.from_numpy(tile).to(dev)[iy][:, ix]
+
+    _log(f"batch of two {H} x {W} images ({2 * n} px packed)")
+    p = m.Params([1.0], mode=0, cycles=1, substeps=4)
+    pin = torch.empty(2 * n, dtype=torch.float32, device=dev)
+    for k in range(2):
+        pin[k * n:(k + 1) * n] = folded(synth.creases(230, 250, 3, seed=70 + k)).ravel()
+    b = m.Batch([(H, W)] * 2, [p, p])
+    ws = b.workspace(dev)
+    pout = torch.empty_like(pin)
+    b.filter(pin, pout, ws)
+    torch.cuda.synchronize()
+    b.close()
+    del ws
+    torch.cuda.empty_cache()
+    ws1 = m.workspace(H, W, p, dev)
+    ref = torch.empty((H, W), dtype=torch.float32, device=dev)
+    for k in range(2):
+        m.mf4d_filter(pin[k * n:(k + 1) * n].view(H, W), ref, p, ws1)
+        torch.cuda.synchronize()
+        assert torch.equal(pout[k * n:(k + 1) * n].view(H, W), ref), k
+        assert not torch.equal(ref, pin[k * n:(k + 1) * n].view(H, W))
+    del ws1, ref, pin, pout
+    torch.cuda.empty_cache()
