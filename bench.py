@@ -301,14 +301,18 @@ def main():
     eager = lambda: mf4d.mf4d_filter(u_in, u_out, p, ws)
     eager()   # the side streams of the concurrent scales exist before a capture
     torch.cuda.synchronize()
-    if args.eager:
-        step = eager
-    else:
+    step, launch = eager, "eager mf4d_filter calls"
+    if not args.eager:
         # one whole filter call recorded into a hipGraph, replayed once per step
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            eager()
-        step = graph.replay
+        try:
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                eager()
+            step, launch = graph.replay, "hipGraph replays of one recorded mf4d_filter call"
+        except RuntimeError as e:   # time the eager calls and say why
+            torch.cuda.synchronize()
+            launch = f"eager mf4d_filter calls (graph recording failed: {e})"
+            print(f"[bench] {launch}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -316,10 +320,9 @@ def main():
     ms = time_stream(torch, step, args.steps)
     px_sub = w.H * w.W * w.cycles * w.substeps
     value = px_sub / (ms * 1e-3) / 1e6
-    launch = "eager mf4d_filter calls" if args.eager else "hipGraph replays of one recorded mf4d_filter call"
     print(f"[bench] {args.steps} steps ({launch}), {ms:.2f} ms/step, {value:.0f} Mpx-substeps/s", file=sys.stderr,
           flush=True)
-    ms_eager = ms if args.eager else time_stream(torch, eager, args.steps)
+    ms_eager = ms if step is eager else time_stream(torch, eager, args.steps)
 
     # roofline of the fused FED substep kernel as the filter launches it: same
     # kernel, shapes, substeps per launch and tensor planes of the workload
