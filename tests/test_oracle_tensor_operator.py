@@ -57,6 +57,31 @@ def test_tensor_eigen_structure(oracle_lib):
         assert np.allclose(mu, [m1, m2, (m1 + m2) / 2, 0.0], atol=1e-12)
 
 
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_tensor_compact_form(oracle_lib, mode):
+    """With mu3 the mean of mu1 and mu2 and mu4 = 0 (Sec. 3.2), D[xx][yy]
+    vanishes and D acts on a symmetric h through three numbers:
+    T_xx = (mb + al) h_xx + be h_xy, T_xy = T_yx = mb h_xy + be (h_xx + h_yy) / 2,
+    T_yy = (mb - al) h_yy + be h_xy, with mb = (D00 + D33) / 2,
+    al = (D00 - D33) / 2 and be = D01 + D02, where mb = (mu1 + mu2) / 2 and
+    (al, be) = (mu1 - mu2) / 2 (cos 2t, sin 2t) for the angle t of e1."""
+    rng = np.random.default_rng(40 + mode)
+    for _ in range(200):
+        a, b, d = rng.normal(scale=0.01, size=3)
+        D, e, mu = oracle_lib.dtensor_px(a, b, d, 0.005, mode)
+        assert abs(D[0, 3]) <= 1e-15 and abs(D[3, 0]) <= 1e-15
+        mb, al, be = (D[0, 0] + D[3, 3]) / 2, (D[0, 0] - D[3, 3]) / 2, D[0, 1] + D[0, 2]
+        t = math.atan2(e[1], e[0])   # e holds e1 = (cos t, sin t) first
+        assert math.isclose(mb, (mu[0] + mu[1]) / 2, abs_tol=1e-14)
+        assert math.isclose(al, (mu[0] - mu[1]) / 2 * math.cos(2 * t), abs_tol=1e-14)
+        assert math.isclose(be, (mu[0] - mu[1]) / 2 * math.sin(2 * t), abs_tol=1e-14)
+        hxx, hxy, hyy = rng.normal(size=3)
+        T = D @ np.array([hxx, hxy, hxy, hyy])
+        want = [(mb + al) * hxx + be * hxy, mb * hxy + be * (hxx + hyy) / 2, mb * hxy + be * (hxx + hyy) / 2,
+                (mb - al) * hyy + be * hxy]
+        assert np.allclose(T, want, rtol=0, atol=1e-14)
+
+
 def test_tensor_acts_by_rotation(oracle_lib):
     # independent route: rotate a symmetric H into the eigenbasis of H_rho,
     # scale (h11, h12, h22) by (mu1, mu3, mu2), rotate back
