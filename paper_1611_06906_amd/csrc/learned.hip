@@ -49,11 +49,8 @@ __host__ __device__ constexpr int wsize(int l) { return 9 * kCP[l + 1] * kCP[l];
 
 __device__ __forceinline__ uint16_t to_bf16(float f)
 {
-    // round to nearest even
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    // round to nearest even: one v_cvt_pk_bf16_f32 on gfx950
+    return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -63,7 +60,7 @@ enum { EPI_RELU = 0, EPI_LINEAR = 1, EPI_MASK = 2, EPI_SELECT = 3 };
 
 // ------------------------------------------------------------------ forward
 template <int CINP, int COUTP, int EPI>
-__global__ __launch_bounds__(256) void conv_kernel(const uint16_t *__restrict__ in, const uint16_t *__restrict__ wt,
+__global__ __launch_bounds__(256, 4) void conv_kernel(const uint16_t *__restrict__ in, const uint16_t *__restrict__ wt,
                                                    const float *__restrict__ bias, const uint16_t *__restrict__ mask,
                                                    void *__restrict__ out, int H, int W, int tiles_per_img,
                                                    float thr = 0.f, int ns = 0)
