@@ -80,6 +80,78 @@ __host__ __device__ __forceinline__ int last_slices(int R)
     return z <= 0 ? 0 : (z >= 16 ? 4 : (z + 3) / 4);
 }
 
+// ------------------------------------------------------------------ split BF16
+// Products of FP32 values on the BF16 matrix cores: each value x is split by
+// truncation into three BF16 parts, x = hi + mid + lo exactly (8 significant
+// bits each), and a product a b is taken as the six part products above
+// 2^-24 |a b| (hi hi, hi mid, mid hi, hi lo, lo hi, mid mid), accumulated in
+// FP32 by v_mfma_f32_16x16x32_bf16 in that fixed order.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+union BF8 {
+    uint32_t u[4];
+    bf8 v;
+};
+
+__device__ __forceinline__ float bf_trunc(float x) { return __uint_as_float(__float_as_uint(x) & 0xffff0000u); }
+__device__ __forceinline__ uint32_t bf_pack(float a, float b)   // a, b exact in BF16: a low half, b high half
+{
+    return (__float_as_uint(a) >> 16) | (__float_as_uint(b) & 0xffff0000u);
+}
+
+__device__ __forceinline__ void split3(const float (&x)[8], BF8 &h, BF8 &m, BF8 &l)
+{
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float x0 = x[2 * q], x1 = x[2 * q + 1];
+        const float h0 = bf_trunc(x0), h1 = bf_trunc(x1);
+        const float r0 = x0 - h0, r1 = x1 - h1;
+        const float m0 = bf_trunc(r0), m1 = bf_trunc(r1);
+        h.u[q] = bf_pack(h0, h1);
+        m.u[q] = bf_pack(m0, m1);
+        l.u[q] = bf_pack(r0 - m0, r1 - m1);
+    }
+}
+
+struct BF3 {
+    BF8 h, m, l;
+};
+
+__device__ __forceinline__ f4 mfma_bf3(const BF3 &a, const BF3 &b, f4 c)
+{
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h.v, b.h.v, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h.v, b.m.v, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.m.v, b.h.v, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h.v, b.l.v, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.l.v, b.h.v, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.m.v, b.m.v, c, 0, 0, 0);
+    return c;
+}
+
+// This lane's Toeplitz entries of 32-input slice sl, split: tap[k - m] for
+// row m = lane % 16 and input k = 32 sl + 8 (lane / 16) + j, j = 0..7.
+template <int NSL>
+__device__ __forceinline__ void toeplitz_bf3(const float *tap, int R, BF3 (&a)[NSL])
+{
+    const int lane = threadIdx.x & 63, m = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int sl = 0; sl < NSL; ++sl) {
+        float x[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int t = 32 * sl + 8 * g + j - m;
+            x[j] = (t >= 0 && t <= 2 * R) ? tap[t] : 0.f;
+        }
+        split3(x, a[sl].h, a[sl].m, a[sl].l);
+    }
+}
+
+__device__ __forceinline__ void split8(const f4 &x0, const f4 &x1, BF3 &b)
+{
+    const float x[8] = {x0[0], x0[1], x0[2], x0[3], x1[0], x1[1], x1[2], x1[3]};
+    split3(x, b.h, b.m, b.l);
+}
+
 // ------------------------------------------------------------------ horizontal
 // Tile: 16 rows x 256 output columns at (x0, y0); wave w owns columns
 // 64w .. 64w+63 as four 16 x 16 blocks. The rows' inputs (x0 - R onwards)
@@ -305,6 +377,11 @@ __device__ __forceinline__ float vpass_mfma_tile(const float *__restrict__ A, co
 // whose products and per-pixel outputs are those of vpass_mfma_tile; the
 // values equal those of the two separate passes bit for bit. Rows outside
 // the image are the horizontal pass of the reflected row of u.
+// With 4, 6 or 8 chunks (the scales bound by the matrix cores) the products
+// are split-BF16 instead (32-input slices on v_mfma_f32_16x16x32_bf16, six
+// part products per FP32 product): the same staging, shifts, ring and
+// epilogue, about 1.25x the rate of the FP32 form at sigma = 16, but not the
+// bits of the FP32 split passes.
 __host__ __device__ constexpr size_t fused_lds(int nc) { return sizeof(float) * 4 * kVMW * (16 * nc + 16 + 4); }
 
 template <int NC>
@@ -331,10 +408,21 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
     const int JL = last_slices<NC>(R);
     const int cb = 16 * (wv & 1), rb = 16 * (wv >> 1);   // this wave's block: columns cb.., rows rb..
     const bool xin = (x0 - R >= 0) && (x0 - R + UW <= W);
-    float ag[NC][4], a1[NC][4], a2[NC][4];
-    toeplitz_lane<NC>(t.g, R, ag);
-    toeplitz_lane<NC>(t.d1, R, a1);
-    toeplitz_lane<NC>(t.d2, R, a2);
+    // 4 and 6 chunks: split-BF16 products over NC / 2 slices of 32 inputs
+    constexpr bool BF = (NC == 4 || NC == 6 || NC == 8);
+    constexpr int NSL = BF ? NC / 2 : 1;
+    constexpr int NCF = BF ? 1 : NC;
+    float ag[NCF][4], a1[NCF][4], a2[NCF][4];
+    BF3 bg[NSL], b1[NSL], b2[NSL];
+    if constexpr (BF) {
+        toeplitz_bf3<NSL>(t.g, R, bg);
+        toeplitz_bf3<NSL>(t.d1, R, b1);
+        toeplitz_bf3<NSL>(t.d2, R, b2);
+    } else {
+        toeplitz_lane<NC>(t.g, R, ag);
+        toeplitz_lane<NC>(t.d1, R, a1);
+        toeplitz_lane<NC>(t.d2, R, a2);
+    }
     const float gsum = t.gsum;
     // 32 rows of u from row r0 on (reflected), all loads before any LDS store;
     // value 2 g + h is row r0 + 16 h + tr, column x0 - R + 16 g + tc, so inside
@@ -375,8 +463,21 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
         hg = (f4){0.f, 0.f, 0.f, 0.f};
         h1 = hg;
         h2 = hg;
+        if constexpr (BF) {
 #pragma unroll
-        for (int c = 0; c < NC - 1; ++c) {
+            for (int sl = 0; sl < NSL; ++sl) {
+                const float *q = row + cb + 32 * sl + 8 * kq;
+                BF3 b;
+                split8(*(const f4 *)q - ref, *(const f4 *)(q + 4) - ref, b);
+                hg = mfma_bf3(bg[sl], b, hg);
+                h1 = mfma_bf3(b1[sl], b, h1);
+                h2 = mfma_bf3(b2[sl], b, h2);
+            }
+            hg = hg + ref * gsum;
+            return;
+        }
+#pragma unroll
+        for (int c = 0; c < NCF - 1; ++c) {
             const f4 b = *(const f4 *)(row + cb + 16 * c + 4 * kq) - ref;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -388,10 +489,10 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             if (j < JL) {   // last chunk, contiguous slices
-                const float b = row[cb + 16 * (NC - 1) + 4 * j + kq] - ref;
-                hg = mfma_f32(ag[NC - 1][j], b, hg);
-                h1 = mfma_f32(a1[NC - 1][j], b, h1);
-                h2 = mfma_f32(a2[NC - 1][j], b, h2);
+                const float b = row[cb + 16 * (NCF - 1) + 4 * j + kq] - ref;
+                hg = mfma_f32(ag[NCF - 1][j], b, hg);
+                h1 = mfma_f32(a1[NCF - 1][j], b, h1);
+                h2 = mfma_f32(a2[NCF - 1][j], b, h2);
             }
         hg = hg + ref * gsum;
     };
@@ -451,8 +552,27 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
         const int sr = (y0 - ys + R) % RS;       // slot of row y0
         const float aref = rA[sr], bref = rB[sr];
         f4 cuy = {0.f, 0.f, 0.f, 0.f}, cuyy = cuy, cux = cuy, cuxy = cuy, cuxx = cuy;
+        if constexpr (BF) {
+            // window rows 32 sl + 8 kq .. + 7 of this lane: an 8-slot group that
+            // wraps around the ring as a whole (s0 and RS are multiples of 16)
 #pragma unroll
-        for (int c = 0; c < NC - 1; ++c) {
+            for (int sl = 0; sl < NSL; ++sl) {
+                int sg = s0 + 32 * sl + 8 * kq;
+                sg = sg >= RS ? sg - RS : sg;
+                const float *q = rA + sg;
+                BF3 va, vb, vc;
+                split8(*(const f4 *)q - aref, *(const f4 *)(q + 4) - aref, va);
+                split8(*(const f4 *)(q + PL) - bref, *(const f4 *)(q + PL + 4) - bref, vb);
+                split8(*(const f4 *)(q + 2 * PL), *(const f4 *)(q + 2 * PL + 4), vc);
+                cuy = mfma_bf3(b1[sl], va, cuy);
+                cuyy = mfma_bf3(b2[sl], va, cuyy);
+                cux = mfma_bf3(bg[sl], vb, cux);
+                cuxy = mfma_bf3(b1[sl], vb, cuxy);
+                cuxx = mfma_bf3(bg[sl], vc, cuxx);
+            }
+        } else {
+#pragma unroll
+        for (int c = 0; c < NCF - 1; ++c) {
             int sc = s0 + 16 * c;
             sc = sc >= RS ? sc - RS : sc;
             const float *q = rAq + sc;
@@ -468,19 +588,20 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
                 cuxx = mfma_f32(ag[c][j], vc[j], cuxx);
             }
         }
-        int sl = s0 + 16 * (NC - 1);
+        int sl = s0 + 16 * (NCF - 1);
         sl = sl >= RS ? sl - RS : sl;
         const float *ql = rAk + sl;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             if (j < JL) {   // last chunk, contiguous slices
                 const float va = ql[4 * j] - aref, vb = ql[PL + 4 * j] - bref, vc = ql[2 * PL + 4 * j];
-                cuy = mfma_f32(a1[NC - 1][j], va, cuy);
-                cuyy = mfma_f32(a2[NC - 1][j], va, cuyy);
-                cux = mfma_f32(ag[NC - 1][j], vb, cux);
-                cuxy = mfma_f32(a1[NC - 1][j], vb, cuxy);
-                cuxx = mfma_f32(ag[NC - 1][j], vc, cuxx);
+                cuy = mfma_f32(a1[NCF - 1][j], va, cuy);
+                cuyy = mfma_f32(a2[NCF - 1][j], va, cuyy);
+                cux = mfma_f32(ag[NCF - 1][j], vb, cux);
+                cuxy = mfma_f32(a1[NCF - 1][j], vb, cuxy);
+                cuxx = mfma_f32(ag[NCF - 1][j], vc, cuxx);
             }
+        }
         // horizontal products of the rows entering the next window
         f4 hg, h1, h2;
         hpass_block(hg, h1, h2);
