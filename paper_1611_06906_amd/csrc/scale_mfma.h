@@ -1,6 +1,7 @@
-// Matrix-core (FP32 MFMA) forms of the two separable passes of the scale
-// sweep (Sec. 3.3, derivatives of u_sigma for Eq. (9) and Eq. (6)), shared by
-// the single-image and the batched kernels.
+// Matrix-core forms of the two separable passes of the scale sweep
+// (Sec. 3.3, derivatives of u_sigma for Eq. (9) and Eq. (6)), shared by the
+// single-image and the batched kernels: FP32 MFMA products, and in the fused
+// kernel at 4, 6 and 8 chunks split-BF16 products (see "split BF16" below).
 //
 // A 1-D correlation of 16 consecutive outputs with a (2R+1)-tap filter is the
 // product of a 16 x K banded Toeplitz matrix T[m][k] = tap[k - m] with the K
