@@ -1,7 +1,7 @@
 // Matrix-core forms of the two separable passes of the scale sweep
 // (Sec. 3.3, derivatives of u_sigma for Eq. (9) and Eq. (6)), shared by the
 // single-image and the batched kernels: FP32 MFMA products, and in the fused
-// kernel at 4, 6 and 8 chunks split-BF16 products (see "split BF16" below).
+// kernel at even chunk counts split-BF16 products (see "split BF16" below).
 //
 // A 1-D correlation of 16 consecutive outputs with a (2R+1)-tap filter is the
 // product of a 16 x K banded Toeplitz matrix T[m][k] = tap[k - m] with the K
@@ -378,11 +378,12 @@ __device__ __forceinline__ float vpass_mfma_tile(const float *__restrict__ A, co
 // whose products and per-pixel outputs are those of vpass_mfma_tile; the
 // values equal those of the two separate passes bit for bit. Rows outside
 // the image are the horizontal pass of the reflected row of u.
-// With 4, 6 or 8 chunks (the scales bound by the matrix cores) the products
-// are split-BF16 instead (32-input slices on v_mfma_f32_16x16x32_bf16, six
-// part products per FP32 product): the same staging, shifts, ring and
-// epilogue, about 1.25x the rate of the FP32 form at sigma = 16, but not the
-// bits of the FP32 split passes.
+// With an even number of chunks the products are split-BF16 instead
+// (32-input slices on v_mfma_f32_16x16x32_bf16, six part products per FP32
+// product): the same staging, shifts, ring and epilogue, about 1.25x the rate
+// of the FP32 form at sigma = 16, but not the bits of the FP32 split passes.
+// Odd chunk counts keep FP32 products: 32-input slices would read past the
+// staged row.
 __host__ __device__ constexpr size_t fused_lds(int nc) { return sizeof(float) * 4 * kVMW * (16 * nc + 16 + 4); }
 
 template <int NC>
@@ -409,8 +410,8 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
     const int JL = last_slices<NC>(R);
     const int cb = 16 * (wv & 1), rb = 16 * (wv >> 1);   // this wave's block: columns cb.., rows rb..
     const bool xin = (x0 - R >= 0) && (x0 - R + UW <= W);
-    // 4 and 6 chunks: split-BF16 products over NC / 2 slices of 32 inputs
-    constexpr bool BF = (NC == 4 || NC == 6 || NC == 8);
+    // even chunk counts: split-BF16 products over NC / 2 slices of 32 inputs
+    constexpr bool BF = (NC % 2 == 0);
     constexpr int NSL = BF ? NC / 2 : 1;
     constexpr int NCF = BF ? 1 : NC;
     float ag[NCF][4], a1[NCF][4], a2[NCF][4];

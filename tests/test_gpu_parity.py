@@ -250,11 +250,11 @@ def test_scale_select_large_scales(env, engine, mode, monkeypatch):
 
 
 def test_sweep_segmentation_changes_no_value(env, monkeypatch):
-    """With FP32 products (2, 3, 5 and 7 chunks) the fused kernel equals the
-    two separate matrix-core passes bit for bit, and neither changes any bit
-    with the number of 32-row steps per workgroup."""
+    """With FP32 products (odd chunk counts: 3, 5 and 7) the fused kernel
+    equals the two separate matrix-core passes bit for bit, and neither
+    changes any bit with the number of 32-row steps per workgroup."""
     u = _large_image(env, 260, 200, seed=5)
-    p = env["m"].Params([1.0, 4.0, 10.0, 14.0], mode=2)
+    p = env["m"].Params([3.0, 4.0, 10.0, 14.0], mode=2)
     base = _gpu_select(env, u, p)
     for engine in ("", "split"):
         for rows in ("", "32", "64", "160", "4096"):
@@ -266,10 +266,10 @@ def test_sweep_segmentation_changes_no_value(env, monkeypatch):
 
 
 def test_split_bf16_sweep_segmentation_changes_no_value(env, monkeypatch):
-    """The split-BF16 fused kernels (4, 6 and 8 chunks) give the same bits
+    """The split-BF16 fused kernels (2, 4, 6 and 8 chunks) give the same bits
     for any number of 32-row steps per workgroup."""
     u = _large_image(env, 260, 200, seed=6)
-    p = env["m"].Params([7.0, 11.0, 16.0], mode=2)
+    p = env["m"].Params([1.0, 7.0, 11.0, 16.0], mode=2)
     base = _gpu_select(env, u, p)
     for rows in ("32", "64", "160", "4096"):
         monkeypatch.setenv("MF4D_VSEG_ROWS", rows)
@@ -280,8 +280,8 @@ def test_split_bf16_sweep_segmentation_changes_no_value(env, monkeypatch):
 @pytest.mark.parametrize("mode", [0, 1, 2])
 @pytest.mark.parametrize("shape", [(190, 300), (257, 131)])
 def test_scale_select_split_bf16_scales(env, mode, shape):
-    """Scale selection at scales of 4, 6 and 8 chunks (split-BF16 products)
-    against the oracle."""
+    """Scale selection at scales of 2, 4, 6 and 8 chunks (split-BF16
+    products) against the oracle."""
     sig = [1.0, 7.0, 11.0, 16.0]
     u = _large_image(env, shape[0], shape[1], seed=13 + mode)
     _log(f"scale select split-BF16 scales {shape} mode {mode}")
