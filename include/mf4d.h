@@ -141,6 +141,10 @@ size_t mf4d_workspace_bytes(int H, int W, const mf4d_params *p);
  * symmetric extension at the border, central differences as in Sec. 3.4) is
  * scale-normalised by sigma^2; S, R_B and the vesselness V_s follow Eq. (9)
  * with c = max over all scales and pixels of S / 2 (or params->c when > 0).
+ * The filter products run on the matrix cores at FP32 accuracy: FP32 MFMA,
+ * or split BF16 (each value the exact sum of three BF16 parts, six part
+ * products, FP32 accumulation), so results match an FP64 evaluation to
+ * FP32 rounding, not bit for bit.
  *   u        device, float32 [H][W], read only.
  *   idx_out  device, uint8 [H][W]: smallest s with V_s = max_t V_t.
  *   vmax_out device, float32 [H][W] (nullable): max_t V_t.
