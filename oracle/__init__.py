@@ -60,6 +60,11 @@ _ip = ctypes.POINTER(ctypes.c_int)
 _u8p = ctypes.POINTER(ctypes.c_uint8)
 
 
+class _RefOpts(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int), ("postprocess", ctypes.c_int), ("theta", ctypes.c_double),
+                ("idx_inject", _u8p)]
+
+
 def _declare(L):
     L.ref_fed_n.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_double]
     L.ref_fed_n.restype = ctypes.c_int
@@ -91,7 +96,12 @@ def _declare(L):
                              ctypes.c_int, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                              ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                              ctypes.c_double, ctypes.c_double, ctypes.c_int,
-                             _u8p, _dp, _dp, _dp]
+                             _u8p, _dp, _dp, _dp, ctypes.POINTER(_RefOpts)]
+    L.ref_ifod_diffusivity.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp]
+    L.ref_ifod_dtensor.argtypes = [_dp, ctypes.c_int, ctypes.c_int, _dp]
+    L.ref_cross_direction.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _u8p, _dp, _dp]
+    L.ref_postprocess.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _u8p, _dp, _dp, _dp,
+                                  ctypes.c_double, ctypes.c_int, _u8p]
     L.ref_filter.restype = ctypes.c_int
     L.net_param_count.restype = ctypes.c_int
     L.net_forward.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp]
@@ -236,8 +246,14 @@ def fed_cycle(u, D, ordered_tau):
 
 
 def filter(u, sigmas, mode, lam=0.005, rho=0.5, beta=0.5, c=-1.0, cycles=1, substeps=10,
-           stop_time=0.0, tau_max=0.05, reselect=1, record=False):
-    """The whole filter. Returns u_out, or (u_out, records) if record."""
+           stop_time=0.0, tau_max=0.05, reselect=1, record=False, model=0, postprocess=0,
+           theta=0.2, idx_inject=None):
+    """The whole filter. Returns u_out, or (u_out, records) if record.
+
+    model: 0 the anisotropic filter, 1 IFOD (Eq. (4), g on H(u_sigma) with
+    sigma = sigmas[0]). postprocess, theta: scale-image postprocessing
+    (Sec. 3.3). idx_inject: [cycles][H][W] uint8 scale indices used instead
+    of the selection in each cycle (teacher forcing)."""
     u = _f64(u)
     H, W = u.shape
     sig = _f64(np.asarray(sigmas, dtype=np.float32))
@@ -251,15 +267,96 @@ def filter(u, sigmas, mode, lam=0.005, rho=0.5, beta=0.5, c=-1.0, cycles=1, subs
         args = (idx_rec.ctypes.data_as(_u8p), _d(c_rec), _d(hrho_rec), _d(u_rec))
     else:
         args = (_null(_u8p), _null(_dp), _null(_dp), _null(_dp))
+    inj = None
+    if idx_inject is not None:
+        inj = np.ascontiguousarray(idx_inject, dtype=np.uint8)
+        if inj.shape != (cycles, H, W):
+            raise ValueError("idx_inject must be [cycles][H][W]")
+    opts = _RefOpts(int(model), int(postprocess), float(np.float32(theta)),
+                    inj.ctypes.data_as(_u8p) if inj is not None else _null(_u8p))
     n = lib().ref_filter(_d(u), _d(out), H, W, len(sig), _d(sig), int(mode), lam32,
                          float(np.float32(rho)), float(np.float32(beta)), float(np.float32(c)),
                          int(cycles), int(substeps), float(stop_time), float(tau_max), int(reselect),
-                         *args)
+                         *args, ctypes.byref(opts))
     if n < 0:
         raise ValueError("invalid schedule")
     if record:
         return out, dict(idx=idx_rec, c=c_rec[:cycles], hrho=hrho_rec, u=u_rec, n=n)
     return out
+
+
+def filter_l2stop(u, gt, sigmas, mode, cycles, **kw):
+    """l2-optimal stopping against a noise-free image (Sec. 4: the evolution
+    is stopped where the l2 difference to the ground truth is smallest),
+    taken at the ends of FED cycles. Returns (u_best, e, k_best): e[k] is
+    ||u^k - gt||_2 for k = 0..cycles (u^0 the input), k_best the smallest
+    k of minimal e[k], u_best = u^{k_best}."""
+    u0 = _f64(u)
+    g = _f64(gt)
+    if cycles > 0:
+        _, rec = filter(u, sigmas, mode, cycles=cycles, record=True, **kw)
+        states = [u0] + [rec["u"][k] for k in range(cycles)]
+    else:
+        states = [u0]
+    e = np.array([np.sqrt(np.sum((s - g) ** 2)) for s in states])
+    k = int(np.argmin(e))          # first index of the minimum
+    return states[k].copy(), e, k
+
+
+def ifod_diffusivity(u, sigma, lam=0.005):
+    """g = 1 / (1 + ||H(u_sigma)||_F^2 / lambda^2) (Eq. (4) with Eq. (1));
+    returns (g, hess[3])."""
+    u = _f64(u)
+    H, W = u.shape
+    g = np.zeros_like(u)
+    hess = np.zeros((3, H, W))
+    lib().ref_ifod_diffusivity(_d(u), H, W, float(np.float32(sigma)), float(np.float32(lam)), _d(g), _d(hess))
+    return g, hess
+
+
+def ifod_dtensor(g):
+    """D = g Id as [H][W][16] (vec order xx, xy, yx, yy)."""
+    g = _f64(g)
+    H, W = g.shape
+    out = np.zeros((H, W, 16))
+    lib().ref_ifod_dtensor(_d(g), H, W, _d(out))
+    return out
+
+
+def cross_direction(u, idx, sigmas):
+    """Unit vector across the crease: eigenvector of the stronger eigenvalue
+    of H(u_sigma) at each pixel's selected scale. Returns (ex, ey)."""
+    u = _f64(u)
+    H, W = u.shape
+    sig = _f64(np.asarray(sigmas, dtype=np.float32))
+    idx = np.ascontiguousarray(idx, dtype=np.uint8)
+    ex, ey = np.zeros_like(u), np.zeros_like(u)
+    lib().ref_cross_direction(_d(u), H, W, len(sig), _d(sig), idx.ctypes.data_as(_u8p), _d(ex), _d(ey))
+    return ex, ey
+
+
+def postprocess(idx, vmax, ex, ey, sigmas, theta, tmax=None):
+    """Scale-image postprocessing (Sec. 3.3) from given scale indices, max
+    vesselness and cross directions. tmax defaults to ceil(3 sigma_max)."""
+    idx = np.ascontiguousarray(idx, dtype=np.uint8)
+    H, W = idx.shape
+    sig = _f64(np.asarray(sigmas, dtype=np.float32))
+    if tmax is None:
+        tmax = int(np.ceil(3.0 * sig[-1]))
+    out = np.zeros_like(idx)
+    lib().ref_postprocess(H, W, len(sig), _d(sig), idx.ctypes.data_as(_u8p), _d(_f64(vmax)), _d(_f64(ex)),
+                          _d(_f64(ey)), float(np.float32(theta)), int(tmax), out.ctypes.data_as(_u8p))
+    return out
+
+
+def scale_select_postprocessed(u, sigmas, mode, theta, beta=0.5, c=-1.0):
+    """Scale selection followed by the postprocessing, as the filter does it."""
+    sel = scale_select(u, sigmas, mode, beta=beta, c=c)
+    ex, ey = cross_direction(u, sel["idx"], sigmas)
+    sel["idx_raw"] = sel["idx"]
+    sel["ex"], sel["ey"] = ex, ey
+    sel["idx"] = postprocess(sel["idx_raw"], sel["vmax"], ex, ey, sigmas, theta)
+    return sel
 
 
 # ------------------------------------------------------------- learned net

@@ -493,8 +493,156 @@ void ref_fed_cycle(double *u, const double *Dall, int H, int W, const double *or
 }
 
 /* ------------------------------------------------------------------------ */
+/* Isotropic fourth-order diffusion (IFOD): Sec. 3.1, Eq. (4)                */
+/* ------------------------------------------------------------------------ */
+
+/* Diffusivity of the isotropic model of Eq. (4): g = 1 / (1 + F / lambda^2)
+ * with F = ||H(u_sigma)||_F^2 = h_xx^2 + h_xy^2 + h_yx^2 + h_yy^2 (Eq. (1)
+ * with the squared Frobenius norm of the Hessian as its argument).
+ * reading: the Hessian is taken of u_sigma = u * G_sigma (the comparison
+ * experiments of Sec. 4.1 regularise IFOD with sigma = 1), with the same
+ * Gaussian, symmetric extension and central differences as the scale stack.
+ * Optional hess (nullable) receives (h_xx, h_xy, h_yy) planes. */
+void ref_ifod_diffusivity(const double *u, int H, int W, double sigma, double lambda,
+                          double *g, double *hess /* 3*H*W or NULL */)
+{
+    size_t m = (size_t)H * W;
+    double *us = (double *)malloc(sizeof(double) * m);
+    double *hxx = (double *)malloc(sizeof(double) * m);
+    double *hxy = (double *)malloc(sizeof(double) * m);
+    double *hyy = (double *)malloc(sizeof(double) * m);
+    ref_blur(u, H, W, sigma, us);
+    ref_derivatives(us, H, W, NULL, NULL, hxx, hxy, hyy);
+    #pragma omp parallel for schedule(static)
+    for (size_t p = 0; p < m; ++p) {
+        double F = hxx[p] * hxx[p] + 2.0 * hxy[p] * hxy[p] + hyy[p] * hyy[p];
+        g[p] = 1.0 / (1.0 + F / (lambda * lambda));
+    }
+    if (hess) {
+        memcpy(hess, hxx, sizeof(double) * m);
+        memcpy(hess + m, hxy, sizeof(double) * m);
+        memcpy(hess + 2 * m, hyy, sizeof(double) * m);
+    }
+    free(us); free(hxx); free(hxy); free(hyy);
+}
+
+/* The isotropic model as a fourth-order tensor: D = g Id on (xx, xy, yx, yy),
+ * i.e. every component of the Hessian is scaled by g (Eq. (4)). */
+void ref_ifod_dtensor(const double *g, int H, int W, double *Dall)
+{
+    size_t m = (size_t)H * W;
+    #pragma omp parallel for schedule(static)
+    for (size_t p = 0; p < m; ++p) {
+        double *D = Dall + 16 * p;
+        for (int k = 0; k < 16; ++k) D[k] = 0.0;
+        for (int k = 0; k < 4; ++k) D[5 * k] = g[p];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Scale-image postprocessing: Sec. 3.3, the text after Eq. (9)              */
+/* ------------------------------------------------------------------------ */
+
+/* Direction across the crease at every pixel: the unit eigenvector of the
+ * eigenvalue of larger magnitude of H(u_sigma) at the pixel's selected scale
+ * sigma_{idx}. reading: at equal magnitudes the eigenvector of the larger
+ * eigenvalue, at angle t = atan2(2 h_xy, h_xx - h_yy) / 2, is taken (for
+ * h_xx = h_yy, h_xy = 0 that is (1, 0)). */
+void ref_cross_direction(const double *u, int H, int W, int ns, const double *sigmas,
+                         const uint8_t *idx, double *ex, double *ey)
+{
+    size_t m = (size_t)H * W;
+    double *us = (double *)malloc(sizeof(double) * m);
+    double *hxx = (double *)malloc(sizeof(double) * m);
+    double *hxy = (double *)malloc(sizeof(double) * m);
+    double *hyy = (double *)malloc(sizeof(double) * m);
+    for (int s = 0; s < ns; ++s) {
+        int used = 0;
+        for (size_t p = 0; p < m && !used; ++p) used = (idx[p] == s);
+        if (!used) continue;
+        ref_blur(u, H, W, sigmas[s], us);
+        ref_derivatives(us, H, W, NULL, NULL, hxx, hxy, hyy);
+        #pragma omp parallel for schedule(static)
+        for (size_t p = 0; p < m; ++p) {
+            if (idx[p] != s) continue;
+            double l1, l2;
+            eig2_values(hxx[p], hxy[p], hyy[p], &l1, &l2);
+            double t = 0.5 * atan2(2.0 * hxy[p], hxx[p] - hyy[p]);
+            double e1x = cos(t), e1y = sin(t);
+            if (fabs(l2) > fabs(l1)) { ex[p] = -e1y; ey[p] = e1x; }
+            else { ex[p] = e1x; ey[p] = e1y; }
+        }
+    }
+    free(us); free(hxx); free(hxy); free(hyy);
+}
+
+/* Rounds half away from zero, so that a march and its mirror image visit
+ * mirrored pixels. */
+static double round_away(double v)
+{
+    return v >= 0.0 ? floor(v + 0.5) : -floor(-v + 0.5);
+}
+
+/* The postprocessing of the scale image. A pixel is on a vessel when its
+ * vesselness max_s V_s reaches theta. For every vessel pixel p, its
+ * cross-section is sampled by marching from p along +e(p) and -e(p) (the
+ * direction across the crease, above) in unit steps, t = 1, 2, ..., tmax,
+ * visiting the pixel nearest to p + t e (each coordinate offset rounded
+ * half away from zero), and stopping in each direction at the first sample
+ * that leaves the image or is not a vessel pixel. p then takes the scale
+ * closest to the mean sigma over the samples (p itself and every visited
+ * sample, repeats counted); ties go to the smaller scale. Other pixels keep
+ * their scale. reading: the march follows the straight line through p along
+ * p's own direction; tmax = ceil(3 sigma_max), the support radius of the
+ * largest scale. The comparison |mean - sigma_s| is made as |sum - n sigma_s|
+ * (the same order after multiplying by n > 0; exact in double, as every
+ * term is a float32 sigma times a small integer). */
+void ref_postprocess(int H, int W, int ns, const double *sigmas, const uint8_t *idx_in,
+                     const double *vmax, const double *ex, const double *ey, double theta,
+                     int tmax, uint8_t *idx_out)
+{
+    #pragma omp parallel for schedule(static)
+    for (int y = 0; y < H; ++y) {
+        for (int x = 0; x < W; ++x) {
+            size_t p = (size_t)y * W + x;
+            if (!(vmax[p] >= theta)) { idx_out[p] = idx_in[p]; continue; }
+            double sum = sigmas[idx_in[p]];
+            double n = 1.0;
+            for (int dir = -1; dir <= 1; dir += 2) {
+                for (int t = 1; t <= tmax; ++t) {
+                    int xx = x + (int)round_away(dir * t * ex[p]);
+                    int yy = y + (int)round_away(dir * t * ey[p]);
+                    if (xx < 0 || xx >= W || yy < 0 || yy >= H) break;
+                    size_t q = (size_t)yy * W + xx;
+                    if (!(vmax[q] >= theta)) break;
+                    sum += sigmas[idx_in[q]];
+                    n += 1.0;
+                }
+            }
+            int best = 0;
+            double bd = fabs(sum - n * sigmas[0]);
+            for (int s = 1; s < ns; ++s) {
+                double d = fabs(sum - n * sigmas[s]);
+                if (d < bd) { bd = d; best = s; }
+            }
+            idx_out[p] = (uint8_t)best;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* The whole filter: M FED cycles, each re-forming P from u^k (Eq. (21))     */
 /* ------------------------------------------------------------------------ */
+
+/* Options of ref_filter beyond the paper's core parameters (NULL = all 0). */
+typedef struct ref_opts {
+    int model;                  /* 0: the anisotropic model, Eqs. (5)-(8); 1: IFOD, Eq. (4) */
+    int postprocess;            /* 1: scale-image postprocessing after each scale selection */
+    double theta;               /* vessel threshold of the postprocessing */
+    const uint8_t *idx_inject;  /* [M][H][W] or NULL: the scale indices of each cycle are
+                                   taken from here instead of being selected (teacher
+                                   forcing of stage parity) */
+} ref_opts;
 
 /* reading: scales are re-selected on u^k at every cycle when reselect != 0,
  * otherwise once on u^0 (the normalised Hessian is still re-formed from u^k
@@ -503,13 +651,18 @@ void ref_fed_cycle(double *u, const double *Dall, int H, int W, const double *or
  * Eq. (22) with stop_time T and the steps from Eq. (23).
  * Optional records (nullable): idx_rec [M][H][W], c_rec [M],
  * hrho_rec [M][3][H][W], u_rec [M][H][W] (state after each cycle).
+ * With opts->model == 1 (IFOD) no scale is selected: D = g Id with g from
+ * H(u_sigma) at sigma = sigmas[0]; hrho_rec then records that Hessian.
  * Returns n, or -1 on invalid schedule. */
 int ref_filter(const double *u_in, double *u_out, int H, int W,
                int ns, const double *sigmas, int mode, double lambda, double rho,
                double beta, double c_param, int M, int n_substeps, double stop_time,
                double tau_max, int reselect,
-               uint8_t *idx_rec, double *c_rec, double *hrho_rec, double *u_rec)
+               uint8_t *idx_rec, double *c_rec, double *hrho_rec, double *u_rec,
+               const ref_opts *opts)
 {
+    ref_opts none = {0, 0, 0.0, NULL};
+    if (!opts) opts = &none;
     size_t m = (size_t)H * W;
     int n = n_substeps;
     double *tau, *ordered;
@@ -532,18 +685,40 @@ int ref_filter(const double *u_in, double *u_out, int H, int W,
     uint8_t *idx = (uint8_t *)malloc(m);
     double *hrho = (double *)malloc(sizeof(double) * 3 * m);
     double *Dall = (double *)malloc(sizeof(double) * 16 * m);
+    double *vmax = (double *)malloc(sizeof(double) * m);
+    double *gdiff = (double *)malloc(sizeof(double) * m);
     for (int k = 0; k < M; ++k) {
         double c = 0.0;
-        if (k == 0 || reselect)
-            ref_scale_select(u_out, H, W, ns, sigmas, mode, beta, c_param, idx, NULL, NULL, NULL, &c);
-        ref_tensor(u_out, H, W, idx, ns, sigmas, rho, hrho);
-        ref_dtensor(hrho, H, W, lambda, mode, Dall);
+        if (opts->model == 1) {
+            ref_ifod_diffusivity(u_out, H, W, sigmas[0], lambda, gdiff, hrho);
+            ref_ifod_dtensor(gdiff, H, W, Dall);
+            memset(idx, 0, m);
+        } else {
+            if (opts->idx_inject) {
+                memcpy(idx, opts->idx_inject + k * m, m);
+            } else if (k == 0 || reselect) {
+                ref_scale_select(u_out, H, W, ns, sigmas, mode, beta, c_param, idx, NULL, NULL, vmax, &c);
+                if (opts->postprocess) {
+                    double *ex = (double *)malloc(sizeof(double) * m);
+                    double *ey = (double *)malloc(sizeof(double) * m);
+                    uint8_t *pp = (uint8_t *)malloc(m);
+                    ref_cross_direction(u_out, H, W, ns, sigmas, idx, ex, ey);
+                    ref_postprocess(H, W, ns, sigmas, idx, vmax, ex, ey, opts->theta,
+                                    (int)ceil(3.0 * sigmas[ns - 1]), pp);
+                    memcpy(idx, pp, m);
+                    free(ex); free(ey); free(pp);
+                }
+            }
+            ref_tensor(u_out, H, W, idx, ns, sigmas, rho, hrho);
+            ref_dtensor(hrho, H, W, lambda, mode, Dall);
+        }
         ref_fed_cycle(u_out, Dall, H, W, ordered, n);
         if (idx_rec) memcpy(idx_rec + k * m, idx, m);
         if (c_rec) c_rec[k] = c;
         if (hrho_rec) memcpy(hrho_rec + 3 * k * m, hrho, sizeof(double) * 3 * m);
         if (u_rec) memcpy(u_rec + k * m, u_out, sizeof(double) * m);
     }
+    free(vmax); free(gdiff);
     free(idx); free(hrho); free(Dall); free(ordered); free(perm);
     return n;
 }

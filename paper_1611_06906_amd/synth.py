@@ -77,15 +77,20 @@ def _bezier_samples(p0, p1, p2, spacing=0.5):
 
 def creases(H, W, n_creases, seed, *, background=0.2, amplitude=0.6,
             width_range=(1.0, 3.0), control_range=(0.1, 0.9),
-            signs="bright", noise=0.05):
+            signs="bright", noise=0.05, ground_truth=False):
     """Quadratic-Bezier creases with Gaussian cross-section plus noise.
 
     signs: "bright" (ridges), or "mixed" (alternating bright / dark,
     so half of the creases are ridges and half valleys).
+    ground_truth: also return the noise-free image (clipped to [0, 1]) and
+    the centreline of every crease as an (K, 2) array of (x, y) samples less
+    than 1 px apart, with its sign (+1 ridge, -1 valley), as
+    (image, clean, [(polyline, sign), ...]). The noisy image is the same
+    either way.
     """
     rng = np.random.default_rng(seed)
     lo, hi = control_range
-    all_p, all_n, all_a, all_w = [], [], [], []
+    all_p, all_n, all_a, all_w, lines = [], [], [], [], []
     for c in range(n_creases):
         ctrl = rng.uniform(lo, hi, size=(3, 2)) * np.array([W - 1, H - 1])
         w = rng.uniform(*width_range)
@@ -95,13 +100,18 @@ def creases(H, W, n_creases, seed, *, background=0.2, amplitude=0.6,
         all_n.append(nrm)
         all_a.append(np.full(len(p), sgn * amplitude))
         all_w.append(np.full(len(p), w))
+        lines.append((p, sgn))
     prof = _render_nearest(H, W, np.concatenate(all_p), np.concatenate(all_n),
                            np.concatenate(all_a), np.concatenate(all_w))
-    img = background + prof + rng.normal(0.0, noise, size=(H, W))
-    return np.ascontiguousarray(np.clip(img, 0.0, 1.0).astype(np.float32))
+    clean = background + prof
+    img = clean + rng.normal(0.0, noise, size=(H, W))
+    img = np.ascontiguousarray(np.clip(img, 0.0, 1.0).astype(np.float32))
+    if ground_truth:
+        return img, np.ascontiguousarray(np.clip(clean, 0.0, 1.0).astype(np.float32)), lines
+    return img
 
 
-def fundus(H, W, seed, *, noise=0.03, max_walks=256):
+def fundus(H, W, seed, *, noise=0.03, max_walks=256, ground_truth=False):
     """Fundus-like image: bright vignetted disc with a dark vessel tree.
 
     The tree grows from 4 roots on the disc rim by persistent random walks
@@ -109,6 +119,8 @@ def fundus(H, W, seed, *, noise=0.03, max_walks=256):
     per step) whose radius tapers from 8 px to 1 px; each tree has a
     contrast drawn from U[0.15, 0.35] and a Gaussian cross-section of
     width radius / sqrt(2).
+    ground_truth: also return the noise-free image and the centreline of
+    every walk (valleys, sign -1), as for creases().
     """
     rng = np.random.default_rng(seed)
     cy, cx = (H - 1) / 2.0, (W - 1) / 2.0
@@ -128,17 +140,20 @@ def fundus(H, W, seed, *, noise=0.03, max_walks=256):
         contrast = rng.uniform(0.15, 0.35)
         walks.append((start, head, 8.0, lmax, contrast))
     done = 0
+    lines = []
     while walks and done < max_walks:
         pos, head, r0, length, contrast = walks.pop(0)
         done += 1
         pos = pos.copy()
         steps = int(length)
+        line = []
         for s in range(steps):
             rad = r0 + (1.0 - r0) * (s / max(steps - 1, 1))
             if rad < 1.0:
                 break
             tan = np.array([math.cos(head), math.sin(head)])
             pts.append(pos.copy())
+            line.append(pos.copy())
             nrms.append(np.array([-tan[1], tan[0]]))
             amps.append(-contrast)
             wids.append(rad / math.sqrt(2.0))
@@ -150,14 +165,20 @@ def fundus(H, W, seed, *, noise=0.03, max_walks=256):
             pos += tan
             if math.hypot(pos[0] - cx, pos[1] - cy) > R:
                 break
+        if len(line) >= 2:
+            lines.append((np.array(line), -1.0))
     if pts:
         P = np.array(pts)
         Nn = np.array(nrms)
         prof = _render_nearest(H, W, P, Nn, np.array(amps), np.array(wids), reach=4.0)
     else:
         prof = 0.0
-    img = base + prof + rng.normal(0.0, noise, size=(H, W))
-    return np.ascontiguousarray(np.clip(img, 0.0, 1.0).astype(np.float32))
+    clean = base + prof
+    img = clean + rng.normal(0.0, noise, size=(H, W))
+    img = np.ascontiguousarray(np.clip(img, 0.0, 1.0).astype(np.float32))
+    if ground_truth:
+        return img, np.ascontiguousarray(np.clip(clean, 0.0, 1.0).astype(np.float32)), lines
+    return img
 
 
 # --------------------------------------------------------------------------
@@ -185,6 +206,10 @@ class Workload:
     def image(self):
         return make_image(self)
 
+    def ground_truth(self):
+        """(noisy image, noise-free image, centrelines) of this workload."""
+        return make_image(self, ground_truth=True)
+
     @property
     def px_substeps(self):
         return self.H * self.W * self.cycles * self.substeps
@@ -211,16 +236,17 @@ def creases4096(seed=0, H=4096, W=4096, cycles=30):
 WORKLOADS = {"ridges128": ridges128, "fundus1024": fundus1024, "creases4096": creases4096}
 
 
-def make_image(w: Workload):
+def make_image(w: Workload, ground_truth=False):
+    gt = dict(ground_truth=ground_truth)
     if w.name == "ridges128":
         n = max(1, int(round(3 * math.sqrt(w.H * w.W / 128.0 ** 2))))
-        return creases(w.H, w.W, n, w.seed)
+        return creases(w.H, w.W, n, w.seed, **gt)
     if w.name == "fundus1024":
-        return fundus(w.H, w.W, w.seed)
+        return fundus(w.H, w.W, w.seed, **gt)
     if w.name == "creases4096":
         n = max(2, int(round(64 * math.sqrt(w.H * w.W / 4096.0 ** 2))))
         return creases(w.H, w.W, n, w.seed, background=0.5, amplitude=0.4,
-                       width_range=(1.0, 16.0), control_range=(0.0, 1.0), signs="mixed")
+                       width_range=(1.0, 16.0), control_range=(0.0, 1.0), signs="mixed", **gt)
     raise KeyError(w.name)
 
 

@@ -22,8 +22,15 @@ muts=(
  's|if (uxy) uxy\[c\] = (V(ym, xm) + V(yp, xp) - V(yp, xm) - V(ym, xp)) / 4.0;|if (uxy) uxy[c] = (V(ym, xm) + V(yp, xp) - V(yp, xm) - V(ym, xp)) / 2.0;|'
  's|double theta = 0.5 \* atan2(2.0 \* b, a - d);|double theta = 0.5 * atan2(b, a - d);|'
  's|if (nu1 >= 0.0) mu\[0\] = 1.0;|if (nu1 > 0.1) mu[0] = 1.0;|'
+ 's|double F = hxx\[p\] \* hxx\[p\] + 2.0 \* hxy\[p\] \* hxy\[p\] + hyy\[p\] \* hyy\[p\];|double F = hxx[p] * hxx[p] + hxy[p] * hxy[p] + hyy[p] * hyy[p];|'
+ 's|for (int k = 0; k < 4; ++k) D\[5 \* k\] = g\[p\];|for (int k = 0; k < 4; k += 3) D[5 * k] = g[p];|'
+ 's|if (fabs(l2) > fabs(l1)) { ex\[p\] = -e1y; ey\[p\] = e1x; }|if (fabs(l2) < fabs(l1)) { ex[p] = -e1y; ey[p] = e1x; }|'
+ 's|return v >= 0.0 ? floor(v + 0.5) : -floor(-v + 0.5);|return floor(v + 0.5);|'
+ 's|if (!(vmax\[q\] >= theta)) break;|if (!(vmax[q] >= theta)) continue;|'
+ 's|if (d < bd) { bd = d; best = s; }|if (d <= bd) { bd = d; best = s; }|'
+ 's|for (int t = 1; t <= tmax; ++t) {|for (int t = 1; t < tmax; ++t) {|'
 )
-pins="tests/test_oracle_schedule.py tests/test_oracle_scalespace.py tests/test_oracle_tensor_operator.py tests/test_oracle_filter.py"
+pins="tests/test_oracle_schedule.py tests/test_oracle_scalespace.py tests/test_oracle_tensor_operator.py tests/test_oracle_filter.py tests/test_oracle_ext.py"
 i=0
 for m in "${muts[@]}"; do
   i=$((i+1)); d=$(mktemp -d)

@@ -43,3 +43,23 @@ def test_batch_specs():
     small = dict(specs[0], H=64, W=80)
     ridge, valley = dict(small, mode=synth.RIDGE), dict(small, mode=synth.VALLEY)
     assert np.allclose(synth.batch_image(valley), 1.0 - synth.batch_image(ridge).astype(np.float64), atol=1e-7)
+
+
+def test_ground_truth_outputs():
+    """The noise-free image and centrelines come from the same draws: the
+    noisy image is unchanged, the noise-free one differs from it by the
+    noise only, and the centreline samples lie inside the image."""
+    from paper_1611_06906_amd import synth
+    w = synth.ridges128()
+    img, clean, lines = w.ground_truth()
+    assert np.array_equal(img, w.image())
+    assert clean.dtype == np.float32 and clean.min() >= 0 and clean.max() <= 1
+    d = img.astype(np.float64) - clean
+    assert 0.04 < d.std() < 0.06 and abs(d.mean()) < 0.005
+    assert len(lines) == 3
+    for pts, sgn in lines:
+        assert sgn == 1.0 and pts.shape[1] == 2
+        assert np.all(np.linalg.norm(np.diff(pts, axis=0), axis=1) < 1.0)
+    img2, clean2, lines2 = synth.fundus(256, 256, 5, ground_truth=True)
+    assert np.array_equal(img2, synth.fundus(256, 256, 5))
+    assert all(sgn == -1.0 for _, sgn in lines2) and len(lines2) >= 4
