@@ -11,10 +11,18 @@ the graph run reports the eager time beside it.
 
 Prints one JSON line:
   value     Mpixel-FED-substeps/s of the whole filter (H W M n per step / time)
-  roofline  the fused FED substep kernel: algorithmic flops and bytes per launch
-            (37 flop/px per substep; 20 B/px per launch: u read 4, tensor
-            planes read 12, u write 4) / its average launch time, timed with
-            HIP events on the stream it is launched on
+  roofline  the fused FED substep kernel as the filter launches it (4 substeps
+            per launch): algorithmic bytes per launch (20 B/px: u read 4,
+            tensor planes read 12, u write 4) / its average launch time,
+            timed with HIP events on the stream it is launched on, against
+            the 8 TB/s HBM peak
+  roofline_alu  the same launches in FP32 vector flops (37 per px-substep)
+  roofline_selection  scale sweep, argmax and integration (rows a2-a4) per
+            cycle: 26 B/px algorithmic (sweep and argmax: u read twice, as the
+            image-wide c needs every scale before any argmax, 8, index
+            written 1; integration: u 4 and index 1 read, tensor planes
+            written 12) over the filter's per-cycle time outside its
+            substep launches
   roofline_sweep  the fused scale-sweep kernel at sigma = 16 (both separable
             passes of one scale on the matrix cores, split-BF16 products):
             algorithmic flops (8 filters x 99 taps x 2 per pixel) against the
@@ -41,6 +49,10 @@ BF3_PRODUCTS = 6           # BF16 part products per FP32 product in the split-BF
 SUBSTEP_BYTES_PER_PX = 20  # per launch: u in 4 + tensor planes in 12 + u out 4
 SUBSTEP_FLOPS_PER_PX = 37  # per substep: L u 10, D L u 13, L^T and update 14
 SUBSTEPS_PER_LAUNCH = 4    # as mf4d_filter launches the fused substep kernel (two columns per lane)
+# rows a2-a4 per pixel and cycle: sweep and argmax 9 (u read twice, since the
+# image-wide c needs every scale before any argmax, 8; index written 1) and
+# integration 17 (u 4 and index 1 read, tensor planes written 12)
+SELECTION_BYTES_PER_PX = 26
 CPU_CYCLES = 3             # FED cycles of the oracle's bounded sample (about 15 s on 16 host cores)
 
 
@@ -85,6 +97,41 @@ def counter_traffic(kernel, row=None):
         except (IndexError, ValueError):
             return None
     return None
+
+
+# kernels of rows a2-a4 in the counter summary (rows of one cycle)
+SELECTION_ROWS = ["sweep_fused_kernel<2>", "sweep_fused_kernel<3>", "sweep_fused_kernel<4>",
+                  "sweep_fused_kernel<5>", "sweep_fused_kernel<6>", "sweep_fused_kernel<7>",
+                  "sweep_fused_kernel<8>", "argmax_kernel", "rho_blur_kernel<2>"]
+
+
+def selection_traffic():
+    """HBM bytes of one cycle's scale sweep, argmax and integration from the
+    committed counter summary (per-cycle rows), or None if absent or stale."""
+    prof = os.path.join(ROOT, "profiles", "creases4096_hbm_counters.txt")
+    try:
+        text = open(prof).read()
+        digest = source_digest("sweep_fused_kernel<8>")
+    except (OSError, KeyError):
+        return None
+    if f"sweep_fused_kernel<8> sources sha256 prefix: {digest}" not in text:
+        return None
+    total = 0.0
+    for row in SELECTION_ROWS:
+        found = None
+        for line in text.splitlines():
+            if "sha256" in line or not (line.startswith(row + " ") or line.startswith("void " + row + " ")):
+                continue
+            nums = [c for c in line.split() if c.replace(".", "", 1).isdigit()]
+            try:
+                found = (float(nums[3]) + float(nums[4])) * 1e6
+            except (IndexError, ValueError):
+                found = None
+            break
+        if found is None:
+            return None
+        total += found
+    return total
 
 
 def _events(torch):
@@ -149,6 +196,19 @@ def batched_comparison(torch, mf4d, synth, dev, reps=2):
     ms_p = time_stream(torch, plain, reps)
     torch.cuda.synchronize()
     same = bool(torch.equal(out_b, out_p))
+    # the same per-image calls recorded once into one hipGraph and replayed:
+    # per-image launches without the host's launch cost
+    ms_pg = None
+    try:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            plain()
+        graph.replay()
+        ms_pg = time_stream(torch, graph.replay, reps)
+        same = same and bool(torch.equal(out_b, out_p))
+        del graph
+    except RuntimeError as e:
+        print(f"[bench] per-image graph not recorded: {e}", file=sys.stderr, flush=True)
     px_sub = sum(h * w * sp["cycles"] * 10 for (h, w), sp in zip(shapes, specs))
     plan.close()
     return {"images": len(imgs), "megapixels": float(offs[-1]) / 1e6,
@@ -157,6 +217,9 @@ def batched_comparison(torch, mf4d, synth, dev, reps=2):
             "batched_Mpx_substeps_per_s": px_sub / (ms_b * 1e-3) / 1e6,
             "plain_Mpx_substeps_per_s": px_sub / (ms_p * 1e-3) / 1e6,
             "speedup": ms_p / ms_b, "bit_identical_to_plain": same,
+            "plain_graph_ms": ms_pg,
+            "plain_graph_images_per_s": (len(imgs) / (ms_pg * 1e-3)) if ms_pg else None,
+            "speedup_vs_plain_graph": (ms_pg / ms_b) if ms_pg else None,
             "substeps_per_launch": tune[0], "rows_per_wave": tune[1]}
 
 
@@ -196,15 +259,18 @@ def learned_comparison(torch, mf4d, synth, dev, train_steps=600, reps=1):
     B, C = 8, 256
     ws = mf4d.net_workspace(B, C, C, True, dev)
     rng = np.random.default_rng(0)
-    xb = torch.empty((B, C, C), dtype=torch.float32, device=dev)
-    yb = torch.empty((B, C, C), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
     t1 = time.time()
+    ar = torch.arange(C, device=dev)
     for step in range(1, train_steps + 1):
-        for b in range(B):
-            i, y0, x0 = rng.integers(0, len(train_imgs)), rng.integers(0, 1024 - C + 1), rng.integers(0, 1024 - C + 1)
-            xb[b].copy_(U[i, y0:y0 + C, x0:x0 + C])
-            yb[b].copy_(L[i, y0:y0 + C, x0:x0 + C])
+        # the step's B random crops in one gather launch per tensor
+        sel = torch.from_numpy(np.stack([rng.integers(0, len(train_imgs), B), rng.integers(0, 1024 - C + 1, B),
+                                         rng.integers(0, 1024 - C + 1, B)])).to(dev)
+        ii = sel[0][:, None, None]
+        yy = (sel[1][:, None] + ar[None, :])[:, :, None]
+        xx = (sel[2][:, None] + ar[None, :])[:, None, :]
+        xb = U[ii, yy, xx]
+        yb = L[ii, yy, xx]
         lr = 3e-3 if step < train_steps * 0.7 else 1e-3
         mf4d.mf4d_net_backward(th, xb, yb, g, 0.1, stats, ws)
         mf4d.mf4d_net_step(th, g, mm, vv, step, lr)
@@ -352,15 +418,19 @@ def main():
     m = w.H * w.W
     flops = SUBSTEP_FLOPS_PER_PX * spl * m / t
     hbm = SUBSTEP_BYTES_PER_PX * m / t
-    roofline = {"bound": "alu",
+    traffic = counter_traffic(f"fed_stream2_kernel<{spl}>")
+    roofline = {"bound": "hbm",
                 "kernel": f"fed_stream2_kernel<{spl}> (fused FED substep, {spl} substeps per launch, two columns per lane)",
-                "achieved": flops / 1e12, "peak": VALU_PEAK / 1e12, "unit": "TFLOP/s",
-                "frac": flops / VALU_PEAK, "traffic": counter_traffic(f"fed_stream2_kernel<{spl}>"),
+                "achieved": hbm / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": hbm / HBM_PEAK,
+                "traffic": traffic,
                 "traffic_unit": "B per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
-                "us_per_launch": us_launch,
-                "hbm_achieved_GBs": hbm / 1e9, "hbm_frac": hbm / HBM_PEAK,
-                "hbm_per_substep_equivalent_GBs": hbm * spl / 1e9,
-                "flops_per_px_substep": SUBSTEP_FLOPS_PER_PX, "bytes_per_px_launch": SUBSTEP_BYTES_PER_PX}
+                "traffic_over_algorithmic": (traffic / (SUBSTEP_BYTES_PER_PX * m)) if traffic else None,
+                "us_per_launch": us_launch, "bytes_per_px_launch": SUBSTEP_BYTES_PER_PX,
+                "px_per_launch": m}
+    roofline_alu = {"bound": "alu", "kernel": roofline["kernel"], "achieved": flops / 1e12,
+                    "peak": VALU_PEAK / 1e12, "unit": "TFLOP/s", "frac": flops / VALU_PEAK,
+                    "flops_per_px_substep": SUBSTEP_FLOPS_PER_PX, "us_per_launch": us_launch,
+                    "peak_note": "FP32 vector without packed FP32: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz"}
     # the same kernel at one substep per launch is HBM-bound: report it too
     ms1 = time_stream(torch, lambda: mf4d.mf4d_fed_cycle_tensor(uc, ut, dpar, taus2, 1), reps)
     t1 = ms1 * 1e-3 / (2 * n)
@@ -410,6 +480,18 @@ def main():
         stages = {"per_cycle_scale_select_ms": sel_ms, "per_cycle_tensor_incl_sweep_ms": ten_ms,
                   "per_cycle_substeps_ms": ms_cycle / 2, "cycles": w.cycles}
 
+    # rows a2-a4 per cycle: the filter's time outside its substep launches
+    launches_per_cycle = (w.substeps + spl - 1) // spl
+    sel_cycle_ms = ms / w.cycles - launches_per_cycle * us_launch * 1e-3
+    sel_bytes = SELECTION_BYTES_PER_PX * m
+    sel_traffic = selection_traffic()
+    roofline_selection = {"bound": "hbm", "stages": "scale sweep (8 scales) + argmax + integration, per cycle",
+                          "achieved": sel_bytes / (sel_cycle_ms * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9,
+                          "unit": "GB/s", "frac": sel_bytes / (sel_cycle_ms * 1e-3) / HBM_PEAK,
+                          "ms_per_cycle": sel_cycle_ms, "bytes_per_px": SELECTION_BYTES_PER_PX,
+                          "traffic": sel_traffic, "traffic_unit": "B per cycle (copy-calibrated counters)",
+                          "traffic_over_algorithmic": (sel_traffic / sel_bytes) if sel_traffic else None}
+
     extensions = None
     if not args.no_extensions:
         extensions = {"batched_256": batched_comparison(torch, mf4d, synth, dev)}
@@ -450,6 +532,8 @@ def main():
                    "H": w.H, "W": w.W, "cycles": w.cycles, "substeps": w.substeps,
                    "nscales": len(w.sigmas), "mode": "both", "path": "plain", "launch": launch},
         "roofline": roofline,
+        "roofline_alu": roofline_alu,
+        "roofline_selection": roofline_selection,
         "roofline_single_substep": roofline_single,
         "roofline_sweep": roofline_sweep,
         "cpu_baseline": cpu,

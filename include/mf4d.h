@@ -50,17 +50,24 @@ extern "C" {
 #define MF4D_EINVAL (-1)   /* invalid argument (checked before any launch)   */
 #define MF4D_ENOMEM (-2)   /* workspace smaller than mf4d_workspace_bytes()  */
 #define MF4D_EHIP (-3)     /* a HIP launch or runtime call failed            */
+#define MF4D_ENONFINITE (-4) /* check on: u held a non-finite value          */
+#define MF4D_EUNSTABLE (-5)  /* check on: a cycle grew the l2 norm of u      */
 
 /* Crease type to enhance (Sec. 3.2, text after Eq. (7); Sec. 3.3 Eq. (9)). */
 #define MF4D_RIDGE 0       /* mu_i = 1 where nu_i >= 0; V = 0 where nu~_2 > 0 */
 #define MF4D_VALLEY 1      /* mu_i = 1 where nu_i <= 0; V = 0 where nu~_2 < 0 */
 #define MF4D_BOTH 2        /* no mask, no sign test (the paper's default)    */
 
+/* Diffusion model (params.model). */
+#define MF4D_MAFOD 0       /* anisotropic tensor of Eqs. (7), (8) at the selected scales */
+#define MF4D_IFOD 1        /* isotropic: D = g(||H(u_sigma)||_F^2) Id, Eq. (4) with Eq. (1) */
+
 #define MF4D_MAX_SCALES 16
 #define MF4D_MAX_RADIUS 64 /* Gaussian radius max(1, ceil(3 sigma)) limit   */
 #define MF4D_MAX_SUBSTEPS 1024
 
-/* Filter parameters, in the paper's notation.
+/* Filter parameters, in the paper's notation. Zero-initialise the struct (or
+ * use mf4d_params_default) so that fields added at its end stay 0.
  *   nscales, sigmas  scale set {sigma_min..sigma_max} of Sec. 3.3; host array,
  *                    strictly ascending, > 0, radius ceil(3 sigma) <= 64.
  *   mode             MF4D_RIDGE / MF4D_VALLEY / MF4D_BOTH.
@@ -78,9 +85,31 @@ extern "C" {
  *   tau_max          stable explicit step, 0 < tau_max <= 1/17 (Eq. (20)).
  *   reselect_each_cycle  1: scales re-selected on u^k every cycle; 0: once on
  *                    u^0 (the Hessian is still re-formed from u^k each cycle).
- *   theta, postprocess   vessel threshold and scale-image postprocessing of
- *                    Sec. 3.3; postprocessing is not part of this library and
- *                    postprocess must be 0. theta is unused.
+ *   theta, postprocess   scale-image postprocessing of Sec. 3.3 (text after
+ *                    Eq. (9)): postprocess = 1 re-assigns every pixel whose
+ *                    max_s V_s >= theta the scale nearest to the mean sigma of
+ *                    its cross-section (a march in unit steps, up to
+ *                    ceil(3 sigma_max) on each side, across the crease along
+ *                    the eigenvector of the stronger eigenvalue of the
+ *                    Hessian at the pixel's scale, through vessel pixels
+ *                    only; offsets rounded half away from zero; ties to the
+ *                    smaller scale). 0: no postprocessing, theta unused.
+ *   check            0: none. 1: after every cycle the l2 norm of u is taken
+ *                    (FP64 sum) and compared with the previous one; the call
+ *                    then synchronises `stream` and returns MF4D_ENONFINITE if
+ *                    u (or the input) held a NaN or infinity, else
+ *                    MF4D_EUNSTABLE if a cycle grew ||u||_2 by more than a
+ *                    relative 1e-5 (exact arithmetic forbids any growth:
+ *                    each FED cycle is a contraction for tau_max <= 1/17,
+ *                    Sec. 3.4). The environment variable
+ *                    MF4D_L2_GROWTH_TOL overrides 1e-5 (a negative value
+ *                    forces the growth report, for tests of the error path).
+ *                    A call with check = 1 cannot be recorded into a graph.
+ *   model            MF4D_MAFOD, or MF4D_IFOD: the isotropic fourth-order
+ *                    model of Eq. (4) with g of Eq. (1) on the squared
+ *                    Frobenius norm of the Hessian of u_sigma, sigma =
+ *                    sigmas[0] (nscales must be 1; mode, rho, beta, c,
+ *                    postprocess unused), frozen over each FED cycle.
  */
 typedef struct mf4d_params {
     int nscales;
@@ -97,6 +126,8 @@ typedef struct mf4d_params {
     int reselect_each_cycle;
     float theta;
     int postprocess;
+    int check;
+    int model;
 } mf4d_params;
 
 /* Human-readable text for a status code. Never NULL. */
@@ -146,11 +177,13 @@ size_t mf4d_workspace_bytes(int H, int W, const mf4d_params *p);
  * products, FP32 accumulation), so results match an FP64 evaluation to
  * FP32 rounding, not bit for bit.
  *   u        device, float32 [H][W], read only.
- *   idx_out  device, uint8 [H][W]: smallest s with V_s = max_t V_t.
+ *   idx_out  device, uint8 [H][W]: smallest s with V_s = max_t V_t, then the
+ *            postprocessing of Sec. 3.3 when p->postprocess = 1.
  *   vmax_out device, float32 [H][W] (nullable): max_t V_t.
  *   c_out    device, one float32 (nullable): the c used.
  *   ws       device workspace of ws_bytes >= mf4d_workspace_bytes(H, W, p).
- * Errors: MF4D_EINVAL (bad sizes/params/NULL), MF4D_ENOMEM, MF4D_EHIP. */
+ * Errors: MF4D_EINVAL (bad sizes/params/NULL, or p->model = MF4D_IFOD),
+ * MF4D_ENOMEM, MF4D_EHIP. */
 int mf4d_scale_select(const float *u, int H, int W, const mf4d_params *p,
                       uint8_t *idx_out, float *vmax_out, float *c_out,
                       void *ws, size_t ws_bytes, void *stream);
@@ -167,7 +200,10 @@ int mf4d_scale_select(const float *u, int H, int W, const mf4d_params *p,
  *             T_yy = (m-al) h_yy + be h_xy; planes (m, al, be), where
  *             m = (mu_1+mu_2)/2 and (al, be) = (mu_1-mu_2)/2 (cos 2t, sin 2t)
  *             for the angle t of the first eigenvector of H_rho.
- * Errors as mf4d_scale_select. */
+ * With p->model = MF4D_IFOD, idx is not read (may be NULL), hrho_out
+ * receives the Hessian (h_xx, h_xy, h_yy) of u_sigma at sigma = sigmas[0]
+ * and dparams_out the planes (g, 0, 0) of D = g Id.
+ * Errors as mf4d_scale_select (IFOD allowed). */
 int mf4d_tensor(const float *u, int H, int W, const uint8_t *idx, const mf4d_params *p,
                 float *hrho_out, float *dparams_out,
                 void *ws, size_t ws_bytes, void *stream);
@@ -180,7 +216,8 @@ int mf4d_tensor(const float *u, int H, int W, const uint8_t *idx, const mf4d_par
  *   u      device float32 [H][W], in/out: the result always lands here.
  *   u_tmp  device float32 [H][W] scratch (must not alias u).
  *   hrho   device float32 [3][H][W] from mf4d_tensor.
- * Errors: MF4D_EINVAL, MF4D_EHIP. */
+ * Errors: MF4D_EINVAL (also for p->model = MF4D_IFOD: use
+ * mf4d_fed_cycle_tensor with the (g, 0, 0) planes), MF4D_EHIP. */
 int mf4d_fed_cycle(float *u, float *u_tmp, int H, int W, const float *hrho,
                    const mf4d_params *p, const double *taus, int n, void *stream);
 
@@ -201,9 +238,27 @@ int mf4d_fed_cycle_tensor(float *u, float *u_tmp, int H, int W, const float *dpa
  * mf4d_fed_plan.
  *   u_in   device float32 [H][W], read only.
  *   u_out  device float32 [H][W]; may alias u_in.
- * Errors: MF4D_EINVAL, MF4D_ENOMEM, MF4D_EHIP. */
+ * Errors: MF4D_EINVAL, MF4D_ENOMEM, MF4D_EHIP, and with p->check = 1
+ * MF4D_ENONFINITE / MF4D_EUNSTABLE (u_out then holds the last state). */
 int mf4d_filter(const float *u_in, float *u_out, int H, int W, const mf4d_params *p,
                 void *ws, size_t ws_bytes, void *stream);
+
+/* The filter with l2-optimal stopping against a noise-free image (Sec. 4:
+ * the evolution is stopped where the l2 difference between the filtered and
+ * the noise-free image is smallest), evaluated at the ends of FED cycles,
+ * the states the scheme defines (Eq. (21)). Runs p->cycles cycles.
+ *   ground_truth  device float32 [H][W], the noise-free image.
+ *   u_out         device float32 [H][W], receives u^k* (must not alias u_in or
+ *                 ground_truth).
+ *   l2_out        device double [p->cycles + 1] (nullable): e_k = ||u^k - gt||_2,
+ *                 u^0 = u_in (sum in FP64 of the FP32 differences).
+ *   best_out      device int (nullable): k* = the smallest k of minimal e_k.
+ * Everything stays on the device (no synchronisation), so a call can be
+ * recorded into a graph; p->check = 1 is honoured as in mf4d_filter.
+ * Errors as mf4d_filter. */
+int mf4d_filter_l2stop(const float *u_in, float *u_out, int H, int W, const mf4d_params *p,
+                       const float *ground_truth, double *l2_out, int *best_out,
+                       void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------ batches */
 
@@ -221,6 +276,8 @@ typedef struct mf4d_batch mf4d_batch;
  * substeps, stop_time, tau_max, reselect_each_cycle) must equal image 0's
  * (with substeps == 0, cycles must match too). All arrays are host memory
  * and are copied. *plan receives the plan (destroy with mf4d_batch_destroy).
+ * Batches run the anisotropic model without postprocessing or checks
+ * (model, postprocess and check must be 0).
  * Errors: MF4D_EINVAL. */
 int mf4d_batch_create(int nimg, const int64_t *offsets, const int *H, const int *W,
                       const mf4d_params *per_image, mf4d_batch **plan);
@@ -301,7 +358,7 @@ size_t mf4d_learned_workspace_bytes(int H, int W, const mf4d_params *p);
  * sweep still runs every cycle, since the normalised Hessian at the chosen
  * scale and the image-wide c need it. conf_threshold = 1 with an unsure
  * network reproduces mf4d_filter. H, W multiples of 16, nscales <= 8,
- * reselect_each_cycle = 1. fallback_count (nullable, device uint32): number
+ * reselect_each_cycle = 1, model, postprocess and check 0. fallback_count (nullable, device uint32): number
  * of pixel-cycles that fell back to the exact argmax. Errors: MF4D_EINVAL,
  * MF4D_ENOMEM, MF4D_EHIP. */
 int mf4d_filter_learned(const float *u_in, float *u_out, int H, int W, const mf4d_params *p,

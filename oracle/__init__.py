@@ -25,7 +25,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mf4d_oracle.c")
-_SRCS = [_SRC, os.path.join(_HERE, "net_oracle.c")]
+_SRCS = [_SRC, os.path.join(_HERE, "net_oracle.c"), os.path.join(_HERE, "crease_oracle.c")]
 _LIB = os.path.join(_HERE, "libmf4d_oracle.so")
 
 RIDGE, VALLEY, BOTH = 0, 1, 2
@@ -103,6 +103,14 @@ def _declare(L):
     L.ref_postprocess.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _u8p, _dp, _dp, _dp,
                                   ctypes.c_double, ctypes.c_int, _u8p]
     L.ref_filter.restype = ctypes.c_int
+    L.ref_crease_field.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp]
+    L.ref_marching_creases.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp,
+                                       ctypes.POINTER(ctypes.c_int8)]
+    L.ref_marching_creases.restype = ctypes.c_long
+    L.ref_segment_hausdorff.argtypes = [_dp, _dp]
+    L.ref_segment_hausdorff.restype = ctypes.c_double
+    L.ref_crease_match.argtypes = [_dp, ctypes.POINTER(ctypes.c_int8), ctypes.c_int, ctypes.c_int, _dp, _ip,
+                                   ctypes.c_long, ctypes.c_double, _dp, ctypes.POINTER(ctypes.c_long)]
     L.net_param_count.restype = ctypes.c_int
     L.net_forward.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp]
     L.net_loss.argtypes = [_dp, _u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp]
@@ -357,6 +365,77 @@ def scale_select_postprocessed(u, sigmas, mode, theta, beta=0.5, c=-1.0):
     sel["ex"], sel["ey"] = ex, ey
     sel["idx"] = postprocess(sel["idx_raw"], sel["vmax"], ex, ey, sigmas, theta)
     return sel
+
+
+# ------------------------------------------------------ crease extraction
+def crease_field(u, sigma_d=1.0):
+    """Planes (g_x, g_y, h_xx, h_xy, h_yy, d) of u_sigma_d, d = det(g | Hg)
+    (Sec. 3.6)."""
+    u = _f64(u)
+    H, W = u.shape
+    out = np.zeros((6, H, W))
+    lib().ref_crease_field(_d(u), H, W, float(np.float32(sigma_d)), _d(out))
+    return out
+
+
+def marching_creases(planes, strength=0.0, mode=BOTH):
+    """Marching squares on d with the crease test. Returns (seg, type, count):
+    seg [H-1][W-1][2][4] (x0, y0, x1, y1), type [H-1][W-1][2] int8
+    (+1 ridge, -1 valley, 0 empty)."""
+    planes = _f64(planes)
+    _, H, W = planes.shape
+    seg = np.zeros((H - 1, W - 1, 2, 4))
+    typ = np.zeros((H - 1, W - 1, 2), np.int8)
+    n = lib().ref_marching_creases(_d(planes), H, W, float(np.float32(strength)), int(mode), _d(seg),
+                                   typ.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)))
+    return seg, typ, int(n)
+
+
+def creases(u, sigma_d=1.0, strength=0.0, mode=BOTH):
+    return marching_creases(crease_field(u, sigma_d), strength, mode)
+
+
+def segment_hausdorff(a, b):
+    return lib().ref_segment_hausdorff(_d(_f64(a)), _d(_f64(b)))
+
+
+def gt_segments(lines):
+    """Ground-truth centrelines [(points (K, 2) as (x, y), sign), ...] as
+    segments between consecutive samples: (segs [n][4], types [n])."""
+    segs, types = [], []
+    for pts, sgn in lines:
+        pts = np.asarray(pts, np.float64)
+        if len(pts) < 2:
+            continue
+        segs.append(np.concatenate([pts[:-1], pts[1:]], axis=1))
+        types.append(np.full(len(pts) - 1, int(sgn), np.int32))
+    if not segs:
+        return np.zeros((0, 4)), np.zeros(0, np.int32)
+    return np.ascontiguousarray(np.concatenate(segs)), np.ascontiguousarray(np.concatenate(types))
+
+
+def crease_match(seg, typ, gt, gt_type, radius=6.0):
+    """Per ground-truth segment: distance of its midpoint to the matched
+    reconstruction (-1 if none) and the match index (2 cell + slot)."""
+    seg = _f64(seg)
+    Hm, Wm = seg.shape[:2]
+    typ = np.ascontiguousarray(typ, np.int8)
+    gt = _f64(gt).reshape(-1, 4)
+    gtt = np.ascontiguousarray(gt_type, np.int32)
+    n = len(gt)
+    dist = np.zeros(n)
+    match = np.zeros(n, np.int64)
+    lib().ref_crease_match(_d(seg), typ.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), Hm + 1, Wm + 1, _d(gt),
+                           gtt.ctypes.data_as(_ip), n, float(radius), _d(dist),
+                           match.ctypes.data_as(ctypes.POINTER(ctypes.c_long)))
+    return dist, match
+
+
+def crease_scores(dist):
+    """E = mean distance over detected ground-truth segments, p = detected share (Sec. 4)."""
+    dist = np.asarray(dist)
+    ok = dist >= 0
+    return (float(dist[ok].mean()) if ok.any() else float("nan")), float(ok.mean()) if len(dist) else float("nan")
 
 
 # ------------------------------------------------------------- learned net

@@ -515,6 +515,8 @@ int mf4d_batch_create(int nimg, const int64_t *offsets, const int *H, const int 
     if (nimg < 1 || !offsets || !H || !W || !per_image) return MF4D_EINVAL;
     for (int i = 0; i < nimg; ++i) {
         if (validate_params(H[i], W[i], &per_image[i]) != MF4D_OK) return MF4D_EINVAL;
+        if (per_image[i].model != MF4D_MAFOD || per_image[i].postprocess != 0 || per_image[i].check != 0)
+            return MF4D_EINVAL;
         if (offsets[i] < 0 || !same_shared(per_image[0], per_image[i])) return MF4D_EINVAL;
     }
     // images must not overlap in the packed buffer

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "mf4d_internal.h"
@@ -87,7 +88,11 @@ int validate(int H, int W, const mf4d_params *p)
     if (p->substeps == 0 && p->cycles > 0 && !(p->stop_time > 0.0 && std::isfinite(p->stop_time)))
         return MF4D_EINVAL;
     if (p->reselect_each_cycle != 0 && p->reselect_each_cycle != 1) return MF4D_EINVAL;
-    if (p->postprocess != 0) return MF4D_EINVAL;
+    if (p->postprocess != 0 && p->postprocess != 1) return MF4D_EINVAL;
+    if (p->postprocess == 1 && !std::isfinite(p->theta)) return MF4D_EINVAL;
+    if (p->check != 0 && p->check != 1) return MF4D_EINVAL;
+    if (p->model != MF4D_MAFOD && p->model != MF4D_IFOD) return MF4D_EINVAL;
+    if (p->model == MF4D_IFOD && p->nscales != 1) return MF4D_EINVAL;
     return MF4D_OK;
 }
 
@@ -162,6 +167,11 @@ struct Workspace {
     float *tens;             // compact tensor planes of the current cycle
     float *utmp;
     unsigned *smax;
+    float *vmax;             // max_s V_s (postprocessing)
+    uint8_t *idx2;           // postprocessed indices
+    float *u2;               // second ping-pong image (l2-optimal stopping)
+    double *partial;         // kRedBlocks partial sums of an l2 reduction
+    MonitorState *mon;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -185,6 +195,11 @@ size_t layout(int H, int W, int ns, Workspace *w, char *base)
     t.tens = (float *)take(m * 12);
     t.utmp = (float *)take(m * 4);
     t.smax = (unsigned *)take(256);
+    t.vmax = (float *)take(m * 4);
+    t.idx2 = (uint8_t *)take(m);
+    t.u2 = (float *)take(m * 4);
+    t.partial = (double *)take(sizeof(double) * kRedBlocks);
+    t.mon = (MonitorState *)take(sizeof(MonitorState));
     if (w) *w = t;
     return off;
 }
@@ -284,7 +299,7 @@ int run_substeps(const float *u_first, float *const bufs[2], int &launch_index, 
 // (when want_n) and the image-wide maximum of S (cleared first unless
 // clear_max is false: an earlier kernel on the stream has left it at 0).
 int run_sweep(const float *u, int H, int W, const mf4d_params *p, const Workspace &w,
-              bool want_n, hipStream_t s, bool clear_max = true)
+              bool want_n, hipStream_t s, bool clear_max = true, bool fork = true)
 {
     const size_t m = (size_t)H * W;
     if (clear_max) CHECK_HIP(launch_fill_u32(w.smax, 0u, 1, s));
@@ -294,7 +309,7 @@ int run_sweep(const float *u, int H, int W, const mf4d_params *p, const Workspac
         make_taps(p->sigmas[k], &taps[k]);
         fused = fused && sweep_engine(taps[k]) == kSweepFused;
     }
-    ForkStreams *fs = (fused && p->nscales > 1) ? fork_streams() : nullptr;
+    ForkStreams *fs = (fork && fused && p->nscales > 1) ? fork_streams() : nullptr;
     auto launch = [&](int k, hipStream_t st) {
         ScalePlanes planes{w.SA + 2 * k * m, want_n ? w.N + 3 * k * m : nullptr};
         return launch_sweep_scale(u, w.hA, w.hB, w.hC, H, W, taps[k], p->sigmas[k], p->mode, p->beta, planes,
@@ -337,6 +352,38 @@ SelectArgs select_args(const mf4d_params *p, const Workspace &w)
     return a;
 }
 
+// Ordered schedules already computed, keyed by (n, T/M, tau_max) bit for bit:
+// the kappa search costs O(phi(n) n Q) on the host, milliseconds at n = 10
+// and a large fraction of a second at n in the hundreds, so every call after
+// the first reuses it. The cache is bounded and shared by all threads.
+struct Schedule {
+    int n;
+    double TM, tau_max;
+    int kappa;
+    std::vector<double> ordered;
+    std::vector<int> perm;
+};
+
+const Schedule &cached_schedule(int n, double TM, double tau_max)
+{
+    static std::mutex mu;
+    static std::vector<Schedule *> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    for (const Schedule *c : cache)
+        if (c->n == n && std::memcmp(&c->TM, &TM, sizeof TM) == 0 &&
+            std::memcmp(&c->tau_max, &tau_max, sizeof tau_max) == 0)
+            return *c;
+    Schedule *c = new Schedule{n, TM, tau_max, 1, std::vector<double>(n), std::vector<int>(n)};
+    c->kappa = order_steps(natural_steps(n, TM), tau_max, c->ordered.data(), c->perm.data());
+    if (cache.size() >= 64) {   // entries stay valid for earlier callers: retire, do not free
+        static std::vector<Schedule *> retired;
+        retired.push_back(cache.front());
+        cache.erase(cache.begin());
+    }
+    cache.push_back(c);
+    return *c;
+}
+
 int plan(const mf4d_params *p, int *n_out, std::vector<double> &ordered)
 {
     int n = p->substeps;
@@ -349,9 +396,143 @@ int plan(const mf4d_params *p, int *n_out, std::vector<double> &ordered)
         if (n < 1) return MF4D_EINVAL;
         TM = p->stop_time / p->cycles;
     }
-    ordered.assign(n, 0.0);
-    order_steps(natural_steps(n, TM), p->tau_max, ordered.data(), nullptr);
+    ordered = cached_schedule(n, TM, p->tau_max).ordered;
     *n_out = n;
+    return MF4D_OK;
+}
+
+// l2-optimal stopping (mf4d_filter_l2stop): the ground truth and the outputs.
+struct StopArgs {
+    const float *gt;
+    double *l2_out;
+    int *best_out;
+};
+
+float growth_tolerance()
+{
+    if (const char *e = std::getenv("MF4D_L2_GROWTH_TOL")) return (float)std::atof(e);
+    return 1e-5f;
+}
+
+// Scale selection of one cycle into w.idx (raw argmax) or, with the
+// postprocessing, w.idx2; returns the indices the tensor must use.
+int select_cycle(const float *src, int H, int W, const mf4d_params *p, const Workspace &w, const SelectArgs &a,
+                 bool first, bool reselect, hipStream_t s, bool fork)
+{
+    int st = run_sweep(src, H, W, p, w, true, s, first, fork);
+    if (st != MF4D_OK) return st;
+    SelectArgs ak = a;
+    if (!p->postprocess) {
+        if (reselect) ak.idx_out = w.idx;
+        else ak.idx_in = w.idx;
+        CHECK_HIP(launch_select(ak, H, W, s));
+        return MF4D_OK;
+    }
+    if (reselect) {
+        SelectArgs am = a;
+        am.coef = nullptr;
+        am.hrho = nullptr;
+        am.smax_reset = nullptr;
+        am.idx_out = w.idx;
+        am.vmax_out = w.vmax;
+        CHECK_HIP(launch_select(am, H, W, s));
+        ScaleTable tab{};
+        for (int k = 0; k < p->nscales; ++k) tab.s[k] = p->sigmas[k];
+        const int tmax = (int)std::ceil(3.0 * (double)p->sigmas[p->nscales - 1]);
+        CHECK_HIP(launch_postprocess(w.idx, w.vmax, w.N, p->nscales, H, W, tab, p->theta, tmax, w.idx2, s));
+    }
+    ak.idx_in = w.idx2;
+    CHECK_HIP(launch_rho(ak, H, W, s));
+    return MF4D_OK;
+}
+
+// Isotropic model: the tensor planes (g, 0, 0) of one cycle (and optionally
+// the Hessian of u_sigma) from one horizontal pass and the g kernel.
+int ifod_cycle(const float *src, int H, int W, const mf4d_params *p, const Workspace &w, float *coef, float *hess,
+               hipStream_t s)
+{
+    WinTaps t;
+    make_taps(p->sigmas[0], &t);
+    CHECK_HIP(launch_hpass(src, w.hA, w.hB, w.hC, H, W, t, s));
+    CHECK_HIP(launch_ifod_coef(w.hA, w.hB, w.hC, H, W, t, 1.f / (p->lambda * p->lambda), coef, hess, s));
+    return MF4D_OK;
+}
+
+// The whole filter (a1-a7), optionally with the stability monitor
+// (p->check) and l2-optimal stopping (stop != nullptr).
+int run_filter(const float *u_in, float *u_out, int H, int W, const mf4d_params *p, char *base,
+               const StopArgs *stop, hipStream_t s, bool fork = true)
+{
+    const size_t m = (size_t)H * W;
+    Workspace w;
+    layout(H, W, p->nscales, &w, base);
+    const bool check = p->check == 1;
+    const float tol = growth_tolerance();
+    if (check || stop) CHECK_HIP(launch_monitor_reset(w.mon, s));
+    if (check) CHECK_HIP(launch_l2(u_in, nullptr, m, w.partial, w.mon, kMonitorInit, tol, 0, nullptr, nullptr, s));
+    if (stop) {
+        CHECK_HIP(launch_l2(u_in, stop->gt, m, w.partial, w.mon, kStopStep, tol, 0, stop->l2_out, stop->best_out, s));
+        CHECK_HIP(launch_copy_f32(u_in, u_out, m, s));
+    }
+    int st = MF4D_OK;
+    if (p->cycles == 0) {
+        if (!stop && u_in != u_out) CHECK_HIP(launch_copy_f32(u_in, u_out, m, s));
+    } else {
+        std::vector<double> ordered;
+        int n = 0;
+        st = plan(p, &n, ordered);
+        if (st != MF4D_OK) return st;
+        std::vector<float> tau32(n);
+        for (int i = 0; i < n; ++i) tau32[i] = (float)ordered[i];
+        // substeps run kSubstepsPerLaunch per launch (the intermediate images
+        // stay in registers); the last launch of a cycle takes the remainder
+        const int spl = kSubstepsPerLaunch;
+        const int launches_per_cycle = (n + spl - 1) / spl;
+        // launch j writes bufs[j % 2]; without stopping the last launch must
+        // write u_out; with stopping the images ping-pong in the workspace and
+        // the best one is copied to u_out
+        const long long total = (long long)p->cycles * launches_per_cycle;
+        float *bufs[2];
+        const float *src = u_in;
+        if (stop) {
+            bufs[0] = w.utmp;
+            bufs[1] = w.u2;
+        } else {
+            bufs[0] = (total % 2 == 1) ? u_out : w.utmp;
+            bufs[1] = (total % 2 == 1) ? w.utmp : u_out;
+            if ((const float *)bufs[0] == u_in) {
+                // in-place call whose first launch would overwrite its own input
+                CHECK_HIP(launch_copy_f32(u_in, w.utmp, m, s));
+                src = w.utmp;
+                bufs[0] = u_out;
+                bufs[1] = w.utmp;
+            }
+        }
+        SelectArgs a = select_args(p, w);
+        a.coef = w.tens;
+        a.smax_reset = w.smax;   // each cycle's integration clears the max of S for the next cycle's sweep
+        int li = 0;
+        for (int k = 0; k < p->cycles; ++k) {
+            if (p->model == MF4D_IFOD) st = ifod_cycle(src, H, W, p, w, w.tens, nullptr, s);
+            else st = select_cycle(src, H, W, p, w, a, k == 0, (k == 0) || p->reselect_each_cycle, s, fork);
+            if (st != MF4D_OK) return st;
+            st = run_substeps(src, bufs, li, w.tens, H, W, tau32.data(), n, spl, s, &src);
+            if (st != MF4D_OK) return st;
+            if (check)
+                CHECK_HIP(launch_l2(src, nullptr, m, w.partial, w.mon, kMonitorCycle, tol, 0, nullptr, nullptr, s));
+            if (stop) {
+                CHECK_HIP(launch_l2(src, stop->gt, m, w.partial, w.mon, kStopStep, tol, k + 1, stop->l2_out,
+                                    stop->best_out, s));
+                CHECK_HIP(launch_take_copy(src, u_out, m, w.mon, s));
+            }
+        }
+    }
+    if (!check) return MF4D_OK;
+    CHECK_HIP(hipStreamSynchronize(s));
+    MonitorState h;
+    CHECK_HIP(hipMemcpy(&h, w.mon, sizeof h, hipMemcpyDeviceToHost));
+    if (h.nonfinite) return MF4D_ENONFINITE;
+    if (h.growth) return MF4D_EUNSTABLE;
     return MF4D_OK;
 }
 
@@ -389,6 +570,8 @@ const char *mf4d_status_string(int status)
     case MF4D_EINVAL: return "invalid argument";
     case MF4D_ENOMEM: return "workspace too small";
     case MF4D_EHIP: return "HIP runtime or launch error";
+    case MF4D_ENONFINITE: return "non-finite value in the image";
+    case MF4D_EUNSTABLE: return "l2 norm grew over a cycle";
     default: return "unknown status";
     }
 }
@@ -418,7 +601,10 @@ int mf4d_fed_schedule(int n, double tau_max, double *taus_out, int *perm_out)
 {
     if (n < 1 || n > MF4D_MAX_SUBSTEPS || !valid_tau_max(tau_max) || !taus_out) return MF4D_EINVAL;
     const double TM = tau_max * ((double)n * n + n) / 3.0;
-    return order_steps(natural_steps(n, TM), tau_max, taus_out, perm_out);
+    const Schedule &c = cached_schedule(n, TM, tau_max);
+    std::memcpy(taus_out, c.ordered.data(), sizeof(double) * n);
+    if (perm_out) std::memcpy(perm_out, c.perm.data(), sizeof(int) * n);
+    return c.kappa;
 }
 
 int mf4d_fed_substeps(double stop_time, int cycles, double tau_max)
@@ -454,18 +640,26 @@ int mf4d_scale_select(const float *u, int H, int W, const mf4d_params *p, uint8_
 {
     int st = validate(H, W, p);
     if (st != MF4D_OK) return st;
-    if (!u || !idx_out || !ws) return MF4D_EINVAL;
+    if (!u || !idx_out || !ws || p->model != MF4D_MAFOD) return MF4D_EINVAL;
     if (ws_bytes < layout(H, W, p->nscales, nullptr, nullptr)) return MF4D_ENOMEM;
     hipStream_t s = (hipStream_t)stream;
     Workspace w;
     layout(H, W, p->nscales, &w, (char *)ws);
-    st = run_sweep(u, H, W, p, w, false, s);
+    const bool post = p->postprocess == 1;
+    st = run_sweep(u, H, W, p, w, post, s);   // the postprocessing reads the Hessians (N) of every scale
     if (st != MF4D_OK) return st;
     SelectArgs a = select_args(p, w);
-    a.idx_out = idx_out;
-    a.vmax_out = vmax_out;
+    a.idx_out = post ? w.idx : idx_out;
+    a.vmax_out = post ? w.vmax : vmax_out;
     a.c_out = c_out;
-    return hip_status(launch_select(a, H, W, s));
+    CHECK_HIP(launch_select(a, H, W, s));
+    if (!post) return MF4D_OK;
+    ScaleTable tab{};
+    for (int k = 0; k < p->nscales; ++k) tab.s[k] = p->sigmas[k];
+    const int tmax = (int)std::ceil(3.0 * (double)p->sigmas[p->nscales - 1]);
+    CHECK_HIP(launch_postprocess(w.idx, w.vmax, w.N, p->nscales, H, W, tab, p->theta, tmax, idx_out, s));
+    if (vmax_out) CHECK_HIP(launch_copy_f32(w.vmax, vmax_out, (size_t)H * W, s));
+    return MF4D_OK;
 }
 
 int mf4d_tensor(const float *u, int H, int W, const uint8_t *idx, const mf4d_params *p,
@@ -473,11 +667,12 @@ int mf4d_tensor(const float *u, int H, int W, const uint8_t *idx, const mf4d_par
 {
     int st = validate(H, W, p);
     if (st != MF4D_OK) return st;
-    if (!u || !idx || !hrho_out || !ws) return MF4D_EINVAL;
+    if (!u || !hrho_out || !ws || (!idx && p->model == MF4D_MAFOD)) return MF4D_EINVAL;
     if (ws_bytes < layout(H, W, p->nscales, nullptr, nullptr)) return MF4D_ENOMEM;
     hipStream_t s = (hipStream_t)stream;
     Workspace w;
     layout(H, W, p->nscales, &w, (char *)ws);
+    if (p->model == MF4D_IFOD) return ifod_cycle(u, H, W, p, w, dparams_out ? dparams_out : w.tens, hrho_out, s);
     st = run_sweep(u, H, W, p, w, true, s);
     if (st != MF4D_OK) return st;
     SelectArgs a = select_args(p, w);
@@ -495,6 +690,7 @@ int mf4d_fed_cycle(float *u, float *u_tmp, int H, int W, const float *hrho, cons
     if (st != MF4D_OK) return st;
     if (!u || !u_tmp || u == u_tmp || !hrho || !taus || n < 1 || n > MF4D_MAX_SUBSTEPS)
         return MF4D_EINVAL;
+    if (p->model != MF4D_MAFOD) return MF4D_EINVAL;
     for (int i = 0; i < n; ++i)
         if (!(taus[i] > 0.0) || !std::isfinite(taus[i])) return MF4D_EINVAL;
     hipStream_t s = (hipStream_t)stream;
@@ -538,59 +734,25 @@ int mf4d_filter(const float *u_in, float *u_out, int H, int W, const mf4d_params
     if (st != MF4D_OK) return st;
     if (!u_in || !u_out || !ws) return MF4D_EINVAL;
     if (ws_bytes < layout(H, W, p->nscales, nullptr, nullptr)) return MF4D_ENOMEM;
-    hipStream_t s = (hipStream_t)stream;
-    const size_t m = (size_t)H * W;
-    if (p->cycles == 0) {
-        if (u_in != u_out) CHECK_HIP(launch_copy_f32(u_in, u_out, m, s));
-        return MF4D_OK;
-    }
-    std::vector<double> ordered;
-    int n = 0;
-    st = plan(p, &n, ordered);
-    if (st != MF4D_OK) return st;
-    std::vector<float> tau32(n);
-    for (int i = 0; i < n; ++i) tau32[i] = (float)ordered[i];
-    // substeps run kSubstepsPerLaunch per launch (the intermediate images stay
-    // in registers); the last launch of a cycle takes the remainder
-    const int spl = kSubstepsPerLaunch;
-    const int launches_per_cycle = (n + spl - 1) / spl;
+    return run_filter(u_in, u_out, H, W, p, (char *)ws, nullptr, (hipStream_t)stream);
+}
 
-    Workspace w;
-    layout(H, W, p->nscales, &w, (char *)ws);
-    // launch j writes bufs[j % 2]; the last launch must write u_out
-    const long long total = (long long)p->cycles * launches_per_cycle;
-    float *bufs[2];
-    bufs[0] = (total % 2 == 1) ? u_out : w.utmp;
-    bufs[1] = (total % 2 == 1) ? w.utmp : u_out;
-    const float *src = u_in;
-    if ((const float *)bufs[0] == u_in) {
-        // in-place call whose first launch would overwrite its own input
-        CHECK_HIP(launch_copy_f32(u_in, w.utmp, m, s));
-        src = w.utmp;
-        bufs[0] = u_out;
-        bufs[1] = w.utmp;
-    }
-    SelectArgs a = select_args(p, w);
-    a.coef = w.tens;
-    a.smax_reset = w.smax;   // each cycle's integration clears the max of S for the next cycle's sweep
-    int li = 0;
-    for (int k = 0; k < p->cycles; ++k) {
-        const bool reselect = (k == 0) || p->reselect_each_cycle;
-        st = run_sweep(src, H, W, p, w, true, s, k == 0);
-        if (st != MF4D_OK) return st;
-        SelectArgs ak = a;
-        if (reselect) ak.idx_out = w.idx;
-        else ak.idx_in = w.idx;
-        CHECK_HIP(launch_select(ak, H, W, s));
-        st = run_substeps(src, bufs, li, w.tens, H, W, tau32.data(), n, spl, s, &src);
-        if (st != MF4D_OK) return st;
-    }
-    return MF4D_OK;
+int mf4d_filter_l2stop(const float *u_in, float *u_out, int H, int W, const mf4d_params *p,
+                       const float *ground_truth, double *l2_out, int *best_out, void *ws, size_t ws_bytes,
+                       void *stream)
+{
+    int st = validate(H, W, p);
+    if (st != MF4D_OK) return st;
+    if (!u_in || !u_out || !ground_truth || !ws || u_out == u_in || u_out == ground_truth) return MF4D_EINVAL;
+    if (ws_bytes < layout(H, W, p->nscales, nullptr, nullptr)) return MF4D_ENOMEM;
+    StopArgs stop{ground_truth, l2_out, best_out};
+    return run_filter(u_in, u_out, H, W, p, (char *)ws, &stop, (hipStream_t)stream);
 }
 
 size_t mf4d_learned_workspace_bytes(int H, int W, const mf4d_params *p)
 {
     if (validate(H, W, p) != MF4D_OK || p->nscales > 8 || H % 16 != 0 || W % 16 != 0) return 0;
+    if (p->model != MF4D_MAFOD || p->postprocess != 0 || p->check != 0) return 0;
     return align256(layout(H, W, p->nscales, nullptr, nullptr)) + align256(net_forward_bytes(H, W)) +
            sizeof(unsigned) * kFallbackSlots;
 }
@@ -602,6 +764,7 @@ int mf4d_filter_learned(const float *u_in, float *u_out, int H, int W, const mf4
     if (st != MF4D_OK) return st;
     if (!u_in || !u_out || !theta || !ws || p->nscales > 8 || H % 16 != 0 || W % 16 != 0) return MF4D_EINVAL;
     if (!(conf_threshold >= 0.f) || conf_threshold > 1.f || p->reselect_each_cycle != 1) return MF4D_EINVAL;
+    if (p->model != MF4D_MAFOD || p->postprocess != 0 || p->check != 0) return MF4D_EINVAL;
     const size_t need = mf4d_learned_workspace_bytes(H, W, p);
     if (ws_bytes < need) return MF4D_ENOMEM;
     hipStream_t s = (hipStream_t)stream;

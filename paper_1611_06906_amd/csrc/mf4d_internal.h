@@ -134,4 +134,32 @@ hipError_t launch_learned_select(const uint8_t *sel, const SelectArgs &a, int H,
                                  hipStream_t s);
 hipError_t launch_fallback_sum(const unsigned *slots, unsigned *total, hipStream_t s);
 
+// ------------------------------------------------------------ aux_kernels.hip
+// Per-call device state of the stability monitor and of l2-optimal stopping
+// (kept in the workspace; reset by launch_monitor_reset at the start of a call).
+struct MonitorState {
+    double prev;          // squared l2 norm after the last monitored cycle
+    double best;          // smallest distance to the ground truth so far
+    unsigned nonfinite;   // a non-finite value was seen
+    unsigned growth;      // a cycle grew the l2 norm beyond the tolerance
+    unsigned take;        // the last stopping step improved on the best
+    int best_k;
+};
+constexpr int kRedBlocks = 1024;   // partial sums of one l2 reduction (FP64)
+enum { kMonitorInit = 0, kMonitorCycle = 1, kStopStep = 2 };
+struct ScaleTable {
+    float s[MF4D_MAX_SCALES];
+};
+hipError_t launch_monitor_reset(MonitorState *st, hipStream_t s);
+// sum of d^2 over m values (d = u, or u - ref), then the bookkeeping `what`
+// (step k of a stopping run writes l2_out[k] and *best_out)
+hipError_t launch_l2(const float *u, const float *ref, size_t m, double *partial, MonitorState *st, int what,
+                     float growth_tol, int k, double *l2_out, int *best_out, hipStream_t s);
+hipError_t launch_take_copy(const float *src, float *dst, size_t m, const MonitorState *st, hipStream_t s);
+// isotropic model: g planes (g, 0, 0) from the horizontal planes of one scale
+hipError_t launch_ifod_coef(const float *A, const float *B, const float *C, int H, int W, const WinTaps &t,
+                            float inv_lam2, float *coef, float *hess, hipStream_t s);
+hipError_t launch_postprocess(const uint8_t *idx, const float *vmax, const float *N, int ns, int H, int W,
+                              const ScaleTable &sig, float theta, int tmax, uint8_t *out, hipStream_t s);
+
 }  // namespace mf4d

@@ -18,14 +18,16 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmf4d.so")
 
 MF4D_OK, MF4D_EINVAL, MF4D_ENOMEM, MF4D_EHIP = 0, -1, -2, -3
+MF4D_ENONFINITE, MF4D_EUNSTABLE = -4, -5
 MF4D_RIDGE, MF4D_VALLEY, MF4D_BOTH = 0, 1, 2
+MF4D_MAFOD, MF4D_IFOD = 0, 1
 MF4D_MAX_SCALES, MF4D_MAX_RADIUS, MF4D_MAX_SUBSTEPS = 16, 64, 1024
 
 # every symbol include/mf4d.h declares
 EXPORTS = ["mf4d_status_string", "mf4d_params_default", "mf4d_fed_schedule",
            "mf4d_fed_substeps", "mf4d_fed_plan", "mf4d_workspace_bytes",
            "mf4d_scale_select", "mf4d_tensor", "mf4d_fed_cycle", "mf4d_fed_cycle_tensor",
-           "mf4d_filter", "mf4d_batch_create", "mf4d_batch_workspace_bytes", "mf4d_filter_batch",
+           "mf4d_filter", "mf4d_filter_l2stop", "mf4d_batch_create", "mf4d_batch_workspace_bytes", "mf4d_filter_batch",
            "mf4d_batch_autotune", "mf4d_batch_get_tuning", "mf4d_batch_set_tuning", "mf4d_batch_destroy",
            "mf4d_net_param_count", "mf4d_net_workspace_bytes", "mf4d_net_forward", "mf4d_net_backward",
            "mf4d_net_step", "mf4d_learned_workspace_bytes", "mf4d_filter_learned"]
@@ -53,6 +55,8 @@ class mf4d_params(ctypes.Structure):
         ("reselect_each_cycle", ctypes.c_int),
         ("theta", ctypes.c_float),
         ("postprocess", ctypes.c_int),
+        ("check", ctypes.c_int),
+        ("model", ctypes.c_int),
     ]
 
 
@@ -61,11 +65,12 @@ class Params:
 
     def __init__(self, sigmas, mode=MF4D_BOTH, lam=0.005, rho=0.5, beta=0.5, c=-1.0,
                  cycles=1, substeps=10, stop_time=0.0, tau_max=0.05, reselect_each_cycle=1,
-                 theta=0.0, postprocess=0):
+                 theta=0.0, postprocess=0, check=0, model=MF4D_MAFOD):
         self.sigmas = np.ascontiguousarray(np.asarray(sigmas, dtype=np.float32))
         self.mode, self.lam, self.rho, self.beta, self.c = mode, lam, rho, beta, c
         self.cycles, self.substeps, self.stop_time, self.tau_max = cycles, substeps, stop_time, tau_max
         self.reselect_each_cycle, self.theta, self.postprocess = reselect_each_cycle, theta, postprocess
+        self.check, self.model = check, model
 
     @classmethod
     def from_workload(cls, w, **kw):
@@ -90,6 +95,8 @@ class Params:
         p.reselect_each_cycle = int(self.reselect_each_cycle)
         p.theta = float(self.theta)
         p.postprocess = int(self.postprocess)
+        p.check = int(self.check)
+        p.model = int(self.model)
         return p
 
 
@@ -127,6 +134,8 @@ def lib():
         L.mf4d_fed_cycle_tensor.restype = i
         L.mf4d_filter.argtypes = [vp, vp, i, i, P(mf4d_params), vp, sz, vp]
         L.mf4d_filter.restype = i
+        L.mf4d_filter_l2stop.argtypes = [vp, vp, i, i, P(mf4d_params), vp, vp, vp, vp, sz, vp]
+        L.mf4d_filter_l2stop.restype = i
         L.mf4d_batch_create.argtypes = [i, P(ctypes.c_int64), P(i), P(i), P(mf4d_params), P(vp)]
         L.mf4d_batch_create.restype = i
         L.mf4d_batch_workspace_bytes.argtypes = [vp]
@@ -297,6 +306,25 @@ def mf4d_filter(u_in, u_out, params: Params, ws=None, stream=None):
     st = params.struct()
     _check(lib().mf4d_filter(_ptr(u_in), _ptr(u_out), H, W, ctypes.byref(st), _ptr(ws), ws.numel(),
                              _stream(stream)), "mf4d_filter")
+
+
+def mf4d_filter_l2stop(u_in, u_out, params: Params, ground_truth, l2_out=None, best_out=None, ws=None,
+                       stream=None):
+    """l2-optimal stopping (Sec. 4): u_out receives the cycle-end state closest
+    to ground_truth; l2_out (float64 [cycles + 1]) and best_out (int32 [1])
+    receive the distances and the chosen cycle."""
+    H, W = _hw(_dev(u_in, torch.float32, name="u_in"))
+    _dev(u_out, torch.float32, (H, W), "u_out")
+    _dev(ground_truth, torch.float32, (H, W), "ground_truth")
+    _dev(l2_out, torch.float64, (params.cycles + 1,), "l2_out")
+    _dev(best_out, torch.int32, (1,), "best_out")
+    if ws is None:
+        ws = workspace(H, W, params, u_in.device)
+    _dev(ws, torch.uint8, name="ws")
+    st = params.struct()
+    _check(lib().mf4d_filter_l2stop(_ptr(u_in), _ptr(u_out), H, W, ctypes.byref(st), _ptr(ground_truth),
+                                    _ptr(l2_out), _ptr(best_out), _ptr(ws), ws.numel(), _stream(stream)),
+           "mf4d_filter_l2stop")
 
 
 # ------------------------------------------------------------------ batches

@@ -21,15 +21,16 @@ def m():
 
 def test_header_symbols_exported(m):
     hdr = open(os.path.join(ROOT, "include", "mf4d.h")).read()
-    declared = set(re.findall(r"\b(mf4d_[a-z_]+)\s*\(", hdr))
+    declared = set(re.findall(r"\b(mf4d_[a-z0-9_]+)\s*\(", hdr))
     assert declared == set(m.EXPORTS)
     for name in declared:
         assert hasattr(m.lib(), name), name
 
 
 def test_status_strings(m):
-    for st in (0, -1, -2, -3, 7):
+    for st in (0, -1, -2, -3, -4, -5, 7):
         assert len(m.status_string(st)) > 0
+    assert m.status_string(-4) != m.status_string(7) and m.status_string(-5) != m.status_string(7)
 
 
 def test_schedule_equals_oracle_bitwise(m, oracle_lib):
@@ -72,15 +73,27 @@ def test_validation_rejects_before_launch(m):
         (64, 64, P(rho=-1.0)), (64, 64, P(rho=5.0)), (64, 64, P(beta=0.0)),
         (64, 64, P(c=float("inf"))), (64, 64, P(cycles=-1)), (64, 64, P(tau_max=0.06)),
         (64, 64, P(tau_max=0.0)), (64, 64, P(substeps=0, stop_time=0.0)),
-        (64, 64, P(substeps=2000)), (64, 64, P(reselect_each_cycle=2)), (64, 64, P(postprocess=1)),
+        (64, 64, P(substeps=2000)), (64, 64, P(reselect_each_cycle=2)), (64, 64, P(postprocess=2)),
+        (64, 64, P(postprocess=1, theta=float("nan"))), (64, 64, P(check=2)), (64, 64, P(model=2)),
+        (64, 64, P(model=1)),   # the isotropic model takes exactly one scale
     ]
     for H, W, p in bad:
         assert m.mf4d_workspace_bytes(H, W, p) == 0
         assert _raw_filter(m, H, W, p) == m.MF4D_EINVAL
     # valid parameters but missing buffers are rejected too
     assert _raw_filter(m, 64, 64, P()) == m.MF4D_EINVAL
-    # lambda = +inf (linear isotropic) and rho = 0 are valid
+    # lambda = +inf (linear isotropic) and rho = 0 are valid, and so are the
+    # postprocessing, the check and the isotropic model with one scale
     assert m.mf4d_workspace_bytes(64, 64, P(lam=math.inf, rho=0.0)) > 0
+    assert m.mf4d_workspace_bytes(64, 64, P(postprocess=1, theta=0.2, check=1)) > 0
+    assert m.mf4d_workspace_bytes(64, 64, P(sigmas=[1.0], model=1)) > 0
+    # l2 stopping: u_out must not alias the input or the ground truth
+    st = P().struct()
+    L = m.lib()
+    for uo in (16, 32):
+        assert L.mf4d_filter_l2stop(ctypes.c_void_p(16), ctypes.c_void_p(uo), 64, 64, ctypes.byref(st),
+                                    ctypes.c_void_p(32), None, None, ctypes.c_void_p(64), 1 << 30,
+                                    None) == m.MF4D_EINVAL
     # workspace too small
     st = P().struct()
     nb = m.mf4d_workspace_bytes(64, 64, P())
@@ -126,6 +139,9 @@ def test_batch_plan_validation(m):
         (shapes, [P(sig, substeps=5), P(sig, substeps=6)], None),   # different schedule
         (shapes, [P(sig), P(sig)], [0, 100]),                       # overlapping images
         ([(2, 40), (20, 20)], [P(sig), P(sig)], None),              # invalid size
+        (shapes, [P(sig, postprocess=1), P(sig, postprocess=1)], None),   # batches do not postprocess
+        (shapes, [P(sig, check=1), P(sig, check=1)], None),               # nor check
+        (shapes, [P([1.0], model=1), P([1.0], model=1)], None),           # nor run the isotropic model
     ]
     for sh, prm, off in bad:
         with pytest.raises(m.MF4DError):

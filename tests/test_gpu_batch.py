@@ -179,3 +179,43 @@ def test_batch_total_beyond_2e31_pixels(env):
         assert not torch.equal(ref, pin[k * n:(k + 1) * n].view(H, W))
     del ws1, ref, pin, pout
     torch.cuda.empty_cache()
+
+
+# images of the 256-image batched workload (indices into synth.batch_of_images():
+# ridge and valley, 6 to 25 cycles, one side >= 1024)
+ORACLE_PICK = [210, 162, 58, 144, 12, 22]
+
+
+def test_batch_against_oracle(env):
+    """Batched outputs against the FP64 oracle, element by element, on
+    images of the batched workload itself (sizes U[256, 1536], per-image
+    mode and cycle count, scales 1, 1.5, 2, 3, n = 10)."""
+    import oracle
+    m, synth, torch = env["m"], env["synth"], env["torch"]
+    specs = synth.batch_of_images()
+    pick = [specs[i] for i in ORACLE_PICK]
+    assert {s["mode"] for s in pick} == {0, 1} and max(max(s["H"], s["W"]) for s in pick) >= 1024
+    assert len({s["cycles"] for s in pick}) == len(pick)
+    sig = [1.0, 1.5, 2.0, 3.0]
+    imgs = [synth.batch_image(s) for s in pick]
+    params = [m.Params(sig, mode=s["mode"], cycles=s["cycles"], substeps=10) for s in pick]
+    shapes = [(s["H"], s["W"]) for s in pick]
+    packed = torch.from_numpy(np.concatenate([im.ravel() for im in imgs])).to(env["dev"])
+    out = torch.empty_like(packed)
+    plan = m.Batch(shapes, params)
+    ws = plan.workspace(env["dev"])
+    plan.autotune(ws)
+    plan.filter(packed, out, ws)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    plan.close()
+    pos = 0
+    for s, im in zip(pick, imgs):
+        h, w = s["H"], s["W"]
+        g = got[pos:pos + h * w].reshape(h, w).astype(np.float64)
+        pos += h * w
+        ref = oracle.filter(im, sig, s["mode"], cycles=s["cycles"], substeps=10)
+        e = float(np.abs(g - ref).max())
+        r = float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
+        _log(f"batch vs oracle {h}x{w} mode {s['mode']} cycles {s['cycles']}: max-abs {e:.3e} rel-L2 {r:.3e}")
+        assert e <= 2e-4 and r <= 1e-5
