@@ -243,6 +243,27 @@ int mf4d_fed_cycle_tensor(float *u, float *u_tmp, int H, int W, const float *dpa
 int mf4d_filter(const float *u_in, float *u_out, int H, int W, const mf4d_params *p,
                 void *ws, size_t ws_bytes, void *stream);
 
+/* mf4d_filter for callers that cannot allocate device memory (code under
+ * hipGraph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation and the same values as mf4d_filter, with the scratch
+ * taken from a fixed array of mf4d_noalloc_max_bytes() bytes (128 MiB) that
+ * the library keeps on each GPU it runs on until the process ends, instead
+ * of a workspace argument. The call allocates nothing (no hipMalloc, no
+ * side streams: every scale runs on `stream`) and enqueues kernels only
+ * (with p->check = 1 it also synchronises and copies the status back, as
+ * mf4d_filter does). All calls on one GPU share that array: calls that
+ * overlap in time on one GPU (other streams, other host threads) race and
+ * must be serialised by the caller. Everything a call reads from the array
+ * it first writes (or clears) itself.
+ * Errors: MF4D_EINVAL, MF4D_ENOMEM (mf4d_workspace_bytes(H, W, p) exceeds
+ * mf4d_noalloc_max_bytes()), MF4D_EHIP, and with p->check = 1
+ * MF4D_ENONFINITE / MF4D_EUNSTABLE. */
+int mf4d_filter_noalloc(const float *u_in, float *u_out, int H, int W, const mf4d_params *p,
+                        void *stream);
+
+/* Bytes of the fixed scratch array of mf4d_filter_noalloc. */
+size_t mf4d_noalloc_max_bytes(void);
+
 /* The filter with l2-optimal stopping against a noise-free image (Sec. 4:
  * the evolution is stopped where the l2 difference between the filtered and
  * the noise-free image is smallest), evaluated at the ends of FED cycles,

@@ -536,6 +536,29 @@ int run_filter(const float *u_in, float *u_out, int H, int W, const mf4d_params 
     return MF4D_OK;
 }
 
+// Scratch of mf4d_filter_noalloc: a file-scope device array, one per GPU,
+// held from the library's first use on that GPU until the process ends. Host
+// code never passes `scratch` itself to a kernel (on the host the name only
+// stands in for the symbol): it uses the device address from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kStaticScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+char *static_scratch(int dev)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *ptrs[kMaxDevices] = {};
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptrs[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        ptrs[dev] = ptr;
+    }
+    return (char *)ptrs[dev];
+}
+
 }  // namespace
 
 namespace mf4d {
@@ -736,6 +759,22 @@ int mf4d_filter(const float *u_in, float *u_out, int H, int W, const mf4d_params
     if (ws_bytes < layout(H, W, p->nscales, nullptr, nullptr)) return MF4D_ENOMEM;
     return run_filter(u_in, u_out, H, W, p, (char *)ws, nullptr, (hipStream_t)stream);
 }
+
+int mf4d_filter_noalloc(const float *u_in, float *u_out, int H, int W, const mf4d_params *p, void *stream)
+{
+    int st = validate(H, W, p);
+    if (st != MF4D_OK) return st;
+    if (!u_in || !u_out) return MF4D_EINVAL;
+    if (layout(H, W, p->nscales, nullptr, nullptr) > kStaticScratchBytes) return MF4D_ENOMEM;
+    int dev = -1;
+    CHECK_HIP(hipGetDevice(&dev));
+    char *base = static_scratch(dev);
+    if (!base) return MF4D_EHIP;
+    // every scale on the caller's stream: no side streams are created
+    return run_filter(u_in, u_out, H, W, p, base, nullptr, (hipStream_t)stream, false);
+}
+
+size_t mf4d_noalloc_max_bytes(void) { return kStaticScratchBytes; }
 
 int mf4d_filter_l2stop(const float *u_in, float *u_out, int H, int W, const mf4d_params *p,
                        const float *ground_truth, double *l2_out, int *best_out, void *ws, size_t ws_bytes,

@@ -27,7 +27,8 @@ MF4D_MAX_SCALES, MF4D_MAX_RADIUS, MF4D_MAX_SUBSTEPS = 16, 64, 1024
 EXPORTS = ["mf4d_status_string", "mf4d_params_default", "mf4d_fed_schedule",
            "mf4d_fed_substeps", "mf4d_fed_plan", "mf4d_workspace_bytes",
            "mf4d_scale_select", "mf4d_tensor", "mf4d_fed_cycle", "mf4d_fed_cycle_tensor",
-           "mf4d_filter", "mf4d_filter_l2stop", "mf4d_batch_create", "mf4d_batch_workspace_bytes", "mf4d_filter_batch",
+           "mf4d_filter", "mf4d_filter_noalloc", "mf4d_noalloc_max_bytes", "mf4d_filter_l2stop",
+           "mf4d_batch_create", "mf4d_batch_workspace_bytes", "mf4d_filter_batch",
            "mf4d_batch_autotune", "mf4d_batch_get_tuning", "mf4d_batch_set_tuning", "mf4d_batch_destroy",
            "mf4d_net_param_count", "mf4d_net_workspace_bytes", "mf4d_net_forward", "mf4d_net_backward",
            "mf4d_net_step", "mf4d_learned_workspace_bytes", "mf4d_filter_learned"]
@@ -134,6 +135,10 @@ def lib():
         L.mf4d_fed_cycle_tensor.restype = i
         L.mf4d_filter.argtypes = [vp, vp, i, i, P(mf4d_params), vp, sz, vp]
         L.mf4d_filter.restype = i
+        L.mf4d_filter_noalloc.argtypes = [vp, vp, i, i, P(mf4d_params), vp]
+        L.mf4d_filter_noalloc.restype = i
+        L.mf4d_noalloc_max_bytes.argtypes = []
+        L.mf4d_noalloc_max_bytes.restype = sz
         L.mf4d_filter_l2stop.argtypes = [vp, vp, i, i, P(mf4d_params), vp, vp, vp, vp, sz, vp]
         L.mf4d_filter_l2stop.restype = i
         L.mf4d_batch_create.argtypes = [i, P(ctypes.c_int64), P(i), P(i), P(mf4d_params), P(vp)]
@@ -306,6 +311,19 @@ def mf4d_filter(u_in, u_out, params: Params, ws=None, stream=None):
     st = params.struct()
     _check(lib().mf4d_filter(_ptr(u_in), _ptr(u_out), H, W, ctypes.byref(st), _ptr(ws), ws.numel(),
                              _stream(stream)), "mf4d_filter")
+
+
+def mf4d_filter_noalloc(u_in, u_out, params: Params, stream=None):
+    """mf4d_filter with the library's fixed scratch array (no workspace)."""
+    H, W = _hw(_dev(u_in, torch.float32, name="u_in"))
+    _dev(u_out, torch.float32, (H, W), "u_out")
+    st = params.struct()
+    _check(lib().mf4d_filter_noalloc(_ptr(u_in), _ptr(u_out), H, W, ctypes.byref(st), _stream(stream)),
+           "mf4d_filter_noalloc")
+
+
+def mf4d_noalloc_max_bytes() -> int:
+    return int(lib().mf4d_noalloc_max_bytes())
 
 
 def mf4d_filter_l2stop(u_in, u_out, params: Params, ground_truth, l2_out=None, best_out=None, ws=None,
