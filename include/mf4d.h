@@ -281,6 +281,55 @@ int mf4d_filter_l2stop(const float *u_in, float *u_out, int H, int W, const mf4d
                        const float *ground_truth, double *l2_out, int *best_out,
                        void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------ crease extraction */
+
+/* Device workspace bytes of mf4d_creases for an H x W image (0 if invalid). */
+size_t mf4d_creases_workspace_bytes(int H, int W);
+
+/* Creases of an (already filtered) image, Sec. 3.6: the zero contour of
+ * d = det(g | Hg), g and H the gradient and Hessian of u_sigma (sigma =
+ * sigma_d; the Gaussian, symmetric extension and central differences of
+ * the scale stack), by marching squares on the pixel grid: a corner is
+ * inside when d >= 0, crossings are interpolated linearly in d along each
+ * edge, saddle cells are split by the sign of the mean of their corners.
+ * The zero set of d is a superset of the creases; a segment is kept when H,
+ * interpolated likewise, gives both ends the same type -- ridge where its
+ * eigenvalue of larger magnitude is negative, valley where positive, that
+ * magnitude >= strength -- allowed by mode (MF4D_RIDGE / MF4D_VALLEY /
+ * MF4D_BOTH), and the segment runs closer to the eigenvector of the weaker
+ * eigenvalue (at the mean Hessian of its ends) than to the other.
+ *   u         device float32 [H][W].
+ *   seg_out   device float32 [H-1][W-1][2][4]: per cell (x, y) (corners
+ *             (x,y), (x+1,y), (x+1,y+1), (x,y+1); pixel centres at integer
+ *             coordinates, x = column) up to two segments (x0, y0, x1, y1)
+ *             in slots sorted by their first crossed edge (top, right,
+ *             bottom, left); unused slots are zero.
+ *   type_out  device int8 [H-1][W-1][2]: +1 ridge, -1 valley, 0 empty slot.
+ *   count_out device uint32 (nullable): the number of segments is ADDED to it.
+ *   field_out device float32 [6][H][W] (nullable): the planes g_x, g_y, h_xx,
+ *             h_xy, h_yy, d.
+ *   ws        device workspace of mf4d_creases_workspace_bytes(H, W) bytes.
+ * Every slot is written, so the result does not depend on scheduling.
+ * Errors: MF4D_EINVAL (H, W < 3, sigma_d outside (0, 21.3], strength < 0 or
+ * not finite, bad mode, NULL), MF4D_ENOMEM, MF4D_EHIP. */
+int mf4d_creases(const float *u, int H, int W, float sigma_d, float strength, int mode, float *seg_out,
+                 int8_t *type_out, unsigned *count_out, float *field_out, void *ws, size_t ws_bytes,
+                 void *stream);
+
+/* Evaluation of extracted creases against ground-truth segments, Sec. 4:
+ * each ground-truth segment gt[i] = (x0, y0, x1, y1) of type gt_type[i]
+ * (+1 ridge, -1 valley) is matched to the segment of seg / type (as written
+ * by mf4d_creases for an H x W image) of the same type with the least
+ * directed Hausdorff distance from gt[i] (the largest distance of a point of
+ * gt[i] to it), if that distance is at most radius (the neighbourhood: the
+ * paper uses 6 px on synthetic data); ties go to the first cell in row-major
+ * order, then slot 0. dist_out[i] = distance from gt[i]'s midpoint to its
+ * match, -1 if none; match_out[i] = 2 * (y (W-1) + x) + slot, or -1. The mean
+ * of the non-negative distances is the paper's E, their share its p.
+ * All arrays are device memory; n >= 0. Errors: MF4D_EINVAL, MF4D_EHIP. */
+int mf4d_crease_match(const float *seg, const int8_t *type, int H, int W, const float *gt, const int *gt_type,
+                      int n, float radius, float *dist_out, int *match_out, void *stream);
+
 /* ------------------------------------------------------------ batches */
 
 /* A batch plan: many images of different sizes filtered together. Every
@@ -375,10 +424,15 @@ int mf4d_net_step(float *theta, const float *grad, float *adam_m, float *adam_v,
 size_t mf4d_learned_workspace_bytes(int H, int W, const mf4d_params *p);
 
 /* The filter with the network's scale where its confidence reaches
- * conf_threshold (0..1) and the exact argmax of Eq. (9) elsewhere; the exact
- * sweep still runs every cycle, since the normalised Hessian at the chosen
- * scale and the image-wide c need it. conf_threshold = 1 with an unsure
- * network reproduces mf4d_filter. H, W multiples of 16, nscales <= 8,
+ * conf_threshold (0..1) and the exact argmax of Eq. (9) elsewhere. The first
+ * cycle sweeps every scale over every pixel and fixes the image-wide c
+ * (with params c <= 0); the later cycles keep that c and their sweeps skip
+ * the 32 x 32 blocks (in whole workgroups of the sweep: a strip segment) in
+ * which no pixel needs a scale -- a block needs every scale where a pixel is
+ * not confident, and the network's scale where it is (for the normalised
+ * Hessian at that scale). With params c > 0, c is used as given throughout.
+ * conf_threshold = 1 with an unsure network reproduces mf4d_filter for one
+ * cycle (and for more cycles with params c > 0). H, W multiples of 16, nscales <= 8,
  * reselect_each_cycle = 1, model, postprocess and check 0. fallback_count (nullable, device uint32): number
  * of pixel-cycles that fell back to the exact argmax. Errors: MF4D_EINVAL,
  * MF4D_ENOMEM, MF4D_EHIP. */

@@ -117,6 +117,7 @@ def _declare(L):
     L.net_loss.restype = ctypes.c_double
     L.net_grad.argtypes = [_dp, _dp, _u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp]
     L.net_grad.restype = ctypes.c_double
+    L.net_forward_bf16.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp]
 
 
 def _d(a):
@@ -471,6 +472,57 @@ def net_forward(theta, u):
     z = np.zeros((B, 9, H, W))
     lib().net_forward(_d(theta), _d(u), B, H, W, _null(_dp), _d(z))
     return z
+
+
+def net_forward_bf16(theta, u):
+    """The network with BF16 weights, inputs and activations (the library's
+    definition); theta as float32 values. u: [B][H][W]; returns z [B][9][H][W]."""
+    theta = _f64(np.asarray(theta, np.float32))
+    u = _f64(np.asarray(u, np.float32))
+    if u.ndim == 2:
+        u = u[None]
+    B, H, W = u.shape
+    z = np.zeros((B, 9, H, W))
+    lib().net_forward_bf16(_d(theta), _d(np.ascontiguousarray(u)), B, H, W, _d(z))
+    return z
+
+
+def net_decisions(z, ns, thr):
+    """Per pixel of a single image's logits z [9][H][W]: the network's scale
+    (first maximum of the first min(ns, 8) logits) and whether its
+    confidence sigmoid(z_8) reaches thr."""
+    k = min(ns, 8)
+    scale = np.argmax(z[:k], axis=0).astype(np.uint8)
+    conf = 1.0 / (1.0 + np.exp(-z[8]))
+    return scale, conf >= thr, conf
+
+
+def filter_learned(u, theta, sigmas, mode, thr=0.9, lam=0.005, rho=0.5, beta=0.5, c=-1.0, cycles=1,
+                   substeps=10, tau_max=0.05, record=False):
+    """The learned filter: in each cycle the network's scale where its
+    confidence (on the cycle's image) reaches thr, the exact argmax of
+    Eq. (9) elsewhere. With c <= 0 the image-wide c of the first cycle is
+    kept for every later cycle (the learned filter does not sweep every
+    scale over every pixel after the first cycle); c > 0 is used as given.
+    Returns u_out (and per-cycle records: net scale, confident mask, exact
+    selection, indices used, c)."""
+    uk = _f64(u)
+    sig = list(sigmas)
+    recs = []
+    c_held = float(np.float32(c)) if c > 0 else None
+    for k in range(cycles):
+        z = net_forward_bf16(theta, uk.astype(np.float32))[0]
+        ns_, conf_ok, conf = net_decisions(z, len(sig), thr)
+        sel = scale_select(uk, sig, mode, beta=beta, c=c_held if c_held is not None else -1.0)
+        if c_held is None:
+            c_held = sel["c"]
+        idx = np.where(conf_ok, ns_, sel["idx"]).astype(np.uint8)
+        nxt = filter(uk, sig, mode, lam=lam, rho=rho, beta=beta, c=c_held, cycles=1, substeps=substeps,
+                     tau_max=tau_max, idx_inject=idx[None])
+        if record:
+            recs.append(dict(z=z, net=ns_, conf=conf, confident=conf_ok, sel=sel, idx=idx, c=c_held, u_in=uk))
+        uk = nxt
+    return (uk, recs) if record else uk
 
 
 def net_loss(z, label, w_conf=0.1):

@@ -17,16 +17,20 @@
  *    to corner b is a + t (b - a) with t = d_a / (d_a - d_b); saddle cells
  *    (two opposite corners inside) are split by the sign of the mean of the
  *    four corners;
- *  - a crossing is a ridge point when, with n the unit normal of g and
- *    lambda_n = n^T H n, lambda_g = g^T H g / |g|^2 (g and H interpolated
- *    linearly along the edge), lambda_n < 0 and -lambda_n >= |lambda_g|
- *    (the curvature across the crease dominates, as for a tube in Eq. (9);
- *    without it the flanks of a curved crease beyond the inflection points,
- *    where the weak curvature along the crease is the smaller eigenvalue,
- *    pass too) and -lambda_n >= strength; a valley point with the signs
- *    reversed; a
- *    segment is kept when both ends are crease points of one type that the
- *    mode allows (the zero set of d is a superset of the creases);
+ *  - the zero set of d is a superset of the creases: it also holds the lines
+ *    where the gradient along a crease vanishes, which cross the crease,
+ *    and contours in flat regions. A segment is kept as a crease when, with
+ *    H interpolated linearly along each crossed edge, both ends have the
+ *    same type -- ridge where the eigenvalue of larger magnitude is
+ *    negative, valley where it is positive (that eigenvalue's magnitude at
+ *    least `strength`; none for equal eigenvalues) -- which the mode
+ *    allows, and when the segment runs closer to the eigenvector of the
+ *    weaker eigenvalue than to that of the stronger (at the mean of the two
+ *    ends' Hessians), i.e. along the crease. The gradient's own direction
+ *    is not used: the linear interpolation of d places a crossing a tenth
+ *    of a pixel off the crest where the gradient along the crest is weak,
+ *    and there the gradient points across it, while H and the contour's
+ *    direction change slowly;
  *  - segments are stored per cell (x, y), corners (x, y), (x+1, y),
  *    (x+1, y+1), (x, y+1), in two slots sorted by their first edge (edges
  *    0 top, 1 right, 2 bottom, 3 left), ends ordered by edge;
@@ -67,17 +71,28 @@ void ref_crease_field(const double *u, int H, int W, double sigma_d, double *pla
     free(us);
 }
 
-/* Crease type of a point with gradient g and Hessian (a, b, c):
- * +1 ridge, -1 valley, 0 none. */
-static int crease_type(double gx, double gy, double a, double b, double c, double strength)
+/* Crease type of a point with Hessian (a, b, c): +1 ridge (stronger
+ * eigenvalue negative), -1 valley (positive), 0 none (equal magnitudes or
+ * below strength). The stronger eigenvalue is m + r for m > 0 and m - r for
+ * m < 0, with m = (a + c) / 2 and r = sqrt(((a - c) / 2)^2 + b^2). */
+static int crease_type(double a, double b, double c, double strength)
 {
-    double g2 = gx * gx + gy * gy;
-    if (!(g2 > 0.0)) return 0;
-    double ln = (a * gy * gy - 2.0 * b * gx * gy + c * gx * gx) / g2;   /* n = (-gy, gx) / |g| */
-    double lg = (a * gx * gx + 2.0 * b * gx * gy + c * gy * gy) / g2;
-    if (ln < 0.0 && -ln >= fabs(lg) && -ln >= strength) return 1;
-    if (ln > 0.0 && ln >= fabs(lg) && ln >= strength) return -1;
-    return 0;
+    double m = 0.5 * (a + c);
+    double r = sqrt(0.25 * (a - c) * (a - c) + b * b);
+    if (!(r > 0.0) || m == 0.0) return 0;
+    if (fabs(m) + r < strength) return 0;
+    return m < 0.0 ? 1 : -1;
+}
+
+/* Does direction v run closer to the weaker eigenvector of H = (a, b, c)
+ * than to the stronger one? With q = v^T (H - m Id) v, (v.e1)^2 - (v.e2)^2
+ * has the sign of q (e1 the eigenvector of m + r); the stronger one is e1
+ * when m > 0 and e2 when m < 0. */
+static int along_weak(double vx, double vy, double a, double b, double c)
+{
+    double m = 0.5 * (a + c);
+    double q = 0.5 * (a - c) * (vx * vx - vy * vy) + 2.0 * b * vx * vy;
+    return m > 0.0 ? q <= 0.0 : q >= 0.0;
 }
 
 /* Segment edge pairs per inside-pattern (bit k = corner k inside), for the
@@ -113,8 +128,7 @@ long ref_marching_creases(const double *planes, int H, int W, double strength, i
                           double *seg, int8_t *type)
 {
     size_t m = (size_t)H * W;
-    const double *gx = planes, *gy = planes + m, *hxx = planes + 2 * m, *hxy = planes + 3 * m,
-                 *hyy = planes + 4 * m, *d = planes + 5 * m;
+    const double *hxx = planes + 2 * m, *hxy = planes + 3 * m, *hyy = planes + 4 * m, *d = planes + 5 * m;
     long count = 0;
     /* corner k of cell (x, y) and the corners (a, b) of edge e */
     const int cx[4] = {0, 1, 1, 0}, cy[4] = {0, 0, 1, 1};
@@ -139,7 +153,7 @@ long ref_marching_creases(const double *planes, int H, int W, double strength, i
             cell_edges(pat, centre, &ns, e);
             int slot = 0;
             for (int q = 0; q < ns; ++q) {
-                double px[2], py[2];
+                double px[2], py[2], ha[2], hb[2], hc[2];
                 int ty[2];
                 for (int j = 0; j < 2; ++j) {
                     int ed = e[q][j], a = ea[ed], b = eb[ed];
@@ -147,11 +161,15 @@ long ref_marching_creases(const double *planes, int H, int W, double strength, i
                     px[j] = (double)(x + cx[a]) + tt * (double)(cx[b] - cx[a]);
                     py[j] = (double)(y + cy[a]) + tt * (double)(cy[b] - cy[a]);
                     size_t pa = pc[a], pb = pc[b];
-#define LERP(P) (P[pa] + tt * (P[pb] - P[pa]))
-                    ty[j] = crease_type(LERP(gx), LERP(gy), LERP(hxx), LERP(hxy), LERP(hyy), strength);
-#undef LERP
+                    ha[j] = hxx[pa] + tt * (hxx[pb] - hxx[pa]);
+                    hb[j] = hxy[pa] + tt * (hxy[pb] - hxy[pa]);
+                    hc[j] = hyy[pa] + tt * (hyy[pb] - hyy[pa]);
+                    ty[j] = crease_type(ha[j], hb[j], hc[j], strength);
                 }
                 if (ty[0] == 0 || ty[0] != ty[1]) continue;
+                if (!along_weak(px[1] - px[0], py[1] - py[0], 0.5 * (ha[0] + ha[1]), 0.5 * (hb[0] + hb[1]),
+                                0.5 * (hc[0] + hc[1])))
+                    continue;
                 if (mode == 0 && ty[0] != 1) continue;
                 if (mode == 1 && ty[0] != -1) continue;
                 s[4 * slot + 0] = px[0];

@@ -41,6 +41,8 @@ static const double *layer_w(const double *theta, int l)
 static void conv3x3(const double *in, int B, int cin, int H, int W, const double *w, const double *b, int cout,
                     double *out)
 {
+    /* OpenMP only splits the independent output planes */
+    #pragma omp parallel for collapse(2) schedule(static)
     for (int n = 0; n < B; ++n)
         for (int co = 0; co < cout; ++co)
             for (int y = 0; y < H; ++y)
@@ -172,4 +174,49 @@ double net_grad(const double *theta, const double *u, const uint8_t *label, int 
     free(d);
     free(dn);
     return loss;
+}
+
+/* The network as the library defines it for inference (BF16 weights, inputs
+ * and activations): the input, the weights and every layer's activation
+ * (relu of the layer's output rounded to float) are rounded to BF16, round to
+ * nearest even; sums are taken in double, the biases are used as given and
+ * the logits are not rounded. z receives [B][9][H][W]. */
+static double bf16_of(double v)
+{
+    float f = (float)v;
+    uint32_t b;
+    memcpy(&b, &f, sizeof b);
+    b += 0x7fffu + ((b >> 16) & 1u);
+    b &= 0xffff0000u;
+    memcpy(&f, &b, sizeof f);
+    return (double)f;
+}
+
+void net_forward_bf16(const double *theta, const double *u, int B, int H, int W, double *z)
+{
+    size_t m = (size_t)B * H * W;
+    int np = net_param_count();
+    double *th = (double *)malloc(sizeof(double) * (size_t)np);
+    memcpy(th, theta, sizeof(double) * (size_t)np);
+    for (int l = 0; l < 5; ++l) {   /* weights to BF16, biases kept */
+        double *w = th + (layer_w(theta, l) - theta);
+        for (int i = 0; i < NET_C[l + 1] * NET_C[l] * 9; ++i) w[i] = bf16_of(w[i]);
+    }
+    double *a = (double *)malloc(sizeof(double) * m * 32);
+    double *t = (double *)malloc(sizeof(double) * m * 32);
+    for (size_t i = 0; i < m; ++i) a[i] = bf16_of(u[i]);
+    for (int l = 0; l < 5; ++l) {
+        const double *w = th + (layer_w(theta, l) - theta);
+        const double *b = w + NET_C[l + 1] * NET_C[l] * 9;
+        conv3x3(a, B, NET_C[l], H, W, w, b, NET_C[l + 1], l < 4 ? t : z);
+        if (l < 4) {
+            for (size_t i = 0; i < m * 32; ++i) t[i] = bf16_of(t[i] > 0.0 ? t[i] : 0.0);
+            double *s = a;
+            a = t;
+            t = s;
+        }
+    }
+    free(a);
+    free(t);
+    free(th);
 }

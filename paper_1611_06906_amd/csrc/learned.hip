@@ -414,6 +414,27 @@ __global__ __launch_bounds__(256) void learned_select_kernel(const uint8_t *__re
     if (threadIdx.x == 0 && cnt) atomicAdd(fallback + blockIdx.x % kFallbackSlots, cnt);
 }
 
+// one workgroup per 32 x 32 block: the scales its pixels need
+__global__ __launch_bounds__(256) void need_flags_kernel(const uint8_t *__restrict__ sel, int H, int W, int ns,
+                                                         int bx, uint8_t *__restrict__ need)
+{
+    __shared__ unsigned bits;
+    if (threadIdx.x == 0) bits = 0u;
+    __syncthreads();
+    const int x0 = (blockIdx.x % bx) * 32, y0 = (blockIdx.x / bx) * 32;
+    const unsigned all = (1u << ns) - 1u;
+    unsigned m = 0u;
+    for (int i = threadIdx.x; i < 1024; i += 256) {
+        const int x = x0 + (i & 31), y = y0 + (i >> 5);
+        if (x >= W || y >= H) continue;
+        const unsigned code = sel[(size_t)y * W + x];
+        m |= (code & 0x80u) ? (1u << (code & 0x7fu)) : all;
+    }
+    if (m) atomicOr(&bits, m);
+    __syncthreads();
+    if (threadIdx.x == 0) need[blockIdx.x] = (uint8_t)bits;
+}
+
 // the total of the fallback counters
 __global__ void fallback_sum_kernel(const unsigned *__restrict__ slots, unsigned *__restrict__ total)
 {
@@ -551,6 +572,13 @@ size_t net_forward_bytes(int H, int W) { return net::net_layout(1, H, W, false, 
 hipError_t launch_fallback_sum(const unsigned *slots, unsigned *total, hipStream_t s)
 {
     hipLaunchKernelGGL(net::fallback_sum_kernel, dim3(1), dim3(64), 0, s, slots, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_need_flags(const uint8_t *sel, int H, int W, int ns, uint8_t *need, hipStream_t s)
+{
+    const int bx = (W + 31) / 32, by = (H + 31) / 32;
+    hipLaunchKernelGGL(net::need_flags_kernel, dim3(bx * by), dim3(256), 0, s, sel, H, W, ns, bx, need);
     return hipGetLastError();
 }
 

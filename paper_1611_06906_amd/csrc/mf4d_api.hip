@@ -176,6 +176,9 @@ struct Workspace {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// one byte per 32 x 32 block (the learned filter's need bits)
+size_t need_bytes(int H, int W) { return (size_t)((H + 31) / 32) * (size_t)((W + 31) / 32); }
+
 size_t layout(int H, int W, int ns, Workspace *w, char *base)
 {
     const size_t m = (size_t)H * W;
@@ -299,7 +302,8 @@ int run_substeps(const float *u_first, float *const bufs[2], int &launch_index, 
 // (when want_n) and the image-wide maximum of S (cleared first unless
 // clear_max is false: an earlier kernel on the stream has left it at 0).
 int run_sweep(const float *u, int H, int W, const mf4d_params *p, const Workspace &w,
-              bool want_n, hipStream_t s, bool clear_max = true, bool fork = true)
+              bool want_n, hipStream_t s, bool clear_max = true, bool fork = true,
+              const uint8_t *need = nullptr)
 {
     const size_t m = (size_t)H * W;
     if (clear_max) CHECK_HIP(launch_fill_u32(w.smax, 0u, 1, s));
@@ -313,7 +317,7 @@ int run_sweep(const float *u, int H, int W, const mf4d_params *p, const Workspac
     auto launch = [&](int k, hipStream_t st) {
         ScalePlanes planes{w.SA + 2 * k * m, want_n ? w.N + 3 * k * m : nullptr};
         return launch_sweep_scale(u, w.hA, w.hB, w.hC, H, W, taps[k], p->sigmas[k], p->mode, p->beta, planes,
-                                  w.smax, fs != nullptr, st);
+                                  w.smax, fs != nullptr, st, ScaleNeed{need, (W + 31) / 32, k});
     };
     if (!fs) {
         for (int k = 0; k < p->nscales; ++k) CHECK_HIP(launch(k, s));
@@ -788,12 +792,51 @@ int mf4d_filter_l2stop(const float *u_in, float *u_out, int H, int W, const mf4d
     return run_filter(u_in, u_out, H, W, p, (char *)ws, &stop, (hipStream_t)stream);
 }
 
+size_t mf4d_creases_workspace_bytes(int H, int W)
+{
+    if (H < 3 || W < 3 || (long long)H * (long long)W >= (1LL << 31)) return 0;
+    const size_t m = (size_t)H * W;
+    return align256(m * 12) + align256(m * 24);
+}
+
+int mf4d_creases(const float *u, int H, int W, float sigma_d, float strength, int mode, float *seg_out,
+                 int8_t *type_out, unsigned *count_out, float *field_out, void *ws, size_t ws_bytes, void *stream)
+{
+    const size_t need = mf4d_creases_workspace_bytes(H, W);
+    if (!need || !u || !seg_out || !type_out || !ws) return MF4D_EINVAL;
+    if (!(sigma_d > 0.f) || !std::isfinite(sigma_d) || radius_of(sigma_d) > MF4D_MAX_RADIUS) return MF4D_EINVAL;
+    if (!(strength >= 0.f) || !std::isfinite(strength)) return MF4D_EINVAL;
+    if (mode < MF4D_RIDGE || mode > MF4D_BOTH) return MF4D_EINVAL;
+    if (ws_bytes < need) return MF4D_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t m = (size_t)H * W;
+    float *hA = (float *)ws;
+    float *planes = field_out ? field_out : (float *)((char *)ws + align256(m * 12));
+    WinTaps t;
+    make_taps(sigma_d, &t);
+    CHECK_HIP(launch_hpass(u, hA, hA + m, hA + 2 * m, H, W, t, s));
+    CHECK_HIP(launch_crease_field(hA, hA + m, hA + 2 * m, H, W, t, planes, s));
+    CHECK_HIP(launch_marching(planes, H, W, strength, mode, seg_out, type_out, count_out, s));
+    return MF4D_OK;
+}
+
+int mf4d_crease_match(const float *seg, const int8_t *type, int H, int W, const float *gt, const int *gt_type, int n,
+                      float radius, float *dist_out, int *match_out, void *stream)
+{
+    if (H < 3 || W < 3 || (long long)H * (long long)W >= (1LL << 31) || n < 0) return MF4D_EINVAL;
+    if (!(radius >= 0.f) || !std::isfinite(radius)) return MF4D_EINVAL;
+    if (n == 0) return MF4D_OK;
+    if (!seg || !type || !gt || !gt_type || !dist_out || !match_out) return MF4D_EINVAL;
+    CHECK_HIP(launch_crease_match(seg, type, H, W, gt, gt_type, n, radius, dist_out, match_out, (hipStream_t)stream));
+    return MF4D_OK;
+}
+
 size_t mf4d_learned_workspace_bytes(int H, int W, const mf4d_params *p)
 {
     if (validate(H, W, p) != MF4D_OK || p->nscales > 8 || H % 16 != 0 || W % 16 != 0) return 0;
     if (p->model != MF4D_MAFOD || p->postprocess != 0 || p->check != 0) return 0;
     return align256(layout(H, W, p->nscales, nullptr, nullptr)) + align256(net_forward_bytes(H, W)) +
-           sizeof(unsigned) * kFallbackSlots;
+           align256(sizeof(unsigned) * kFallbackSlots) + align256(need_bytes(H, W));
 }
 
 int mf4d_filter_learned(const float *u_in, float *u_out, int H, int W, const mf4d_params *p, const float *theta,
@@ -804,14 +847,14 @@ int mf4d_filter_learned(const float *u_in, float *u_out, int H, int W, const mf4
     if (!u_in || !u_out || !theta || !ws || p->nscales > 8 || H % 16 != 0 || W % 16 != 0) return MF4D_EINVAL;
     if (!(conf_threshold >= 0.f) || conf_threshold > 1.f || p->reselect_each_cycle != 1) return MF4D_EINVAL;
     if (p->model != MF4D_MAFOD || p->postprocess != 0 || p->check != 0) return MF4D_EINVAL;
-    const size_t need = mf4d_learned_workspace_bytes(H, W, p);
-    if (ws_bytes < need) return MF4D_ENOMEM;
+    if (ws_bytes < mf4d_learned_workspace_bytes(H, W, p)) return MF4D_ENOMEM;
     hipStream_t s = (hipStream_t)stream;
     const size_t m = (size_t)H * W;
     char *base = (char *)ws;
     const size_t img_bytes = align256(layout(H, W, p->nscales, nullptr, nullptr));
     char *net_ws = base + img_bytes;
     unsigned *fb = (unsigned *)(net_ws + align256(net_forward_bytes(H, W)));   // kFallbackSlots counters
+    uint8_t *need = (uint8_t *)fb + align256(sizeof(unsigned) * kFallbackSlots);
     CHECK_HIP(launch_fill_u32(fb, 0u, kFallbackSlots, s));
     if (p->cycles == 0) {
         if (u_in != u_out) CHECK_HIP(launch_copy_f32(u_in, u_out, m, s));
@@ -842,14 +885,20 @@ int mf4d_filter_learned(const float *u_in, float *u_out, int H, int W, const mf4
     SelectArgs a = select_args(p, w);
     a.coef = w.tens;
     a.idx_out = w.idx;
+    // the image-wide c of the first cycle, kept for the later ones (their
+    // sweeps skip blocks where the network decides)
+    unsigned *held = w.smax + 1;
+    a.smax_bits = held;
     int li = 0;
     for (int k = 0; k < p->cycles; ++k) {
         const uint8_t *sel = nullptr;
         st = net_select_into(theta, src, H, W, net_ws, s, conf_threshold, p->nscales, &sel,
                              k == 0);   // weights packed once per call
         if (st != MF4D_OK) return st;
-        st = run_sweep(src, H, W, p, w, true, s);
+        if (k > 0) CHECK_HIP(launch_need_flags(sel, H, W, p->nscales, need, s));
+        st = run_sweep(src, H, W, p, w, true, s, true, true, k > 0 ? need : nullptr);
         if (st != MF4D_OK) return st;
+        if (k == 0) CHECK_HIP(launch_copy_f32((const float *)w.smax, (float *)held, 1, s));
         CHECK_HIP(launch_learned_select(sel, a, H, W, fb, s));
         CHECK_HIP(launch_rho(a, H, W, s));
         st = run_substeps(src, bufs, li, w.tens, H, W, tau32.data(), n, spl, s, &src);

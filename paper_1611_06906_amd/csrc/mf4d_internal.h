@@ -60,11 +60,20 @@ int sweep_chunks(const WinTaps &t);
 // kernel's LDS), or the register-window kernels.
 enum { kSweepFused = 0, kSweepSplit = 1, kSweepValu = 2 };
 int sweep_engine(const WinTaps &t);
+// Which 32 x 32 blocks (the fused sweep's strip width and step) need a
+// scale: bit `scale` of bits[by * bx + bx_index]; bits == nullptr: all.
+struct ScaleNeed {
+    const uint8_t *bits;
+    int bx;
+    int scale;
+};
 // Both passes of one scale (the planes hA, hB, hC are used by the split and
-// register-window forms only); `shared`: other scales run concurrently.
+// register-window forms only); `shared`: other scales run concurrently. The
+// fused kernel skips workgroups whose blocks do not need the scale (the
+// other forms compute every block).
 hipError_t launch_sweep_scale(const float *u, float *hA, float *hB, float *hC, int H, int W, const WinTaps &t,
                               float sigma, int mode, float beta, ScalePlanes out, unsigned *smax_bits, bool shared,
-                              hipStream_t s);
+                              hipStream_t s, ScaleNeed need = ScaleNeed{nullptr, 0, 0});
 // Rows per workgroup of the single-image fused kernel (MF4D_VSEG_ROWS
 // overrides it; values do not change). `shared`: other scales run concurrently.
 int fused_seg_rows(int H, int W, int nc, bool shared);
@@ -132,6 +141,10 @@ size_t net_forward_bytes(int H, int W);
 constexpr int kFallbackSlots = 64;
 hipError_t launch_learned_select(const uint8_t *sel, const SelectArgs &a, int H, int W, unsigned *fallback,
                                  hipStream_t s);
+// Need bits of the learned selection: a 32 x 32 block needs scale s when one
+// of its pixels is not confident (the exact argmax reads every scale there)
+// or the network chose s for it. need: [ceil(H/32)][ceil(W/32)] bytes.
+hipError_t launch_need_flags(const uint8_t *sel, int H, int W, int ns, uint8_t *need, hipStream_t s);
 hipError_t launch_fallback_sum(const unsigned *slots, unsigned *total, hipStream_t s);
 
 // ------------------------------------------------------------ aux_kernels.hip
@@ -161,5 +174,15 @@ hipError_t launch_ifod_coef(const float *A, const float *B, const float *C, int 
                             float inv_lam2, float *coef, float *hess, hipStream_t s);
 hipError_t launch_postprocess(const uint8_t *idx, const float *vmax, const float *N, int ns, int H, int W,
                               const ScaleTable &sig, float theta, int tmax, uint8_t *out, hipStream_t s);
+
+// ---------------------------------------------------------- crease_kernels.hip
+// planes [6][H][W]: g_x, g_y, h_xx, h_xy, h_yy, d = det(g | Hg) of u_sigma,
+// from the horizontal planes of one scale
+hipError_t launch_crease_field(const float *A, const float *B, const float *C, int H, int W, const WinTaps &t,
+                               float *planes, hipStream_t s);
+hipError_t launch_marching(const float *planes, int H, int W, float strength, int mode, float *seg, int8_t *type,
+                           unsigned *count, hipStream_t s);
+hipError_t launch_crease_match(const float *seg, const int8_t *type, int H, int W, const float *gt, const int *gt_type,
+                               int n, float radius, float *dist, int *match, hipStream_t s);
 
 }  // namespace mf4d

@@ -68,13 +68,22 @@ __global__ __launch_bounds__(256, 2) void sweep_fused_kernel(const float *__rest
                                                           float sigma2, float inv2beta2, int mode,
                                                           float *__restrict__ SA, float *__restrict__ No,
                                                           unsigned *__restrict__ smax_bits,
-                                                          int segs, int seg_rows, int nblk, int per_xcd)
+                                                          int segs, int seg_rows, int nblk, int per_xcd,
+                                                          ScaleNeed need)
 {
     extern __shared__ f4 lds4[];
     const int b = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (b >= nblk) return;
     const int strip = b / segs, seg = b - strip * segs;
     const int ys = seg * seg_rows, ye = min(H, ys + seg_rows);
+    if (need.bits) {
+        // a workgroup none of whose 32 x 32 blocks needs this scale has nothing
+        // to compute (the same decision for every thread)
+        bool any = false;
+        for (int by = ys / kVMStep; by * kVMStep < ye; ++by)
+            any = any || ((need.bits[by * need.bx + strip] >> need.scale) & 1);
+        if (!any) return;
+    }
     const float v = sweep_fused_tile<NC>(u, H, W, t, sigma2, inv2beta2, mode, SA, No, strip * kVMW, ys, ye,
                                          (float *)lds4);
     block_max_to(v, smax_bits);
@@ -169,7 +178,7 @@ int fused_seg_rows(int H, int W, int nc, bool shared)
 
 hipError_t launch_sweep_scale(const float *u, float *hA, float *hB, float *hC, int H, int W, const WinTaps &t,
                               float sigma, int mode, float beta, ScalePlanes out, unsigned *smax_bits, bool shared,
-                              hipStream_t s)
+                              hipStream_t s, ScaleNeed need)
 {
     if (sweep_engine(t) != kSweepFused) {
         hipError_t e = launch_hpass(u, hA, hB, hC, H, W, t, s);
@@ -186,7 +195,7 @@ hipError_t launch_sweep_scale(const float *u, float *hA, float *hB, float *hC, i
 #define MF4D_FU(NC)                                                                                           \
     case NC:                                                                                                  \
         hipLaunchKernelGGL(sweep_fused_kernel<NC>, dim3(8 * per), dim3(256), fused_lds(NC), s, u, H, W, t, sigma2, \
-                           inv2beta2, mode, out.SA, out.N, smax_bits, segs, seg_rows, nblk, per);      \
+                           inv2beta2, mode, out.SA, out.N, smax_bits, segs, seg_rows, nblk, per, need); \
         break;
         MF4D_FU(2) MF4D_FU(3) MF4D_FU(4) MF4D_FU(5) MF4D_FU(6) MF4D_FU(7) MF4D_FU(8)
 #undef MF4D_FU

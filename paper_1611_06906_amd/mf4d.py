@@ -28,7 +28,7 @@ EXPORTS = ["mf4d_status_string", "mf4d_params_default", "mf4d_fed_schedule",
            "mf4d_fed_substeps", "mf4d_fed_plan", "mf4d_workspace_bytes",
            "mf4d_scale_select", "mf4d_tensor", "mf4d_fed_cycle", "mf4d_fed_cycle_tensor",
            "mf4d_filter", "mf4d_filter_noalloc", "mf4d_noalloc_max_bytes", "mf4d_filter_l2stop",
-           "mf4d_batch_create", "mf4d_batch_workspace_bytes", "mf4d_filter_batch",
+           "mf4d_creases_workspace_bytes", "mf4d_creases", "mf4d_crease_match", "mf4d_batch_create", "mf4d_batch_workspace_bytes", "mf4d_filter_batch",
            "mf4d_batch_autotune", "mf4d_batch_get_tuning", "mf4d_batch_set_tuning", "mf4d_batch_destroy",
            "mf4d_net_param_count", "mf4d_net_workspace_bytes", "mf4d_net_forward", "mf4d_net_backward",
            "mf4d_net_step", "mf4d_learned_workspace_bytes", "mf4d_filter_learned"]
@@ -141,6 +141,12 @@ def lib():
         L.mf4d_noalloc_max_bytes.restype = sz
         L.mf4d_filter_l2stop.argtypes = [vp, vp, i, i, P(mf4d_params), vp, vp, vp, vp, sz, vp]
         L.mf4d_filter_l2stop.restype = i
+        L.mf4d_creases_workspace_bytes.argtypes = [i, i]
+        L.mf4d_creases_workspace_bytes.restype = sz
+        L.mf4d_creases.argtypes = [vp, i, i, ctypes.c_float, ctypes.c_float, i, vp, vp, vp, vp, vp, sz, vp]
+        L.mf4d_creases.restype = i
+        L.mf4d_crease_match.argtypes = [vp, vp, i, i, vp, vp, i, ctypes.c_float, vp, vp, vp]
+        L.mf4d_crease_match.restype = i
         L.mf4d_batch_create.argtypes = [i, P(ctypes.c_int64), P(i), P(i), P(mf4d_params), P(vp)]
         L.mf4d_batch_create.restype = i
         L.mf4d_batch_workspace_bytes.argtypes = [vp]
@@ -343,6 +349,51 @@ def mf4d_filter_l2stop(u_in, u_out, params: Params, ground_truth, l2_out=None, b
     _check(lib().mf4d_filter_l2stop(_ptr(u_in), _ptr(u_out), H, W, ctypes.byref(st), _ptr(ground_truth),
                                     _ptr(l2_out), _ptr(best_out), _ptr(ws), ws.numel(), _stream(stream)),
            "mf4d_filter_l2stop")
+
+
+# ------------------------------------------------------------ creases
+def mf4d_creases(u, sigma_d=1.0, strength=0.0, mode=MF4D_BOTH, seg_out=None, type_out=None, count_out=None,
+                 field_out=None, ws=None, stream=None):
+    """Crease segments of an image (Sec. 3.6). Returns (seg [H-1][W-1][2][4]
+    float32, type [H-1][W-1][2] int8) device tensors."""
+    H, W = _hw(_dev(u, torch.float32, name="u"))
+    if seg_out is None:
+        seg_out = torch.empty((H - 1, W - 1, 2, 4), dtype=torch.float32, device=u.device)
+    if type_out is None:
+        type_out = torch.empty((H - 1, W - 1, 2), dtype=torch.int8, device=u.device)
+    _dev(seg_out, torch.float32, (H - 1, W - 1, 2, 4), "seg_out")
+    _dev(type_out, torch.int8, (H - 1, W - 1, 2), "type_out")
+    _dev(count_out, torch.int32, (1,), "count_out")
+    _dev(field_out, torch.float32, (6, H, W), "field_out")
+    if ws is None:
+        nb = int(lib().mf4d_creases_workspace_bytes(H, W))
+        if nb == 0:
+            raise MF4DError(MF4D_EINVAL, "mf4d_creases_workspace_bytes")
+        ws = torch.empty(nb, dtype=torch.uint8, device=u.device)
+    _check(lib().mf4d_creases(_ptr(u), H, W, float(sigma_d), float(strength), int(mode), _ptr(seg_out),
+                              _ptr(type_out), _ptr(count_out), _ptr(field_out), _ptr(ws), ws.numel(),
+                              _stream(stream)), "mf4d_creases")
+    return seg_out, type_out
+
+
+def mf4d_crease_match(seg, typ, gt, gt_type, radius=6.0, dist_out=None, match_out=None, stream=None):
+    """Matches ground-truth segments gt [n][4] (types gt_type [n]) to the
+    extracted segments (Sec. 4). Returns (dist [n] float32, match [n] int32)."""
+    _dev(seg, torch.float32, name="seg")
+    if seg.dim() != 4 or tuple(seg.shape[2:]) != (2, 4):
+        raise ValueError("seg must be [H-1][W-1][2][4]")
+    H, W = int(seg.shape[0]) + 1, int(seg.shape[1]) + 1
+    _dev(typ, torch.int8, (H - 1, W - 1, 2), "type")
+    n = int(gt.shape[0]) if gt.dim() == 2 else 0
+    _dev(gt, torch.float32, (n, 4), "gt")
+    _dev(gt_type, torch.int32, (n,), "gt_type")
+    if dist_out is None:
+        dist_out = torch.empty(n, dtype=torch.float32, device=seg.device)
+    if match_out is None:
+        match_out = torch.empty(n, dtype=torch.int32, device=seg.device)
+    _check(lib().mf4d_crease_match(_ptr(seg), _ptr(typ), H, W, _ptr(gt), _ptr(gt_type), n, float(radius),
+                                   _ptr(dist_out), _ptr(match_out), _stream(stream)), "mf4d_crease_match")
+    return dist_out, match_out
 
 
 # ------------------------------------------------------------------ batches

@@ -122,16 +122,23 @@ def test_training_reduces_loss_on_exact_labels(env):
 
 
 def test_learned_filter_extremes(env):
-    """threshold 1 with an unsure net is the exact filter (bitwise); threshold 0
-    uses the net's scale everywhere and every pixel-cycle is counted."""
+    """threshold 1 with an unsure net is the exact filter (bitwise) with c
+    fixed at the first cycle's value, which the learned filter keeps;
+    threshold 0 uses the net's scale everywhere and every pixel-cycle is
+    counted."""
     m, torch, synth = env["m"], env["torch"], env["synth"]
     sig = [8.0 ** (k / 7.0) for k in range(8)]
     H, W = 96, 112
     u = synth.fundus(H, W, seed=3)
     p = m.Params(sig, mode=1, cycles=3, substeps=6)
     ui = torch.from_numpy(u).to(env["dev"])
+    idx = torch.empty((H, W), dtype=torch.uint8, device=env["dev"])
+    c0 = torch.empty(1, dtype=torch.float32, device=env["dev"])
+    m.mf4d_scale_select(ui, p, idx, None, c0)
+    torch.cuda.synchronize()
+    pc = m.Params(sig, mode=1, cycles=3, substeps=6, c=float(c0.item()))
     ref = torch.empty_like(ui)
-    m.mf4d_filter(ui, ref, p)
+    m.mf4d_filter(ui, ref, pc)
     th = m.net_init(7, env["dev"]) * 1e-3   # logits ~ 0: confidence ~ 0.5 everywhere
     out = torch.empty_like(ui)
     fb = torch.zeros(1, dtype=torch.int32, device=env["dev"])
@@ -144,3 +151,83 @@ def test_learned_filter_extremes(env):
     assert int(fb.item()) == 0
     assert torch.isfinite(out).all()
     assert abs(float(out.double().mean()) - float(ui.double().mean())) <= 1e-6   # mass is conserved
+
+
+LOGIT_09 = float(np.log(9.0))   # sigmoid(z) >= 0.9
+
+
+def _theta_with_confidence_split(env, seed, u):
+    """Seeded parameters whose confidence-logit bias puts the 0.9 threshold at
+    the median confidence logit the oracle's network gives on u, so that
+    about half of the pixels are confident (the oracle alone decides it)."""
+    o, torch = env["o"], env["torch"]
+    th_host, _ = _theta(env, seed)
+    z = o.net_forward_bf16(th_host, u)[0]
+    ch = o.NET_CHANNELS
+    nparam = sum(ci * co * 9 + co for ci, co in zip(ch[:-1], ch[1:]))
+    bias8 = nparam - 9 + 8            # last layer's bias of output 8
+    th_host = th_host.copy()
+    th_host[bias8] = np.float32(th_host[bias8] + (LOGIT_09 - np.median(z[8])))
+    return th_host, torch.from_numpy(th_host).to(env["dev"])
+
+
+def test_learned_filter_vs_oracle(env):
+    """The learned filter at the 0.9 threshold against the oracle's learned
+    filter (the network with BF16 weights, inputs and activations in FP64
+    sums; the exact argmax of Eq. (9) elsewhere; c kept from the first
+    cycle), on a fundus-type image with 8 scales, 3 cycles of 8 substeps.
+
+    The network's decisions are near-ties where the oracle's confidence
+    logit lies within eps of the threshold or its two largest scale logits
+    within eps of each other (eps: 4x the largest logit difference the
+    forward pass shows on the cycle-0 image); the exact argmax's as in the
+    plain filter. A decision that differs there perturbs the image within
+    the reach of the later substeps (G_rho radius + 2 px per substep for
+    every remaining cycle); outside it the image tolerance holds."""
+    from scipy import ndimage
+    m, o, torch, synth = env["m"], env["o"], env["torch"], env["synth"]
+    sig = [8.0 ** (k / 7.0) for k in range(8)]
+    H, W = 128, 160
+    u = synth.fundus(H, W, seed=11)
+    th_host, th = _theta_with_confidence_split(env, 3, u)
+    # logits of the GPU's forward pass against the oracle's, to size eps
+    logits = torch.empty((H * W, 16), dtype=torch.float32, device=env["dev"])
+    m.mf4d_net_forward(th, torch.from_numpy(u).to(env["dev"]), logits)
+    torch.cuda.synchronize()
+    zg = logits.cpu().numpy()[:, :9].T.reshape(9, H, W).astype(np.float64)
+    zo = o.net_forward_bf16(th_host, u)[0]
+    dz = float(np.abs(zg - zo).max())
+    eps = 4 * dz + 1e-6
+    cycles, n = 3, 8
+    p = m.Params(sig, mode=1, cycles=cycles, substeps=n)
+    ui = torch.from_numpy(u).to(env["dev"])
+    out = torch.empty_like(ui)
+    fb = torch.zeros(1, dtype=torch.int32, device=env["dev"])
+    m.mf4d_filter_learned(ui, out, p, th, 0.9, fb)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    ref, recs = o.filter_learned(u, th_host, sig, 1, thr=0.9, cycles=cycles, substeps=n, record=True)
+    near = np.zeros((H, W), bool)
+    unconf = 0
+    for k, r in enumerate(recs):
+        z = r["z"]
+        top = np.sort(z[:8], axis=0)
+        frag = np.abs(z[8] - LOGIT_09) <= eps
+        frag |= r["confident"] & (top[-1] - top[-2] <= eps)
+        V = r["sel"]["V"]
+        vmax = V.max(axis=0)
+        ties = (V >= vmax - (1e-5 + 1e-4 * vmax)).sum(axis=0) > 1
+        frag |= ~r["confident"] & ties
+        reach = 2 + 2 * n * (cycles - k)
+        if frag.any():
+            near |= ndimage.maximum_filter(frag.astype(np.uint8), size=2 * reach + 1) > 0
+        unconf += int((~r["confident"]).sum())
+    d = np.abs(got - ref)
+    far = float(d[~near].max()) if (~near).any() else 0.0
+    rel = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    conf_share = 1 - unconf / (cycles * H * W)
+    _log(f"learned vs oracle: logit eps {eps:.2e}; confident share {conf_share:.3f}; fallback GPU {int(fb.item())} "
+         f"oracle {unconf}; max-abs {d.max():.3e}, outside {int(near.sum())} near-tie px {far:.3e}; rel-L2 {rel:.3e}")
+    assert 0.2 < conf_share < 0.8
+    assert far <= 2e-4
+    assert abs(int(fb.item()) - unconf) <= max(8, int(0.01 * unconf))
