@@ -99,15 +99,10 @@ def counter_traffic(kernel, row=None):
     return None
 
 
-# kernels of rows a2-a4 in the counter summary (rows of one cycle)
-SELECTION_ROWS = ["sweep_fused_kernel<2>", "sweep_fused_kernel<3>", "sweep_fused_kernel<4>",
-                  "sweep_fused_kernel<5>", "sweep_fused_kernel<6>", "sweep_fused_kernel<7>",
-                  "sweep_fused_kernel<8>", "argmax_kernel", "rho_blur_kernel<2>"]
-
-
 def selection_traffic():
     """HBM bytes of one cycle's scale sweep, argmax and integration from the
-    committed counter summary (per-cycle rows), or None if absent or stale."""
+    committed counter summary: the sum of per_cycle x (read_MB + write_MB)
+    over its rows of stage "sel", or None if absent or stale."""
     prof = os.path.join(ROOT, "profiles", "creases4096_hbm_counters.txt")
     try:
         text = open(prof).read()
@@ -116,22 +111,18 @@ def selection_traffic():
         return None
     if f"sweep_fused_kernel<8> sources sha256 prefix: {digest}" not in text:
         return None
-    total = 0.0
-    for row in SELECTION_ROWS:
-        found = None
-        for line in text.splitlines():
-            if "sha256" in line or not (line.startswith(row + " ") or line.startswith("void " + row + " ")):
-                continue
-            nums = [c for c in line.split() if c.replace(".", "", 1).isdigit()]
-            try:
-                found = (float(nums[3]) + float(nums[4])) * 1e6
-            except (IndexError, ValueError):
-                found = None
-            break
-        if found is None:
+    total, rows = 0.0, 0
+    for line in text.splitlines():
+        cols = line.split()
+        if "sha256" in line or " sel " not in line or not cols or "_kernel" not in cols[0]:
+            continue
+        nums = [c for c in cols if c.replace(".", "", 1).isdigit()]
+        try:   # n, FETCH_KiB, WRITE_KiB, read_MB, write_MB, per_cycle, ...
+            total += int(nums[5]) * (float(nums[3]) + float(nums[4])) * 1e6
+            rows += 1
+        except (IndexError, ValueError):
             return None
-        total += found
-    return total
+    return total if rows else None
 
 
 def _events(torch):

@@ -25,7 +25,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mf4d_oracle.c")
-_SRCS = [_SRC, os.path.join(_HERE, "net_oracle.c"), os.path.join(_HERE, "crease_oracle.c")]
+_SRCS = [_SRC, os.path.join(_HERE, "net_oracle.c"), os.path.join(_HERE, "crease_oracle.c"),
+         os.path.join(_HERE, "mf4d3d_oracle.c")]
 _LIB = os.path.join(_HERE, "libmf4d_oracle.so")
 
 RIDGE, VALLEY, BOTH = 0, 1, 2
@@ -117,6 +118,23 @@ def _declare(L):
     L.net_loss.restype = ctypes.c_double
     L.net_grad.argtypes = [_dp, _dp, _u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp]
     L.net_grad.restype = ctypes.c_double
+    i_ = ctypes.c_int
+    L.ref3_blur.argtypes = [_dp, i_, i_, i_, ctypes.c_double, _dp]
+    L.ref3_derivatives.argtypes = [_dp, i_, i_, i_, _dp]
+    L.ref3_eig.argtypes = [_dp, _dp, _dp]
+    L.ref3_vesselness_px.argtypes = [_dp, ctypes.c_double, i_, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     _dp]
+    L.ref3_vesselness_px.restype = ctypes.c_double
+    L.ref3_scale_select.argtypes = [_dp, i_, i_, i_, i_, _dp, i_, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, _u8p, _dp, _dp]
+    L.ref3_tensor.argtypes = [_dp, i_, i_, i_, _u8p, i_, _dp, ctypes.c_double, _dp]
+    L.ref3_dtensor_px.argtypes = [_dp, ctypes.c_double, i_, _dp, _dp]
+    L.ref3_dtensor.argtypes = [_dp, i_, i_, i_, ctypes.c_double, i_, _dp]
+    L.ref3_apply_P.argtypes = [_dp, _dp, i_, i_, i_, _dp]
+    L.ref3_fed_cycle.argtypes = [_dp, _dp, i_, i_, i_, _dp, i_]
+    L.ref3_filter.argtypes = [_dp, _dp, i_, i_, i_, i_, _dp, i_, ctypes.c_double, ctypes.c_double,
+                              ctypes.c_double, ctypes.c_double, ctypes.c_double, i_, i_, ctypes.c_double, _u8p,
+                              _dp]
     L.net_forward_bf16.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp]
 
 
@@ -366,6 +384,109 @@ def scale_select_postprocessed(u, sigmas, mode, theta, beta=0.5, c=-1.0):
     sel["ex"], sel["ey"] = ex, ey
     sel["idx"] = postprocess(sel["idx_raw"], sel["vmax"], ex, ey, sigmas, theta)
     return sel
+
+
+# ------------------------------------------------------------------ 3-D
+ALPHA3 = 0.5   # Frangi's tube/plate parameter of the 3-D measure (with beta = 0.5)
+
+
+def blur3(u, sigma):
+    u = _f64(u)
+    D, H, W = u.shape
+    out = np.zeros_like(u)
+    lib().ref3_blur(_d(u), D, H, W, float(np.float32(sigma)), _d(out))
+    return out
+
+
+def derivatives3(v):
+    """(g_x, g_y, g_z, h_xx, h_yy, h_zz, h_xy, h_xz, h_yz) of a smoothed volume."""
+    v = _f64(v)
+    D, H, W = v.shape
+    out = np.zeros((9, D, H, W))
+    lib().ref3_derivatives(_d(v), D, H, W, _d(out))
+    return out
+
+
+def eig3(A):
+    """Jacobi eigen-decomposition of a symmetric 3x3: (descending values, vectors as columns)."""
+    A = _f64(A).reshape(3, 3)
+    ev, V = np.zeros(3), np.zeros((3, 3))
+    lib().ref3_eig(_d(np.ascontiguousarray(A)), _d(ev), _d(V))
+    return ev, V
+
+
+def vesselness3_px(h6, sigma, mode, c, beta=0.5, alpha=ALPHA3):
+    S = np.zeros(1)
+    v = lib().ref3_vesselness_px(_d(_f64(h6)), float(np.float32(sigma)), int(mode), float(alpha), float(beta),
+                                 float(c), _d(S))
+    return v, float(S[0])
+
+
+def scale_select3(u, sigmas, mode, beta=0.5, c=-1.0, alpha=ALPHA3):
+    u = _f64(u)
+    D, H, W = u.shape
+    sig = _f64(np.asarray(sigmas, np.float32))
+    idx = np.zeros((D, H, W), np.uint8)
+    V = np.zeros((len(sig), D, H, W))
+    cc = np.zeros(1)
+    lib().ref3_scale_select(_d(u), D, H, W, len(sig), _d(sig), int(mode), float(alpha), float(np.float32(beta)),
+                            float(np.float32(c)), idx.ctypes.data_as(_u8p), _d(V), _d(cc))
+    return dict(idx=idx, V=V, c=float(cc[0]))
+
+
+def tensor3(u, idx, sigmas, rho=0.5):
+    """H_rho planes (xx, yy, zz, xy, xz, yz)."""
+    u = _f64(u)
+    D, H, W = u.shape
+    sig = _f64(np.asarray(sigmas, np.float32))
+    idx = np.ascontiguousarray(idx, np.uint8)
+    out = np.zeros((6, D, H, W))
+    lib().ref3_tensor(_d(u), D, H, W, idx.ctypes.data_as(_u8p), len(sig), _d(sig), float(np.float32(rho)), _d(out))
+    return out
+
+
+def dtensor3_px(h6, lam, mode):
+    Dm, mu = np.zeros(81), np.zeros(3)
+    lib().ref3_dtensor_px(_d(_f64(h6)), float(lam), int(mode), _d(Dm), _d(mu))
+    return Dm.reshape(9, 9), mu
+
+
+def dtensor3(hrho, lam, mode):
+    hrho = _f64(hrho)
+    _, D, H, W = hrho.shape
+    out = np.zeros((D, H, W, 81))
+    lib().ref3_dtensor(_d(hrho), D, H, W, float(lam), int(mode), _d(out))
+    return out
+
+
+def apply_P3(u, Dall):
+    u = _f64(u)
+    D, H, W = u.shape
+    r = np.zeros_like(u)
+    lib().ref3_apply_P(_d(u), _d(_f64(Dall)), D, H, W, _d(r))
+    return r
+
+
+def fed_cycle3(u, Dall, taus):
+    u = _f64(u).copy()
+    D, H, W = u.shape
+    t = _f64(taus)
+    lib().ref3_fed_cycle(_d(u), _d(_f64(Dall)), D, H, W, _d(t), len(t))
+    return u
+
+
+def filter3(u, sigmas, mode, lam=0.005, rho=0.5, beta=0.5, c=-1.0, cycles=1, substeps=10, tau_max=1.0 / 27.0,
+            alpha=ALPHA3, record=False):
+    u = _f64(u)
+    D, H, W = u.shape
+    sig = _f64(np.asarray(sigmas, np.float32))
+    out = np.zeros_like(u)
+    idx_rec = np.zeros((cycles, D, H, W), np.uint8)
+    c_rec = np.zeros(max(cycles, 1))
+    lib().ref3_filter(_d(u), _d(out), D, H, W, len(sig), _d(sig), int(mode), float(np.float32(lam)),
+                      float(np.float32(rho)), float(alpha), float(np.float32(beta)), float(np.float32(c)),
+                      int(cycles), int(substeps), float(tau_max), idx_rec.ctypes.data_as(_u8p), _d(c_rec))
+    return (out, dict(idx=idx_rec, c=c_rec[:cycles])) if record else out
 
 
 # ------------------------------------------------------ crease extraction
