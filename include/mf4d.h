@@ -330,6 +330,81 @@ int mf4d_creases(const float *u, int H, int W, float sigma_d, float strength, in
 int mf4d_crease_match(const float *seg, const int8_t *type, int H, int W, const float *gt, const int *gt_type,
                       int n, float radius, float *dist_out, int *match_out, void *stream);
 
+/* ------------------------------------------------------------ volumes */
+
+/* The filter on volumes, the 3-D extension the paper names as its next step
+ * (Sec. 5), with every definition of the 2-D filter carried to three axes:
+ *  - volumes are float32 [D][H][W] on the device, x fastest, unit spacing;
+ *    D, H, W >= 3, D <= 65535, D H W < 2^31;
+ *  - scale selection: the Hessian of u_sigma (separable Gaussian, central
+ *    differences, the cross stencil of Sec. 3.4 in each coordinate plane for
+ *    the mixed terms, symmetric extension) scaled by sigma^2, with
+ *    eigenvalues n1, n2, n3 by ascending magnitude; Frangi's tube measure
+ *    V = (1 - exp(-R_A^2 / 2 alpha^2)) exp(-R_B^2 / 2 beta^2)
+ *    (1 - exp(-S^2 / 2 c^2)) with R_A = |n2|/|n3|, R_B = |n1|/sqrt|n2 n3|,
+ *    S the Frobenius norm, alpha = 1/2, beta and c as in 2-D (c = half the
+ *    largest S over all scales and voxels unless p->c > 0); V = 0 where
+ *    n2 n3 = 0 or, in RIDGE (VALLEY) mode, where n2 or n3 is positive
+ *    (negative); the smallest scale index of maximal V;
+ *  - Eq. (6) per component: N = H(u_sigma) / sqrt(1 + |grad u_sigma|) at
+ *    each voxel's scale, H_rho = G_rho * N (planes xx, yy, zz, xy, xz, yz);
+ *  - the tensor: eigenpairs (nu_k, e_k) of H_rho, mu_k of Eq. (7) with the
+ *    mode masks of Sec. 3.2; weight mu_k on e_k e_k^T, (mu_k + mu_l)/2 on the
+ *    symmetric pairs, 0 on the antisymmetric ones;
+ *  - P = L^T D L with the nine second-difference stencils, rows of L only at
+ *    voxels whose 3x3x3 neighbourhood lies inside; its largest eigenvalue is
+ *    at most 3 * 16 + 6 * 1 = 54, so 0 < tau_max <= 1/27.
+ * Parameters are those of mf4d_params with tau_max <= 1/27, model =
+ * MF4D_MAFOD, postprocess = 0, check = 0 and reselect_each_cycle = 1
+ * (other values: MF4D_EINVAL). The eigen-solves run in FP64, everything else
+ * in FP32. */
+
+/* Device workspace bytes of the calls below for a D x H x W volume (0 if the
+ * sizes or params are invalid). */
+size_t mf4d3d_workspace_bytes(int D, int H, int W, const mf4d_params *p);
+
+/* Scale selection over the stack (the tube measure above).
+ *   u        device float32 [D][H][W], read only.
+ *   idx_out  device uint8 [D][H][W]: smallest s of maximal V_s.
+ *   vmax_out device float32 [D][H][W] (nullable): max_s V_s.
+ *   c_out    device, one float32 (nullable): the c used.
+ * Errors: MF4D_EINVAL, MF4D_ENOMEM (ws_bytes too small), MF4D_EHIP. */
+int mf4d3d_scale_select(const float *u, int D, int H, int W, const mf4d_params *p, uint8_t *idx_out,
+                        float *vmax_out, float *c_out, void *ws, size_t ws_bytes, void *stream);
+
+/* Normalised, integrated Hessian at the scales idx (device uint8
+ * [D][H][W], values >= nscales clamped to nscales - 1).
+ *   hrho_out    device float32 [6][D][H][W]: xx, yy, zz, xy, xz, yz.
+ *   dparams_out device float32 [12][D][H][W] (nullable): the tensor as
+ *               mf4d3d_dtensor writes it.
+ * Errors as mf4d3d_scale_select. */
+int mf4d3d_tensor(const float *u, int D, int H, int W, const uint8_t *idx, const mf4d_params *p, float *hrho_out,
+                  float *dparams_out, void *ws, size_t ws_bytes, void *stream);
+
+/* The tensor of each voxel from its H_rho (device float32 [6][D][H][W]):
+ * dparams_out device float32 [12][D][H][W], planes 3 i + k = component i of
+ * the unit eigenvector e_k (k = 0..2), then mu_0, mu_1, mu_2 (lambda and mode
+ * from p). Errors: MF4D_EINVAL, MF4D_EHIP. */
+int mf4d3d_dtensor(const float *hrho, int D, int H, int W, const mf4d_params *p, float *dparams_out, void *stream);
+
+/* n FED substeps (Eq. (21)) u <- u - tau_i L^T D L u in place, with D from
+ * dparams (as mf4d3d_dtensor writes it); taus host, n doubles in the order
+ * applied (each cast to float32).
+ *   u          device float32 [D][H][W], in/out.
+ *   t_scratch  device float32 [6][D][H][W]: T = D L u of the current substep.
+ * Errors: MF4D_EINVAL (sizes, NULL, n outside [1, MF4D_MAX_SUBSTEPS], a tau
+ * not positive and finite), MF4D_EHIP. */
+int mf4d3d_fed_cycle_tensor(float *u, int D, int H, int W, const float *dparams, const double *taus, int n,
+                            float *t_scratch, void *stream);
+
+/* The whole filter on a volume: M cycles of scale selection, integrated
+ * Hessian, tensor and n FED substeps (the schedule of mf4d_fed_plan).
+ *   u_in   device float32 [D][H][W], read only.
+ *   u_out  device float32 [D][H][W]; may alias u_in.
+ * Errors: MF4D_EINVAL, MF4D_ENOMEM, MF4D_EHIP. */
+int mf4d3d_filter(const float *u_in, float *u_out, int D, int H, int W, const mf4d_params *p, void *ws,
+                  size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------ batches */
 
 /* A batch plan: many images of different sizes filtered together. Every

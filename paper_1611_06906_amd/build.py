@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmf4d.so")
-SOURCES = ["mf4d_api.hip", "scale_kernels.hip", "fed_kernels.hip", "batch.hip", "learned.hip", "aux_kernels.hip", "crease_kernels.hip"]
+SOURCES = ["mf4d_api.hip", "scale_kernels.hip", "fed_kernels.hip", "batch.hip", "learned.hip", "aux_kernels.hip",
+           "crease_kernels.hip", "vol3d.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

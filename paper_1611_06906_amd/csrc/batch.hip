@@ -241,16 +241,6 @@ void launch_batch_stream(int cols, int steps, dim3 grid, hipStream_t s, const BI
 
 }  // namespace
 
-// host helpers shared with mf4d_api.hip
-int validate_params(int H, int W, const mf4d_params *p);
-size_t image_workspace_bytes(int H, int W, int ns);
-void image_workspace(int H, int W, int ns, char *base, float **hA, float **SA, float **N,
-                     uint8_t **idx, float **tens, float **utmp, unsigned **smax);
-void window_taps(double sigma, WinTaps *t);
-void rho_taps(double rho, RhoTaps *t);
-int fed_plan_host(const mf4d_params *p, int *n_out, std::vector<double> &ordered);
-int default_stream_rows(int H, int W, int steps);
-
 }  // namespace mf4d
 
 using namespace mf4d;

@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/mf4d.h"
 
 namespace mf4d {
@@ -184,5 +186,18 @@ hipError_t launch_marching(const float *planes, int H, int W, float strength, in
                            unsigned *count, hipStream_t s);
 hipError_t launch_crease_match(const float *seg, const int8_t *type, int H, int W, const float *gt, const int *gt_type,
                                int n, float radius, float *dist, int *match, hipStream_t s);
+
+// ------------------------------------------------- host helpers (mf4d_api.hip)
+// parameter checks of mf4d_filter for an H x W image
+int validate_params(int H, int W, const mf4d_params *p);
+size_t image_workspace_bytes(int H, int W, int ns);
+void image_workspace(int H, int W, int ns, char *base, float **hA, float **SA, float **N,
+                     uint8_t **idx, float **tens, float **utmp, unsigned **smax);
+// combined taps (G, D1 G, D2 G) of a scale, and the integration taps
+void window_taps(double sigma, WinTaps *t);
+void rho_taps(double rho, RhoTaps *t);
+// the ordered FED steps mf4d_fed_plan returns for p
+int fed_plan_host(const mf4d_params *p, int *n_out, std::vector<double> &ordered);
+int default_stream_rows(int H, int W, int steps);
 
 }  // namespace mf4d

@@ -1,0 +1,677 @@
+// The filter on volumes (the 3-D extension that Sec. 5 names as the next
+// step): scale sweep with Frangi's tube measure, the normalised integrated
+// Hessian of Eq. (6) per component, the fourth-order tensor built from the
+// eigentensors of H_rho as Eqs. (7), (8) build it in 2-D, and FED cycles
+// (Eq. (21)) of the operator L^T D L with the 3-D second-difference stencils
+// and natural boundaries. Volumes are float32 [D][H][W], x fastest.
+//
+// Every kernel maps one thread to one voxel: blocks of 64 x 4 threads over
+// (x, y), one z plane per grid layer, so each wave reads and writes 64
+// consecutive floats of a row. The separable passes read their taps along
+// the pass axis straight from global memory (the rows a block touches stay
+// in L1/L2); the eigen-solves run in FP64.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "mf4d_internal.h"
+
+using namespace mf4d;
+
+namespace {
+
+constexpr double kTauLimit3 = 1.0 / 27.0;   // stencil bound 3 * 16 + 6 * 1 = 54, tau <= 2 / 54
+constexpr double kAlpha3 = 0.5;             // Frangi's plate/line parameter of the tube measure
+constexpr int kBX = 64, kBY = 4;
+
+// Half-sample symmetric extension for any i (period 2n).
+__device__ __forceinline__ int sym_index(int i, int n)
+{
+    const int p = 2 * n;
+    int j = i % p;
+    j = j < 0 ? j + p : j;
+    return j < n ? j : p - 1 - j;
+}
+
+struct Vox {
+    int x, y, z;
+    size_t o;        // linear index
+    bool inside;
+};
+
+__device__ __forceinline__ Vox voxel(int D, int H, int W)
+{
+    Vox v;
+    v.x = blockIdx.x * kBX + threadIdx.x;
+    v.y = blockIdx.y * kBY + threadIdx.y;
+    v.z = blockIdx.z;
+    v.inside = v.x < W && v.y < H && v.z < D;
+    v.o = ((size_t)v.z * H + v.y) * W + v.x;
+    return v;
+}
+
+// ------------------------------------------------------------------ sweep
+// Pass along x of one scale: X = (G, D1 G, D2 G) u, planes [3][m]. Inputs are
+// shifted by the voxel's own value (constant rows give exact zeros); the
+// Gaussian output adds it back.
+__global__ __launch_bounds__(256) void sweep3_x_kernel(const float *__restrict__ u, float *__restrict__ X, int D,
+                                                       int H, int W, WinTaps t)
+{
+    const Vox v = voxel(D, H, W);
+    if (!v.inside) return;
+    const size_t m = (size_t)D * H * W;
+    const float *row = u + (v.o - v.x);
+    const float ref = row[v.x];
+    const int R = t.R;
+    const bool inner = v.x - R >= 0 && v.x + R < W;
+    float g = 0.f, d1 = 0.f, d2 = 0.f;
+    for (int k = 0; k <= 2 * R; ++k) {
+        const int xi = inner ? v.x + k - R : sym_index(v.x + k - R, W);
+        const float a = row[xi] - ref;
+        g = fmaf(t.g[k], a, g);
+        d1 = fmaf(t.d1[k], a, d1);
+        d2 = fmaf(t.d2[k], a, d2);
+    }
+    X[v.o] = g + ref * t.gsum;
+    X[m + v.o] = d1;
+    X[2 * m + v.o] = d2;
+}
+
+// Pass along y: from X0 = G u the outputs (G, D1 G, D2 G), from X1 = D1 u the
+// outputs (G, D1 G), from X2 = D2 u the output G. Y planes [6][m] in the
+// order Y00, Y01, Y02, Y10, Y11, Y20 (first digit: x filter, second: y filter).
+__global__ __launch_bounds__(256) void sweep3_y_kernel(const float *__restrict__ X, float *__restrict__ Y, int D,
+                                                       int H, int W, WinTaps t)
+{
+    const Vox v = voxel(D, H, W);
+    if (!v.inside) return;
+    const size_t m = (size_t)D * H * W;
+    const size_t col = v.o - (size_t)v.y * W;   // voxel (z, 0, x)
+    const float r0 = X[v.o], r1 = X[m + v.o], r2 = X[2 * m + v.o];
+    const int R = t.R;
+    const bool inner = v.y - R >= 0 && v.y + R < H;
+    float a00 = 0.f, a01 = 0.f, a02 = 0.f, a10 = 0.f, a11 = 0.f, a20 = 0.f;
+    for (int k = 0; k <= 2 * R; ++k) {
+        const int yi = inner ? v.y + k - R : sym_index(v.y + k - R, H);
+        const size_t q = col + (size_t)yi * W;
+        const float b0 = X[q] - r0, b1 = X[m + q] - r1, b2 = X[2 * m + q] - r2;
+        a00 = fmaf(t.g[k], b0, a00);
+        a01 = fmaf(t.d1[k], b0, a01);
+        a02 = fmaf(t.d2[k], b0, a02);
+        a10 = fmaf(t.g[k], b1, a10);
+        a11 = fmaf(t.d1[k], b1, a11);
+        a20 = fmaf(t.g[k], b2, a20);
+    }
+    Y[v.o] = a00 + r0 * t.gsum;
+    Y[m + v.o] = a01;
+    Y[2 * m + v.o] = a02;
+    Y[3 * m + v.o] = a10 + r1 * t.gsum;
+    Y[4 * m + v.o] = a11;
+    Y[5 * m + v.o] = a20 + r2 * t.gsum;
+}
+
+// Eigenpairs of a symmetric 3 x 3 matrix by cyclic Jacobi rotations in
+// double: on return a[k][k] are the eigenvalues and column k of q (when
+// `vectors`) the unit eigenvector of a[k][k]. Every index is a compile-time
+// constant, so a and q stay in registers.
+template <int P, int Q>
+__device__ __forceinline__ void jacobi_rotate(double (&a)[3][3], double (&q)[3][3], bool vectors)
+{
+    const double apq = a[P][Q];
+    if (apq == 0.0) return;
+    const double th = (a[Q][Q] - a[P][P]) / (2.0 * apq);
+    const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(fma(th, th, 1.0)));
+    const double c = 1.0 / sqrt(fma(t, t, 1.0)), s = t * c;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {   // columns P, Q of a
+        const double akp = a[k][P], akq = a[k][Q];
+        a[k][P] = c * akp - s * akq;
+        a[k][Q] = s * akp + c * akq;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {   // rows P, Q of a
+        const double apk = a[P][k], aqk = a[Q][k];
+        a[P][k] = c * apk - s * aqk;
+        a[Q][k] = s * apk + c * aqk;
+    }
+    if (vectors) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double qkp = q[k][P], qkq = q[k][Q];
+            q[k][P] = c * qkp - s * qkq;
+            q[k][Q] = s * qkp + c * qkq;
+        }
+    }
+}
+
+__device__ __forceinline__ void jacobi3(double (&a)[3][3], double (&q)[3][3], bool vectors)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) q[i][j] = i == j ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 10; ++sweep) {
+        const double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+        const double dia = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
+        if (!(off > 1e-34 * dia)) break;   // also ends on an all-zero matrix
+        jacobi_rotate<0, 1>(a, q, vectors);
+        jacobi_rotate<0, 2>(a, q, vectors);
+        jacobi_rotate<1, 2>(a, q, vectors);
+    }
+}
+
+__device__ __forceinline__ void swap_if(double &a, double &b, bool c)
+{
+    const double ta = a;
+    a = c ? b : a;
+    b = c ? ta : b;
+}
+
+// Frangi's tube measure without its S factor, for sigma^2 H: n1, n2, n3 are
+// the eigenvalues by ascending magnitude (eigenvalues first in descending
+// order, then the exchanges (0,1), (0,2), (1,2) wherever the later one is
+// strictly smaller in magnitude); F = 0 where n2 n3 = 0 or the mode's sign
+// test fails, else (1 - exp(-R_A^2 / 2 alpha^2)) exp(-R_B^2 / 2 beta^2) with
+// R_A = |n2| / |n3|, R_B = |n1| / sqrt|n2 n3|.
+__device__ __forceinline__ double tube_factor(double h00, double h11, double h22, double h01, double h02,
+                                              double h12, int mode, double inv2beta2)
+{
+    double a[3][3] = {{h00, h01, h02}, {h01, h11, h12}, {h02, h12, h22}}, q[3][3];
+    jacobi3(a, q, false);
+    double e0 = a[0][0], e1 = a[1][1], e2 = a[2][2];
+    swap_if(e0, e1, e1 > e0);   // descending
+    swap_if(e0, e2, e2 > e0);
+    swap_if(e1, e2, e2 > e1);
+    swap_if(e0, e1, fabs(e1) < fabs(e0));   // ascending magnitude
+    swap_if(e0, e2, fabs(e2) < fabs(e0));
+    swap_if(e1, e2, fabs(e2) < fabs(e1));
+    if (e1 * e2 == 0.0) return 0.0;
+    if (mode == MF4D_RIDGE && (e1 > 0.0 || e2 > 0.0)) return 0.0;
+    if (mode == MF4D_VALLEY && (e1 < 0.0 || e2 < 0.0)) return 0.0;
+    const double ra = fabs(e1) / fabs(e2);
+    const double rb2 = (e0 * e0) / fabs(e1 * e2);
+    return (1.0 - exp(-(ra * ra) / (2.0 * kAlpha3 * kAlpha3))) * exp(-rb2 * inv2beta2);
+}
+
+// Pass along z and the per-voxel outputs of one scale: the gradient and
+// Hessian of u_sigma, S = |sigma^2 H|_F and the tube factor F (SF [m] pairs),
+// N = H / sqrt(1 + |grad u_sigma|) (planes xx, yy, zz, xy, xz, yz), and the
+// largest S into *smax_bits.
+__global__ __launch_bounds__(256) void sweep3_z_kernel(const float *__restrict__ Y, float2 *__restrict__ SF,
+                                                       float *__restrict__ N, unsigned *__restrict__ smax_bits,
+                                                       int D, int H, int W, WinTaps t, float sigma2, int mode,
+                                                       double inv2beta2)
+{
+    const Vox v = voxel(D, H, W);
+    float Sv = 0.f;
+    if (v.inside) {
+        const size_t plane = (size_t)H * W, m = plane * D;
+        const size_t pos = v.o - (size_t)v.z * plane;   // voxel (0, y, x)
+        float r[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) r[j] = Y[j * m + v.o];
+        const int R = t.R;
+        const bool inner = v.z - R >= 0 && v.z + R < D;
+        float gx = 0.f, gy = 0.f, gz = 0.f, hxx = 0.f, hyy = 0.f, hzz = 0.f, hxy = 0.f, hxz = 0.f, hyz = 0.f;
+        for (int k = 0; k <= 2 * R; ++k) {
+            const int zi = inner ? v.z + k - R : sym_index(v.z + k - R, D);
+            const size_t q = pos + (size_t)zi * plane;
+            const float b00 = Y[q] - r[0], b01 = Y[m + q] - r[1], b02 = Y[2 * m + q] - r[2];
+            const float b10 = Y[3 * m + q] - r[3], b11 = Y[4 * m + q] - r[4], b20 = Y[5 * m + q] - r[5];
+            const float g = t.g[k], d1 = t.d1[k], d2 = t.d2[k];
+            gz = fmaf(d1, b00, gz);
+            hzz = fmaf(d2, b00, hzz);
+            gy = fmaf(g, b01, gy);
+            hyz = fmaf(d1, b01, hyz);
+            hyy = fmaf(g, b02, hyy);
+            gx = fmaf(g, b10, gx);
+            hxz = fmaf(d1, b10, hxz);
+            hxy = fmaf(g, b11, hxy);
+            hxx = fmaf(g, b20, hxx);
+        }
+        gy += r[1] * t.gsum;
+        hyy += r[2] * t.gsum;
+        gx += r[3] * t.gsum;
+        hxy += r[4] * t.gsum;
+        hxx += r[5] * t.gsum;
+        const double s2 = sigma2;
+        const double a00 = s2 * hxx, a11 = s2 * hyy, a22 = s2 * hzz, a01 = s2 * hxy, a02 = s2 * hxz, a12 = s2 * hyz;
+        const double S = sqrt(a00 * a00 + a11 * a11 + a22 * a22 + 2.0 * (a01 * a01 + a02 * a02 + a12 * a12));
+        const double F = tube_factor(a00, a11, a22, a01, a02, a12, mode, inv2beta2);
+        Sv = (float)S;
+        SF[v.o] = make_float2(Sv, (float)F);
+        const float f = 1.f / sqrtf(1.f + sqrtf(gx * gx + gy * gy + gz * gz));
+        N[v.o] = hxx * f;
+        N[m + v.o] = hyy * f;
+        N[2 * m + v.o] = hzz * f;
+        N[3 * m + v.o] = hxy * f;
+        N[4 * m + v.o] = hxz * f;
+        N[5 * m + v.o] = hyz * f;
+    }
+    // block maximum of S, then one atomic (S >= 0: float order = bit order)
+    __shared__ float red[kBX * kBY / 64];
+    float mx = Sv;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+    const int tid = threadIdx.y * kBX + threadIdx.x;
+    if ((tid & 63) == 0) red[tid >> 6] = mx;
+    __syncthreads();
+    if (tid == 0) {
+        float b = red[0];
+        for (int i = 1; i < kBX * kBY / 64; ++i) b = fmaxf(b, red[i]);
+        atomicMax(smax_bits, __float_as_uint(b));
+    }
+}
+
+// ----------------------------------------------------------------- select
+// V_s = F_s (1 - exp(-S_s^2 / 2 c^2)) with c = params c when > 0, else half
+// the largest S over all scales and voxels; the smallest s of maximal V.
+__global__ __launch_bounds__(256) void argmax3_kernel(const float2 *__restrict__ SF, int ns, const unsigned *smax_bits,
+                                                      float c_param, uint8_t *__restrict__ idx,
+                                                      float *__restrict__ vmax, float *__restrict__ c_out, int D,
+                                                      int H, int W)
+{
+    const Vox v = voxel(D, H, W);
+    const float c = c_param > 0.f ? c_param : 0.5f * __uint_as_float(*smax_bits);
+    if (c_out && v.x == 0 && v.y == 0 && v.z == 0) *c_out = c;
+    if (!v.inside) return;
+    const size_t m = (size_t)D * H * W;
+    int best = 0;
+    float bv = 0.f;
+    if (c > 0.f) {
+        const float inv2c2 = 1.f / (2.f * c * c);
+        for (int s = 0; s < ns; ++s) {
+            const float2 sf = SF[s * m + v.o];
+            const float val = sf.y * -expm1f(-(sf.x * sf.x) * inv2c2);
+            if (s == 0 || val > bv) {
+                bv = val;
+                best = s;
+            }
+        }
+    }
+    idx[v.o] = (uint8_t)best;
+    if (vmax) vmax[v.o] = bv;
+}
+
+// N at each voxel's scale (clamped to ns - 1), planes [6][m].
+__global__ __launch_bounds__(256) void gather3_kernel(const float *__restrict__ N, const uint8_t *__restrict__ idx,
+                                                      int ns, float *__restrict__ out, int D, int H, int W)
+{
+    const Vox v = voxel(D, H, W);
+    if (!v.inside) return;
+    const size_t m = (size_t)D * H * W;
+    const int s = min((int)idx[v.o], ns - 1);
+    const float *src = N + (size_t)s * 6 * m;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) out[k * m + v.o] = src[k * m + v.o];
+}
+
+// G_rho along one axis (0: x, 1: y, 2: z) of the six planes.
+template <int AXIS>
+__global__ __launch_bounds__(256) void rho3_kernel(const float *__restrict__ in, float *__restrict__ out, int D, int H,
+                                                   int W, RhoTaps t)
+{
+    const Vox v = voxel(D, H, W);
+    if (!v.inside) return;
+    const size_t plane = (size_t)H * W, m = plane * D;
+    const int n = AXIS == 0 ? W : (AXIS == 1 ? H : D);
+    const int c = AXIS == 0 ? v.x : (AXIS == 1 ? v.y : v.z);
+    const size_t stride = AXIS == 0 ? 1 : (AXIS == 1 ? (size_t)W : plane);
+    const size_t base = v.o - (size_t)c * stride;
+    float acc[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) acc[k] = t.g[0] * in[k * m + v.o];
+    for (int j = 1; j <= t.r; ++j) {
+        const size_t qm = base + (size_t)sym_index(c - j, n) * stride;
+        const size_t qp = base + (size_t)sym_index(c + j, n) * stride;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) acc[k] = fmaf(t.g[j], in[k * m + qm] + in[k * m + qp], acc[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) out[k * m + v.o] = acc[k];
+}
+
+// ----------------------------------------------------------------- tensor
+// Eigenpairs (nu_k, e_k) of H_rho in FP64 and mu_k of Eq. (7) with the mode
+// masks: planes [12][m] = Q (row-major, Q[3 i + k] = component i of e_k),
+// then mu_0, mu_1, mu_2.
+__global__ __launch_bounds__(256) void eig3_kernel(const float *__restrict__ hr, float *__restrict__ tens, int mode,
+                                                   double inv_lam2, int D, int H, int W)
+{
+    const Vox v = voxel(D, H, W);
+    if (!v.inside) return;
+    const size_t m = (size_t)D * H * W;
+    const double hxx = hr[v.o], hyy = hr[m + v.o], hzz = hr[2 * m + v.o];
+    const double hxy = hr[3 * m + v.o], hxz = hr[4 * m + v.o], hyz = hr[5 * m + v.o];
+    double a[3][3] = {{hxx, hxy, hxz}, {hxy, hyy, hyz}, {hxz, hyz, hzz}}, q[3][3];
+    jacobi3(a, q, true);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) tens[(3 * i + k) * m + v.o] = (float)q[i][k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double nu = a[k][k];
+        double mu = 1.0 / (1.0 + nu * nu * inv_lam2);
+        if (mode == MF4D_RIDGE && nu >= 0.0) mu = 1.0;
+        if (mode == MF4D_VALLEY && nu <= 0.0) mu = 1.0;
+        tens[(9 + k) * m + v.o] = (float)mu;
+    }
+}
+
+// ---------------------------------------------------------------- substep
+// T = D h at interior voxels (0 elsewhere): h the second differences of u
+// (cross stencils for the mixed terms), D h = Q (M o (Q^T h Q)) Q^T with
+// M_kk = mu_k and M_kl = (mu_k + mu_l) / 2 -- the action of the eigentensor
+// expansion on a symmetric h (the antisymmetric eigentensors have weight 0).
+// T planes [6][m]: xx, yy, zz, xy, xz, yz.
+__global__ __launch_bounds__(256) void tens3_kernel(const float *__restrict__ u, const float *__restrict__ tens,
+                                                    float *__restrict__ T, int D, int H, int W)
+{
+    const Vox v = voxel(D, H, W);
+    if (!v.inside) return;
+    const size_t plane = (size_t)H * W, m = plane * D;
+    const size_t o = v.o;
+    if (v.x < 1 || v.x > W - 2 || v.y < 1 || v.y > H - 2 || v.z < 1 || v.z > D - 2) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) T[k * m + o] = 0.f;
+        return;
+    }
+    const size_t sy = W, sz = plane;
+    const float c2 = 2.f * u[o];
+    float h[3][3];
+    h[0][0] = u[o - 1] - c2 + u[o + 1];
+    h[1][1] = u[o - sy] - c2 + u[o + sy];
+    h[2][2] = u[o - sz] - c2 + u[o + sz];
+    h[0][1] = 0.25f * ((u[o - sy - 1] + u[o + sy + 1]) - (u[o + sy - 1] + u[o - sy + 1]));
+    h[0][2] = 0.25f * ((u[o - sz - 1] + u[o + sz + 1]) - (u[o + sz - 1] + u[o - sz + 1]));
+    h[1][2] = 0.25f * ((u[o - sz - sy] + u[o + sz + sy]) - (u[o + sz - sy] + u[o - sz + sy]));
+    h[1][0] = h[0][1];
+    h[2][0] = h[0][2];
+    h[2][1] = h[1][2];
+    float q[3][3], mu[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) q[i][k] = tens[(3 * i + k) * m + o];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) mu[k] = tens[(9 + k) * m + o];
+    // B = h Q, A = Q^T B (in the eigenbasis), weighted by M
+    float B[3][3], A[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) B[i][k] = h[i][0] * q[0][k] + h[i][1] * q[1][k] + h[i][2] * q[2][k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int l = k; l < 3; ++l) {
+            const float s = q[0][k] * B[0][l] + q[1][k] * B[1][l] + q[2][k] * B[2][l];
+            A[k][l] = (k == l ? mu[k] : 0.5f * (mu[k] + mu[l])) * s;
+            A[l][k] = A[k][l];
+        }
+    // T = Q A Q^T
+    float C[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int l = 0; l < 3; ++l) C[i][l] = q[i][0] * A[0][l] + q[i][1] * A[1][l] + q[i][2] * A[2][l];
+    auto Tij = [&](int i, int j) { return C[i][0] * q[j][0] + C[i][1] * q[j][1] + C[i][2] * q[j][2]; };
+    T[o] = Tij(0, 0);
+    T[m + o] = Tij(1, 1);
+    T[2 * m + o] = Tij(2, 2);
+    T[3 * m + o] = Tij(0, 1);
+    T[4 * m + o] = Tij(0, 2);
+    T[5 * m + o] = Tij(1, 2);
+}
+
+// u -= tau L^T T in place: the transposed stencils gather T from the
+// neighbours (T is zero off the interior; neighbours outside the volume
+// contribute nothing). The cross stencils enter twice (xy and yx), each with
+// weight 1/4.
+__global__ __launch_bounds__(256) void upd3_kernel(float *__restrict__ u, const float *__restrict__ T, float tau, int D,
+                                                   int H, int W)
+{
+    const Vox v = voxel(D, H, W);
+    if (!v.inside) return;
+    const size_t plane = (size_t)H * W, m = plane * D;
+    auto at = [&](int k, int dz, int dy, int dx) -> float {
+        const int z = v.z + dz, y = v.y + dy, x = v.x + dx;
+        if (z < 0 || z >= D || y < 0 || y >= H || x < 0 || x >= W) return 0.f;
+        return T[k * m + v.o + (ptrdiff_t)dz * (ptrdiff_t)plane + (ptrdiff_t)dy * W + dx];
+    };
+    float r = (at(0, 0, 0, -1) + at(0, 0, 0, 1)) - 2.f * at(0, 0, 0, 0);
+    r += (at(1, 0, -1, 0) + at(1, 0, 1, 0)) - 2.f * at(1, 0, 0, 0);
+    r += (at(2, -1, 0, 0) + at(2, 1, 0, 0)) - 2.f * at(2, 0, 0, 0);
+    r += 0.5f * ((at(3, 0, -1, -1) + at(3, 0, 1, 1)) - (at(3, 0, 1, -1) + at(3, 0, -1, 1)));
+    r += 0.5f * ((at(4, -1, 0, -1) + at(4, 1, 0, 1)) - (at(4, 1, 0, -1) + at(4, -1, 0, 1)));
+    r += 0.5f * ((at(5, -1, -1, 0) + at(5, 1, 1, 0)) - (at(5, 1, -1, 0) + at(5, -1, 1, 0)));
+    u[v.o] = u[v.o] - tau * r;
+}
+
+// ------------------------------------------------------------------ host
+dim3 grid3(int D, int H, int W) { return dim3((W + kBX - 1) / kBX, (H + kBY - 1) / kBY, D); }
+const dim3 kBlock3(kBX, kBY, 1);
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+bool valid_dims(int D, int H, int W)
+{
+    if (D < 3 || H < 3 || W < 3 || D > 65535) return false;
+    return (long long)D * H * W < (1LL << 31);
+}
+
+// Parameter checks of the 2-D filter, then the 3-D restrictions.
+int validate3(int D, int H, int W, const mf4d_params *p)
+{
+    if (!valid_dims(D, H, W) || !p) return MF4D_EINVAL;
+    int st = validate_params(3, 3, p);   // the fields of p (the image size is checked above)
+    if (st != MF4D_OK) return st;
+    if (p->tau_max > kTauLimit3) return MF4D_EINVAL;
+    if (p->model != MF4D_MAFOD || p->postprocess != 0 || p->check != 0 || p->reselect_each_cycle != 1)
+        return MF4D_EINVAL;
+    return MF4D_OK;
+}
+
+struct Work3 {
+    float *X, *Y;        // pass planes [3][m], [6][m]
+    float2 *SF;          // [ns][m]
+    float *N;            // [ns][6][m]
+    uint8_t *idx;
+    float *G1, *G2;      // [6][m] each: gathered N and the blur's ping-pong
+    float *hrho;         // [6][m]
+    float *tens;         // [12][m]
+    float *T;            // [6][m]
+    unsigned *smax;
+};
+
+size_t layout3(int D, int H, int W, int ns, Work3 *w, char *base)
+{
+    const size_t m = (size_t)D * H * W;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *q = base ? base + off : nullptr;
+        off += align256(bytes);
+        return q;
+    };
+    Work3 t;
+    t.X = (float *)take(3 * m * 4);
+    t.Y = (float *)take(6 * m * 4);
+    t.SF = (float2 *)take((size_t)ns * m * 8);
+    t.N = (float *)take((size_t)ns * 6 * m * 4);
+    t.idx = (uint8_t *)take(m);
+    t.G1 = (float *)take(6 * m * 4);
+    t.G2 = (float *)take(6 * m * 4);
+    t.hrho = (float *)take(6 * m * 4);
+    t.tens = (float *)take(12 * m * 4);
+    t.T = (float *)take(6 * m * 4);
+    t.smax = (unsigned *)take(256);
+    if (w) *w = t;
+    return off;
+}
+
+#define CHECK_HIP(expr)                         \
+    do {                                        \
+        hipError_t e_ = (expr);                 \
+        if (e_ != hipSuccess) return MF4D_EHIP; \
+    } while (0)
+#define CHECK_LAUNCH() CHECK_HIP(hipGetLastError())
+
+// All scales: S, F and N per scale, and the largest S (cleared first).
+int sweep3(const float *u, int D, int H, int W, const mf4d_params *p, const Work3 &w, hipStream_t s)
+{
+    const size_t m = (size_t)D * H * W;
+    const dim3 g = grid3(D, H, W);
+    CHECK_HIP(launch_fill_u32(w.smax, 0u, 1, s));
+    const double inv2beta2 = 1.0 / (2.0 * (double)p->beta * (double)p->beta);
+    for (int k = 0; k < p->nscales; ++k) {
+        WinTaps t;
+        window_taps(p->sigmas[k], &t);
+        const float sigma2 = p->sigmas[k] * p->sigmas[k];
+        sweep3_x_kernel<<<g, kBlock3, 0, s>>>(u, w.X, D, H, W, t);
+        CHECK_LAUNCH();
+        sweep3_y_kernel<<<g, kBlock3, 0, s>>>(w.X, w.Y, D, H, W, t);
+        CHECK_LAUNCH();
+        sweep3_z_kernel<<<g, kBlock3, 0, s>>>(w.Y, w.SF + k * m, w.N + (size_t)k * 6 * m, w.smax, D, H, W, t,
+                                              sigma2, p->mode, inv2beta2);
+        CHECK_LAUNCH();
+    }
+    return MF4D_OK;
+}
+
+// H_rho from N at the chosen scales; then (optionally) the tensor planes.
+int integrate3(int D, int H, int W, const mf4d_params *p, const uint8_t *idx, const Work3 &w, float *hrho,
+               float *tens, hipStream_t s)
+{
+    const dim3 g = grid3(D, H, W);
+    RhoTaps rt;
+    rho_taps(p->rho, &rt);
+    gather3_kernel<<<g, kBlock3, 0, s>>>(w.N, idx, p->nscales, w.G1, D, H, W);
+    CHECK_LAUNCH();
+    rho3_kernel<0><<<g, kBlock3, 0, s>>>(w.G1, w.G2, D, H, W, rt);
+    CHECK_LAUNCH();
+    rho3_kernel<1><<<g, kBlock3, 0, s>>>(w.G2, w.G1, D, H, W, rt);
+    CHECK_LAUNCH();
+    rho3_kernel<2><<<g, kBlock3, 0, s>>>(w.G1, hrho, D, H, W, rt);
+    CHECK_LAUNCH();
+    if (tens) {
+        const double inv_lam2 = 1.0 / ((double)p->lambda * (double)p->lambda);
+        eig3_kernel<<<g, kBlock3, 0, s>>>(hrho, tens, p->mode, inv_lam2, D, H, W);
+        CHECK_LAUNCH();
+    }
+    return MF4D_OK;
+}
+
+int substeps3(float *u, int D, int H, int W, const float *tens, const float *taus32, int n, float *T, hipStream_t s)
+{
+    const dim3 g = grid3(D, H, W);
+    for (int i = 0; i < n; ++i) {
+        tens3_kernel<<<g, kBlock3, 0, s>>>(u, tens, T, D, H, W);
+        CHECK_LAUNCH();
+        upd3_kernel<<<g, kBlock3, 0, s>>>(u, T, taus32[i], D, H, W);
+        CHECK_LAUNCH();
+    }
+    return MF4D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mf4d3d_workspace_bytes(int D, int H, int W, const mf4d_params *p)
+{
+    if (validate3(D, H, W, p) != MF4D_OK) return 0;
+    return layout3(D, H, W, p->nscales, nullptr, nullptr);
+}
+
+int mf4d3d_scale_select(const float *u, int D, int H, int W, const mf4d_params *p, uint8_t *idx_out,
+                        float *vmax_out, float *c_out, void *ws, size_t ws_bytes, void *stream)
+{
+    int st = validate3(D, H, W, p);
+    if (st != MF4D_OK) return st;
+    if (!u || !idx_out || !ws) return MF4D_EINVAL;
+    if (ws_bytes < layout3(D, H, W, p->nscales, nullptr, nullptr)) return MF4D_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    Work3 w;
+    layout3(D, H, W, p->nscales, &w, (char *)ws);
+    st = sweep3(u, D, H, W, p, w, s);
+    if (st != MF4D_OK) return st;
+    argmax3_kernel<<<grid3(D, H, W), kBlock3, 0, s>>>(w.SF, p->nscales, w.smax, p->c, idx_out, vmax_out, c_out, D, H,
+                                                      W);
+    CHECK_LAUNCH();
+    return MF4D_OK;
+}
+
+int mf4d3d_tensor(const float *u, int D, int H, int W, const uint8_t *idx, const mf4d_params *p, float *hrho_out,
+                  float *dparams_out, void *ws, size_t ws_bytes, void *stream)
+{
+    int st = validate3(D, H, W, p);
+    if (st != MF4D_OK) return st;
+    if (!u || !idx || !hrho_out || !ws) return MF4D_EINVAL;
+    if (ws_bytes < layout3(D, H, W, p->nscales, nullptr, nullptr)) return MF4D_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    Work3 w;
+    layout3(D, H, W, p->nscales, &w, (char *)ws);
+    st = sweep3(u, D, H, W, p, w, s);
+    if (st != MF4D_OK) return st;
+    return integrate3(D, H, W, p, idx, w, hrho_out, dparams_out, s);
+}
+
+int mf4d3d_dtensor(const float *hrho, int D, int H, int W, const mf4d_params *p, float *dparams_out, void *stream)
+{
+    int st = validate3(D, H, W, p);
+    if (st != MF4D_OK) return st;
+    if (!hrho || !dparams_out) return MF4D_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const double inv_lam2 = 1.0 / ((double)p->lambda * (double)p->lambda);
+    eig3_kernel<<<grid3(D, H, W), kBlock3, 0, s>>>(hrho, dparams_out, p->mode, inv_lam2, D, H, W);
+    CHECK_LAUNCH();
+    return MF4D_OK;
+}
+
+int mf4d3d_fed_cycle_tensor(float *u, int D, int H, int W, const float *dparams, const double *taus, int n,
+                            float *t_scratch, void *stream)
+{
+    if (!valid_dims(D, H, W) || !u || !dparams || !taus || !t_scratch || n < 1 || n > MF4D_MAX_SUBSTEPS)
+        return MF4D_EINVAL;
+    for (int i = 0; i < n; ++i)
+        if (!(taus[i] > 0.0) || !std::isfinite(taus[i])) return MF4D_EINVAL;
+    std::vector<float> t32(n);
+    for (int i = 0; i < n; ++i) t32[i] = (float)taus[i];
+    return substeps3(u, D, H, W, dparams, t32.data(), n, t_scratch, (hipStream_t)stream);
+}
+
+int mf4d3d_filter(const float *u_in, float *u_out, int D, int H, int W, const mf4d_params *p, void *ws,
+                  size_t ws_bytes, void *stream)
+{
+    int st = validate3(D, H, W, p);
+    if (st != MF4D_OK) return st;
+    if (!u_in || !u_out || !ws) return MF4D_EINVAL;
+    if (ws_bytes < layout3(D, H, W, p->nscales, nullptr, nullptr)) return MF4D_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t m = (size_t)D * H * W;
+    Work3 w;
+    layout3(D, H, W, p->nscales, &w, (char *)ws);
+    if (u_in != u_out) CHECK_HIP(launch_copy_f32(u_in, u_out, m, s));
+    if (p->cycles == 0) return MF4D_OK;
+    std::vector<double> ordered;
+    int n = 0;
+    st = fed_plan_host(p, &n, ordered);
+    if (st != MF4D_OK) return st;
+    std::vector<float> t32(n);
+    for (int i = 0; i < n; ++i) t32[i] = (float)ordered[i];
+    const dim3 g = grid3(D, H, W);
+    for (int k = 0; k < p->cycles; ++k) {
+        st = sweep3(u_out, D, H, W, p, w, s);
+        if (st != MF4D_OK) return st;
+        argmax3_kernel<<<g, kBlock3, 0, s>>>(w.SF, p->nscales, w.smax, p->c, w.idx, nullptr, nullptr, D, H, W);
+        CHECK_LAUNCH();
+        st = integrate3(D, H, W, p, w.idx, w, w.hrho, w.tens, s);
+        if (st != MF4D_OK) return st;
+        st = substeps3(u_out, D, H, W, w.tens, t32.data(), n, w.T, s);
+        if (st != MF4D_OK) return st;
+    }
+    return MF4D_OK;
+}
+
+}  // extern "C"

@@ -31,7 +31,9 @@ EXPORTS = ["mf4d_status_string", "mf4d_params_default", "mf4d_fed_schedule",
            "mf4d_creases_workspace_bytes", "mf4d_creases", "mf4d_crease_match", "mf4d_batch_create", "mf4d_batch_workspace_bytes", "mf4d_filter_batch",
            "mf4d_batch_autotune", "mf4d_batch_get_tuning", "mf4d_batch_set_tuning", "mf4d_batch_destroy",
            "mf4d_net_param_count", "mf4d_net_workspace_bytes", "mf4d_net_forward", "mf4d_net_backward",
-           "mf4d_net_step", "mf4d_learned_workspace_bytes", "mf4d_filter_learned"]
+           "mf4d_net_step", "mf4d_learned_workspace_bytes", "mf4d_filter_learned",
+           "mf4d3d_workspace_bytes", "mf4d3d_scale_select", "mf4d3d_tensor", "mf4d3d_dtensor",
+           "mf4d3d_fed_cycle_tensor", "mf4d3d_filter"]
 
 
 class MF4DError(RuntimeError):
@@ -175,6 +177,18 @@ def lib():
         L.mf4d_learned_workspace_bytes.restype = sz
         L.mf4d_filter_learned.argtypes = [vp, vp, i, i, P(mf4d_params), vp, ctypes.c_float, vp, vp, sz, vp]
         L.mf4d_filter_learned.restype = i
+        L.mf4d3d_workspace_bytes.argtypes = [i, i, i, P(mf4d_params)]
+        L.mf4d3d_workspace_bytes.restype = sz
+        L.mf4d3d_scale_select.argtypes = [vp, i, i, i, P(mf4d_params), vp, vp, vp, vp, sz, vp]
+        L.mf4d3d_scale_select.restype = i
+        L.mf4d3d_tensor.argtypes = [vp, i, i, i, vp, P(mf4d_params), vp, vp, vp, sz, vp]
+        L.mf4d3d_tensor.restype = i
+        L.mf4d3d_dtensor.argtypes = [vp, i, i, i, P(mf4d_params), vp, vp]
+        L.mf4d3d_dtensor.restype = i
+        L.mf4d3d_fed_cycle_tensor.argtypes = [vp, i, i, i, vp, P(d), i, vp, vp]
+        L.mf4d3d_fed_cycle_tensor.restype = i
+        L.mf4d3d_filter.argtypes = [vp, vp, i, i, i, P(mf4d_params), vp, sz, vp]
+        L.mf4d3d_filter.restype = i
         _lib = L
     return _lib
 
@@ -546,3 +560,82 @@ def net_init(seed=0, device="cuda"):
         parts.append(rng.normal(0.0, np.sqrt(2.0 / fan_in), size=ch[l + 1] * ch[l] * 9))
         parts.append(np.zeros(ch[l + 1]))
     return torch.from_numpy(np.concatenate(parts).astype(np.float32)).to(device)
+
+
+# ------------------------------------------------------------------- volumes
+def _dhw(u):
+    if u.dim() != 3:
+        raise ValueError("volume must be 3-D [D, H, W]")
+    return int(u.shape[0]), int(u.shape[1]), int(u.shape[2])
+
+
+def mf4d3d_workspace_bytes(D: int, H: int, W: int, params: Params) -> int:
+    st = params.struct()
+    return int(lib().mf4d3d_workspace_bytes(int(D), int(H), int(W), ctypes.byref(st)))
+
+
+def workspace3(D: int, H: int, W: int, params: Params, device="cuda"):
+    nb = mf4d3d_workspace_bytes(D, H, W, params)
+    if nb == 0:
+        raise MF4DError(MF4D_EINVAL, "mf4d3d_workspace_bytes")
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def mf4d3d_scale_select(u, params: Params, idx_out, vmax_out=None, c_out=None, ws=None, stream=None):
+    D, H, W = _dhw(_dev(u, torch.float32, name="u"))
+    _dev(idx_out, torch.uint8, (D, H, W), "idx_out")
+    _dev(vmax_out, torch.float32, (D, H, W), "vmax_out")
+    _dev(c_out, torch.float32, (1,), "c_out")
+    if ws is None:
+        ws = workspace3(D, H, W, params, u.device)
+    _dev(ws, torch.uint8, name="ws")
+    st = params.struct()
+    _check(lib().mf4d3d_scale_select(_ptr(u), D, H, W, ctypes.byref(st), _ptr(idx_out), _ptr(vmax_out),
+                                     _ptr(c_out), _ptr(ws), ws.numel(), _stream(stream)), "mf4d3d_scale_select")
+
+
+def mf4d3d_tensor(u, idx, params: Params, hrho_out, dparams_out=None, ws=None, stream=None):
+    D, H, W = _dhw(_dev(u, torch.float32, name="u"))
+    _dev(idx, torch.uint8, (D, H, W), "idx")
+    _dev(hrho_out, torch.float32, (6, D, H, W), "hrho_out")
+    _dev(dparams_out, torch.float32, (12, D, H, W), "dparams_out")
+    if ws is None:
+        ws = workspace3(D, H, W, params, u.device)
+    _dev(ws, torch.uint8, name="ws")
+    st = params.struct()
+    _check(lib().mf4d3d_tensor(_ptr(u), D, H, W, _ptr(idx), ctypes.byref(st), _ptr(hrho_out), _ptr(dparams_out),
+                               _ptr(ws), ws.numel(), _stream(stream)), "mf4d3d_tensor")
+
+
+def mf4d3d_dtensor(hrho, params: Params, dparams_out, stream=None):
+    _dev(hrho, torch.float32, name="hrho")
+    if hrho.dim() != 4 or hrho.shape[0] != 6:
+        raise ValueError("hrho must be [6, D, H, W]")
+    D, H, W = int(hrho.shape[1]), int(hrho.shape[2]), int(hrho.shape[3])
+    _dev(dparams_out, torch.float32, (12, D, H, W), "dparams_out")
+    st = params.struct()
+    _check(lib().mf4d3d_dtensor(_ptr(hrho), D, H, W, ctypes.byref(st), _ptr(dparams_out), _stream(stream)),
+           "mf4d3d_dtensor")
+
+
+def mf4d3d_fed_cycle_tensor(u, dparams, taus, t_scratch=None, stream=None):
+    D, H, W = _dhw(_dev(u, torch.float32, name="u"))
+    _dev(dparams, torch.float32, (12, D, H, W), "dparams")
+    if t_scratch is None:
+        t_scratch = torch.empty((6, D, H, W), dtype=torch.float32, device=u.device)
+    _dev(t_scratch, torch.float32, (6, D, H, W), "t_scratch")
+    t = np.ascontiguousarray(np.asarray(taus, dtype=np.float64))
+    _check(lib().mf4d3d_fed_cycle_tensor(_ptr(u), D, H, W, _ptr(dparams),
+                                         t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(t),
+                                         _ptr(t_scratch), _stream(stream)), "mf4d3d_fed_cycle_tensor")
+
+
+def mf4d3d_filter(u_in, u_out, params: Params, ws=None, stream=None):
+    D, H, W = _dhw(_dev(u_in, torch.float32, name="u_in"))
+    _dev(u_out, torch.float32, (D, H, W), "u_out")
+    if ws is None:
+        ws = workspace3(D, H, W, params, u_in.device)
+    _dev(ws, torch.uint8, name="ws")
+    st = params.struct()
+    _check(lib().mf4d3d_filter(_ptr(u_in), _ptr(u_out), D, H, W, ctypes.byref(st), _ptr(ws), ws.numel(),
+                               _stream(stream)), "mf4d3d_filter")

@@ -275,6 +275,67 @@ def batch_image(spec):
     return img
 
 
+# --------------------------------------------------------------------------
+# volumes: tubes along quadratic Bezier curves in 3-D
+# --------------------------------------------------------------------------
+def _bezier3_samples(p0, p1, p2, spacing=0.5):
+    """Points and unit tangents along a quadratic Bezier curve in (x, y, z)."""
+    chord = np.linalg.norm(p1 - p0) + np.linalg.norm(p2 - p1)
+    n = max(8, int(math.ceil(chord / spacing)) + 1)
+    t = np.linspace(0.0, 1.0, n)[:, None]
+    pts = (1 - t) ** 2 * p0 + 2 * (1 - t) * t * p1 + t ** 2 * p2
+    tan = 2 * (1 - t) * (p1 - p0) + 2 * t * (p2 - p1)
+    tn = np.linalg.norm(tan, axis=1, keepdims=True)
+    tn[tn == 0] = 1.0
+    return pts, tan / tn
+
+
+def tubes3d(D, H, W, n_tubes, seed, *, background=0.2, amplitude=0.6, width_range=(1.0, 2.5),
+            control_range=(0.1, 0.9), signs="bright", noise=0.05, reach=5.0):
+    """Volume [D][H][W] of tubes with Gaussian cross-section plus noise.
+
+    Each tube follows a quadratic Bezier curve with control points uniform in
+    the control_range box of the volume; every voxel takes the profile
+    amp exp(-d^2 / 2 w^2) of its nearest centreline sample (3-D Euclidean
+    distance transform), d its distance from that sample's tangent line (0
+    beyond reach w). signs: "bright", or "mixed" (alternating bright / dark).
+    """
+    rng = np.random.default_rng(seed)
+    lo, hi = control_range
+    pts, tans, amps, wids = [], [], [], []
+    for c in range(n_tubes):
+        ctrl = rng.uniform(lo, hi, size=(3, 3)) * np.array([W - 1, H - 1, D - 1])
+        w = rng.uniform(*width_range)
+        sgn = 1.0 if (signs == "bright" or c % 2 == 0) else -1.0
+        p, t = _bezier3_samples(ctrl[0], ctrl[1], ctrl[2])
+        pts.append(p)
+        tans.append(t)
+        amps.append(np.full(len(p), sgn * amplitude))
+        wids.append(np.full(len(p), w))
+    prof = np.zeros((D, H, W))
+    if n_tubes:
+        P, T, A, Wd = (np.concatenate(a) for a in (pts, tans, amps, wids))
+        ix, iy, iz = (np.rint(P[:, k]).astype(np.int64) for k in range(3))
+        inside = (ix >= 0) & (ix < W) & (iy >= 0) & (iy < H) & (iz >= 0) & (iz < D)
+        k_in = np.nonzero(inside)[0]
+        if len(k_in):
+            owner = np.full((D, H, W), -1, np.int64)
+            owner[iz[k_in], iy[k_in], ix[k_in]] = k_in     # last sample wins, deterministic
+            _, (nz, ny, nx) = ndimage.distance_transform_edt(owner < 0, return_indices=True)
+            k = owner[nz, ny, nx]
+            del nz, ny, nx
+            zz, yy, xx = np.meshgrid(np.arange(D), np.arange(H), np.arange(W), indexing="ij")
+            vx, vy, vz = xx - P[k, 0], yy - P[k, 1], zz - P[k, 2]
+            del zz, yy, xx
+            along = vx * T[k, 0] + vy * T[k, 1] + vz * T[k, 2]
+            d2 = np.maximum(vx * vx + vy * vy + vz * vz - along * along, 0.0)
+            w = Wd[k]
+            prof = A[k] * np.exp(-d2 / (2.0 * w * w))
+            prof[d2 > (reach * w) ** 2] = 0.0
+    img = background + prof + rng.normal(0.0, noise, size=(D, H, W))
+    return np.ascontiguousarray(np.clip(img, 0.0, 1.0).astype(np.float32))
+
+
 def noise_image(H, W, seed, lo=0.0, hi=1.0):
     """Uniform white noise, for stage-level tests."""
     rng = np.random.default_rng(seed)

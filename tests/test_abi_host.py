@@ -21,7 +21,7 @@ def m():
 
 def test_header_symbols_exported(m):
     hdr = open(os.path.join(ROOT, "include", "mf4d.h")).read()
-    declared = set(re.findall(r"\b(mf4d_[a-z0-9_]+)\s*\(", hdr))
+    declared = set(re.findall(r"\b(mf4d(?:3d)?_[a-z0-9_]+)\s*\(", hdr))
     assert declared == set(m.EXPORTS)
     for name in declared:
         assert hasattr(m.lib(), name), name
@@ -103,6 +103,43 @@ def test_validation_rejects_before_launch(m):
         m.mf4d_fed_schedule(0)
     with pytest.raises(m.MF4DError):
         m.mf4d_fed_schedule(10, 0.07)
+
+
+def test_volume_validation_rejects_before_launch(m):
+    """The 3-D calls: the 2-D parameter checks, tau_max <= 1/27, and the
+    options the volume filter does not take; sizes >= 3 per axis."""
+    good = dict(sigmas=[1.0, 2.0], mode=0, cycles=1, substeps=5, tau_max=1.0 / 27.0)
+    P = lambda **kw: m.Params(**{**good, **kw})
+    assert m.mf4d3d_workspace_bytes(8, 9, 10, P()) > 0
+    assert m.mf4d3d_workspace_bytes(3, 3, 3, P()) > 0
+    bad = [
+        ((2, 9, 10), P()), ((8, 2, 10), P()), ((8, 9, 2), P()), ((70000, 4, 4), P()),
+        ((1 << 11, 1 << 10, 1 << 10), P()),
+        ((8, 9, 10), P(tau_max=0.05)), ((8, 9, 10), P(tau_max=1.0 / 26.0)), ((8, 9, 10), P(tau_max=0.0)),
+        ((8, 9, 10), P(model=1, sigmas=[1.0])), ((8, 9, 10), P(postprocess=1)), ((8, 9, 10), P(check=1)),
+        ((8, 9, 10), P(reselect_each_cycle=0)), ((8, 9, 10), P(sigmas=[2.0, 1.0])), ((8, 9, 10), P(mode=3)),
+        ((8, 9, 10), P(lam=0.0)), ((8, 9, 10), P(beta=0.0)), ((8, 9, 10), P(cycles=-1)),
+    ]
+    L = m.lib()
+    one = ctypes.c_void_p(16)
+    for (D, H, W), p in bad:
+        assert m.mf4d3d_workspace_bytes(D, H, W, p) == 0
+        st = p.struct()
+        assert L.mf4d3d_filter(one, one, D, H, W, ctypes.byref(st), one, 1 << 40, None) == m.MF4D_EINVAL
+        assert L.mf4d3d_scale_select(one, D, H, W, ctypes.byref(st), one, None, None, one, 1 << 40,
+                                     None) == m.MF4D_EINVAL
+    st = P().struct()
+    nb = m.mf4d3d_workspace_bytes(8, 9, 10, P())
+    assert L.mf4d3d_filter(one, one, 8, 9, 10, ctypes.byref(st), one, nb - 1, None) == m.MF4D_ENOMEM
+    assert L.mf4d3d_filter(None, one, 8, 9, 10, ctypes.byref(st), one, nb, None) == m.MF4D_EINVAL
+    taus = (ctypes.c_double * 2)(0.01, -0.01)
+    assert L.mf4d3d_fed_cycle_tensor(one, 8, 9, 10, one, taus, 2, one, None) == m.MF4D_EINVAL
+    assert L.mf4d3d_fed_cycle_tensor(one, 8, 9, 10, one, taus, 0, one, None) == m.MF4D_EINVAL
+    assert L.mf4d3d_fed_cycle_tensor(one, 8, 9, 10, one, taus, 1, None, None) == m.MF4D_EINVAL
+    # the workspace grows with the volume and the number of scales
+    a = m.mf4d3d_workspace_bytes(16, 16, 16, P())
+    assert m.mf4d3d_workspace_bytes(32, 32, 32, P()) > 7.9 * a
+    assert m.mf4d3d_workspace_bytes(16, 16, 16, P(sigmas=[1.0, 2.0, 3.0])) > a
 
 
 def test_workspace_scales_with_image_and_scales(m):

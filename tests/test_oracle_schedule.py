@@ -99,3 +99,25 @@ def test_kappa_order_beats_natural_by_orders_of_magnitude(oracle_lib):
         natural = np.sort(ordered)
         assert _amplification(ordered, 0.05) < 100.0
         assert _amplification(natural, 0.05) > 1000.0
+
+
+def test_kappa_is_exhaustive_argmin_of_the_amplification(oracle_lib):
+    """Reading A11 pinned exactly: for each n the oracle's kappa is the
+    coprime multiplier of least largest partial product (ties to the smaller
+    kappa), found here by trying every kappa on the same z grid; the derived
+    values kappa = 3, 11, 17 for n = 10, 15, 20 and their amplifications."""
+    for n in list(range(3, 25)) + [30]:
+        ordered, _, k = oracle_lib.fed_schedule(n, 0.05)
+        natural = np.sort(ordered)
+        amps = {}
+        for kk in range(1, n):
+            if math.gcd(kk, n) != 1:
+                continue
+            amps[kk] = _amplification(natural[(kk * np.arange(n)) % n], 0.05, Q=8192)
+        best = min(amps.values())
+        expect = min(kk for kk, a in amps.items() if a <= best * (1 + 1e-9))
+        assert k == expect, (n, k, expect, amps)
+    for n, kappa, amp in [(10, 3, 25.4), (15, 11, 18.6), (20, 17, 56.6)]:
+        ordered, _, k = oracle_lib.fed_schedule(n, 0.05)
+        assert k == kappa
+        assert abs(_amplification(ordered, 0.05, Q=8192) - amp) < 0.05
