@@ -28,6 +28,9 @@ Prints one JSON line:
             algorithmic flops (8 filters x 99 taps x 2 per pixel) against the
             FP32-equivalent peak of split-BF16 products (BF16 peak / 6)
   cpu_baseline  the FP64 oracle on a bounded sample (the first 3 cycles of the same image)
+  extensions  batched_256 (256 uneven images in one batch plan vs per-image
+            calls), learned_2048 (the learned selection vs the exact sweep)
+            and volume_256 (the filter on a 256^3 volume)
 """
 from __future__ import annotations
 
@@ -212,6 +215,55 @@ def batched_comparison(torch, mf4d, synth, dev, reps=2):
             "plain_graph_images_per_s": (len(imgs) / (ms_pg * 1e-3)) if ms_pg else None,
             "speedup_vs_plain_graph": (ms_pg / ms_b) if ms_pg else None,
             "substeps_per_launch": tune[0], "rows_per_wave": tune[1]}
+
+
+# one substep of the volume filter moves u in (4 B), the tensor planes (Q,
+# mu: 48 B) and u out (4 B) per voxel at least; the two-kernel form also
+# writes and reads T (6 planes: 48 B)
+VOLUME_SUBSTEP_BYTES = 56
+VOLUME_SUBSTEP_BYTES_ISSUED = 108
+
+
+def volume_comparison(torch, mf4d, synth, dev, reps=3):
+    """The filter on a 256^3 volume of 24 bright and dark tubes (widths
+    U[1, 3]), 4 scales 1..3.375, both modes, 2 cycles of 10 substeps at
+    tau_max = 1/27: voxel throughput and the substep kernels' HBM rate."""
+    D = H = W = 256
+    t0 = time.time()
+    v = synth.tubes3d(D, H, W, 24, seed=0, signs="mixed", width_range=(1.0, 3.0))
+    print(f"[bench] volume {D}x{H}x{W} generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    sig = [1.5 ** k for k in range(4)]
+    cycles, n = 2, 10
+    p = mf4d.Params(sig, mode=mf4d.MF4D_BOTH, cycles=cycles, substeps=n, tau_max=1.0 / 27.0)
+    ui = torch.from_numpy(v).to(dev)
+    uo = torch.empty_like(ui)
+    ws = mf4d.workspace3(D, H, W, p, dev)
+    run = lambda: mf4d.mf4d3d_filter(ui, uo, p, ws)
+    run()
+    ms = time_stream(torch, run, reps)
+    # the substeps alone, from one cycle's tensor
+    m = D * H * W
+    idx = torch.empty((D, H, W), dtype=torch.uint8, device=dev)
+    hr = torch.empty((6, D, H, W), dtype=torch.float32, device=dev)
+    dp = torch.empty((12, D, H, W), dtype=torch.float32, device=dev)
+    mf4d.mf4d3d_scale_select(ui, p, idx, None, None, ws)
+    mf4d.mf4d3d_tensor(ui, idx, p, hr, dp, ws)
+    taus = mf4d.mf4d_fed_plan(p)[1]
+    uc = ui.clone()
+    ts = torch.empty((6, D, H, W), dtype=torch.float32, device=dev)
+    cyc = lambda: mf4d.mf4d3d_fed_cycle_tensor(uc, dp, taus, ts)
+    cyc()
+    ms_sub = time_stream(torch, cyc, reps) / n
+    t = ms_sub * 1e-3
+    return {"volume": [D, H, W], "scales": sig, "cycles": cycles, "substeps": n,
+            "filter_ms": ms, "Mvoxel_substeps_per_s": m * cycles * n / (ms * 1e-3) / 1e6,
+            "ms_per_substep": ms_sub, "per_cycle_outside_substeps_ms": ms / cycles - n * ms_sub,
+            "substep_roofline": {"bound": "hbm", "achieved": VOLUME_SUBSTEP_BYTES * m / t / 1e9,
+                                 "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                                 "frac": VOLUME_SUBSTEP_BYTES * m / t / HBM_PEAK,
+                                 "bytes_per_voxel": VOLUME_SUBSTEP_BYTES,
+                                 "issued_bytes_per_voxel": VOLUME_SUBSTEP_BYTES_ISSUED,
+                                 "issued_GBs": VOLUME_SUBSTEP_BYTES_ISSUED * m / t / 1e9}}
 
 
 def _pool_image(args):
@@ -511,6 +563,8 @@ def main():
         print(f"[bench] batched: {json.dumps(extensions['batched_256'])}", file=sys.stderr, flush=True)
         extensions["learned_2048"] = learned_comparison(torch, mf4d, synth, dev)
         print(f"[bench] learned: {json.dumps(extensions['learned_2048'])}", file=sys.stderr, flush=True)
+        extensions["volume_256"] = volume_comparison(torch, mf4d, synth, dev)
+        print(f"[bench] volume: {json.dumps(extensions['volume_256'])}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -51,50 +51,53 @@ __device__ __forceinline__ Vox voxel(int D, int H, int W)
 }
 
 // ------------------------------------------------------------------ sweep
-// Pass along x of one scale: X = (G, D1 G, D2 G) u, planes [3][m]. Inputs are
-// shifted by the voxel's own value (constant rows give exact zeros); the
-// Gaussian output adds it back.
-__global__ __launch_bounds__(256) void sweep3_x_kernel(const float *__restrict__ u, float *__restrict__ X, int D,
+// The three separable passes of one scale run z, y, x: the pass with one
+// input reads whole planes apart, the pass with six inputs reads along rows.
+// Inputs are shifted by the voxel's own value (constant lines give exact
+// zeros); each Gaussian output adds it back.
+//
+// Pass along z: Z = (G, D1 G, D2 G) u, planes [3][m].
+__global__ __launch_bounds__(256) void sweep3_z_kernel(const float *__restrict__ u, float *__restrict__ Z, int D,
                                                        int H, int W, WinTaps t)
 {
     const Vox v = voxel(D, H, W);
     if (!v.inside) return;
-    const size_t m = (size_t)D * H * W;
-    const float *row = u + (v.o - v.x);
-    const float ref = row[v.x];
+    const size_t plane = (size_t)H * W, m = plane * D;
+    const size_t pos = v.o - (size_t)v.z * plane;   // voxel (0, y, x)
+    const float ref = u[v.o];
     const int R = t.R;
-    const bool inner = v.x - R >= 0 && v.x + R < W;
+    const bool inner = v.z - R >= 0 && v.z + R < D;
     float g = 0.f, d1 = 0.f, d2 = 0.f;
     for (int k = 0; k <= 2 * R; ++k) {
-        const int xi = inner ? v.x + k - R : sym_index(v.x + k - R, W);
-        const float a = row[xi] - ref;
+        const int zi = inner ? v.z + k - R : sym_index(v.z + k - R, D);
+        const float a = u[pos + (size_t)zi * plane] - ref;
         g = fmaf(t.g[k], a, g);
         d1 = fmaf(t.d1[k], a, d1);
         d2 = fmaf(t.d2[k], a, d2);
     }
-    X[v.o] = g + ref * t.gsum;
-    X[m + v.o] = d1;
-    X[2 * m + v.o] = d2;
+    Z[v.o] = g + ref * t.gsum;
+    Z[m + v.o] = d1;
+    Z[2 * m + v.o] = d2;
 }
 
-// Pass along y: from X0 = G u the outputs (G, D1 G, D2 G), from X1 = D1 u the
-// outputs (G, D1 G), from X2 = D2 u the output G. Y planes [6][m] in the
-// order Y00, Y01, Y02, Y10, Y11, Y20 (first digit: x filter, second: y filter).
-__global__ __launch_bounds__(256) void sweep3_y_kernel(const float *__restrict__ X, float *__restrict__ Y, int D,
+// Pass along y: from Z0 = G u the outputs (G, D1 G, D2 G), from Z1 = D1 u the
+// outputs (G, D1 G), from Z2 = D2 u the output G. Y planes [6][m] in the
+// order Y00, Y01, Y02, Y10, Y11, Y20 (first digit: z filter, second: y filter).
+__global__ __launch_bounds__(256) void sweep3_y_kernel(const float *__restrict__ Z, float *__restrict__ Y, int D,
                                                        int H, int W, WinTaps t)
 {
     const Vox v = voxel(D, H, W);
     if (!v.inside) return;
     const size_t m = (size_t)D * H * W;
     const size_t col = v.o - (size_t)v.y * W;   // voxel (z, 0, x)
-    const float r0 = X[v.o], r1 = X[m + v.o], r2 = X[2 * m + v.o];
+    const float r0 = Z[v.o], r1 = Z[m + v.o], r2 = Z[2 * m + v.o];
     const int R = t.R;
     const bool inner = v.y - R >= 0 && v.y + R < H;
     float a00 = 0.f, a01 = 0.f, a02 = 0.f, a10 = 0.f, a11 = 0.f, a20 = 0.f;
     for (int k = 0; k <= 2 * R; ++k) {
         const int yi = inner ? v.y + k - R : sym_index(v.y + k - R, H);
         const size_t q = col + (size_t)yi * W;
-        const float b0 = X[q] - r0, b1 = X[m + q] - r1, b2 = X[2 * m + q] - r2;
+        const float b0 = Z[q] - r0, b1 = Z[m + q] - r1, b2 = Z[2 * m + q] - r2;
         a00 = fmaf(t.g[k], b0, a00);
         a01 = fmaf(t.d1[k], b0, a01);
         a02 = fmaf(t.d2[k], b0, a02);
@@ -110,54 +113,29 @@ __global__ __launch_bounds__(256) void sweep3_y_kernel(const float *__restrict__
     Y[5 * m + v.o] = a20 + r2 * t.gsum;
 }
 
-// Eigenpairs of a symmetric 3 x 3 matrix by cyclic Jacobi rotations in
-// double: on return a[k][k] are the eigenvalues and column k of q (when
-// `vectors`) the unit eigenvector of a[k][k]. Every index is a compile-time
-// constant, so a and q stay in registers.
-template <int P, int Q>
-__device__ __forceinline__ void jacobi_rotate(double (&a)[3][3], double (&q)[3][3], bool vectors)
+// Eigenvalues of the symmetric 3 x 3 matrix (a00, a11, a22, a01, a02, a12)
+// in descending order, from the trigonometric solution of its characteristic
+// cubic in double: with q = tr/3, B = A - q I, p^2 = |B|_F^2 / 6 and
+// r = det(B) / 2p^3, the roots are q + 2p cos(acos(r)/3 + 2 pi k/3). The
+// error is a few ulp of |A| (about 1e-8 |A| where two roots nearly
+// coincide), far below that of the float32 Hessian.
+__device__ __forceinline__ void sym3_eigenvalues(double a00, double a11, double a22, double a01, double a02,
+                                                 double a12, double &e0, double &e1, double &e2)
 {
-    const double apq = a[P][Q];
-    if (apq == 0.0) return;
-    const double th = (a[Q][Q] - a[P][P]) / (2.0 * apq);
-    const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(fma(th, th, 1.0)));
-    const double c = 1.0 / sqrt(fma(t, t, 1.0)), s = t * c;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {   // columns P, Q of a
-        const double akp = a[k][P], akq = a[k][Q];
-        a[k][P] = c * akp - s * akq;
-        a[k][Q] = s * akp + c * akq;
+    const double q = (a00 + a11 + a22) / 3.0;
+    const double b00 = a00 - q, b11 = a11 - q, b22 = a22 - q;
+    const double p2 = (b00 * b00 + b11 * b11 + b22 * b22 + 2.0 * (a01 * a01 + a02 * a02 + a12 * a12)) / 6.0;
+    if (!(p2 > 0.0)) {
+        e0 = e1 = e2 = q;
+        return;
     }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {   // rows P, Q of a
-        const double apk = a[P][k], aqk = a[Q][k];
-        a[P][k] = c * apk - s * aqk;
-        a[Q][k] = s * apk + c * aqk;
-    }
-    if (vectors) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const double qkp = q[k][P], qkq = q[k][Q];
-            q[k][P] = c * qkp - s * qkq;
-            q[k][Q] = s * qkp + c * qkq;
-        }
-    }
-}
-
-__device__ __forceinline__ void jacobi3(double (&a)[3][3], double (&q)[3][3], bool vectors)
-{
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) q[i][j] = i == j ? 1.0 : 0.0;
-    for (int sweep = 0; sweep < 10; ++sweep) {
-        const double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
-        const double dia = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
-        if (!(off > 1e-34 * dia)) break;   // also ends on an all-zero matrix
-        jacobi_rotate<0, 1>(a, q, vectors);
-        jacobi_rotate<0, 2>(a, q, vectors);
-        jacobi_rotate<1, 2>(a, q, vectors);
-    }
+    const double p = sqrt(p2);
+    const double det = b00 * (b11 * b22 - a12 * a12) - a01 * (a01 * b22 - a12 * a02) + a02 * (a01 * a12 - b11 * a02);
+    const double r = fmin(1.0, fmax(-1.0, det / (2.0 * p2 * p)));
+    const double phi = acos(r) / 3.0;
+    e0 = q + 2.0 * p * cos(phi);
+    e2 = q + 2.0 * p * cos(phi + 2.0943951023931957);   // + 2 pi / 3
+    e1 = 3.0 * q - e0 - e2;
 }
 
 __device__ __forceinline__ void swap_if(double &a, double &b, bool c)
@@ -176,9 +154,8 @@ __device__ __forceinline__ void swap_if(double &a, double &b, bool c)
 __device__ __forceinline__ double tube_factor(double h00, double h11, double h22, double h01, double h02,
                                               double h12, int mode, double inv2beta2)
 {
-    double a[3][3] = {{h00, h01, h02}, {h01, h11, h12}, {h02, h12, h22}}, q[3][3];
-    jacobi3(a, q, false);
-    double e0 = a[0][0], e1 = a[1][1], e2 = a[2][2];
+    double e0, e1, e2;
+    sym3_eigenvalues(h00, h11, h22, h01, h02, h12, e0, e1, e2);
     swap_if(e0, e1, e1 > e0);   // descending
     swap_if(e0, e2, e2 > e0);
     swap_if(e1, e2, e2 > e1);
@@ -193,11 +170,11 @@ __device__ __forceinline__ double tube_factor(double h00, double h11, double h22
     return (1.0 - exp(-(ra * ra) / (2.0 * kAlpha3 * kAlpha3))) * exp(-rb2 * inv2beta2);
 }
 
-// Pass along z and the per-voxel outputs of one scale: the gradient and
+// Pass along x and the per-voxel outputs of one scale: the gradient and
 // Hessian of u_sigma, S = |sigma^2 H|_F and the tube factor F (SF [m] pairs),
 // N = H / sqrt(1 + |grad u_sigma|) (planes xx, yy, zz, xy, xz, yz), and the
 // largest S into *smax_bits.
-__global__ __launch_bounds__(256) void sweep3_z_kernel(const float *__restrict__ Y, float2 *__restrict__ SF,
+__global__ __launch_bounds__(256) void sweep3_x_kernel(const float *__restrict__ Y, float2 *__restrict__ SF,
                                                        float *__restrict__ N, unsigned *__restrict__ smax_bits,
                                                        int D, int H, int W, WinTaps t, float sigma2, int mode,
                                                        double inv2beta2)
@@ -205,35 +182,35 @@ __global__ __launch_bounds__(256) void sweep3_z_kernel(const float *__restrict__
     const Vox v = voxel(D, H, W);
     float Sv = 0.f;
     if (v.inside) {
-        const size_t plane = (size_t)H * W, m = plane * D;
-        const size_t pos = v.o - (size_t)v.z * plane;   // voxel (0, y, x)
+        const size_t m = (size_t)D * H * W;
+        const size_t row = v.o - v.x;   // voxel (z, y, 0)
         float r[6];
 #pragma unroll
         for (int j = 0; j < 6; ++j) r[j] = Y[j * m + v.o];
         const int R = t.R;
-        const bool inner = v.z - R >= 0 && v.z + R < D;
+        const bool inner = v.x - R >= 0 && v.x + R < W;
         float gx = 0.f, gy = 0.f, gz = 0.f, hxx = 0.f, hyy = 0.f, hzz = 0.f, hxy = 0.f, hxz = 0.f, hyz = 0.f;
         for (int k = 0; k <= 2 * R; ++k) {
-            const int zi = inner ? v.z + k - R : sym_index(v.z + k - R, D);
-            const size_t q = pos + (size_t)zi * plane;
+            const int xi = inner ? v.x + k - R : sym_index(v.x + k - R, W);
+            const size_t q = row + xi;
             const float b00 = Y[q] - r[0], b01 = Y[m + q] - r[1], b02 = Y[2 * m + q] - r[2];
             const float b10 = Y[3 * m + q] - r[3], b11 = Y[4 * m + q] - r[4], b20 = Y[5 * m + q] - r[5];
             const float g = t.g[k], d1 = t.d1[k], d2 = t.d2[k];
-            gz = fmaf(d1, b00, gz);
-            hzz = fmaf(d2, b00, hzz);
+            gx = fmaf(d1, b00, gx);
+            hxx = fmaf(d2, b00, hxx);
             gy = fmaf(g, b01, gy);
-            hyz = fmaf(d1, b01, hyz);
+            hxy = fmaf(d1, b01, hxy);
             hyy = fmaf(g, b02, hyy);
-            gx = fmaf(g, b10, gx);
+            gz = fmaf(g, b10, gz);
             hxz = fmaf(d1, b10, hxz);
-            hxy = fmaf(g, b11, hxy);
-            hxx = fmaf(g, b20, hxx);
+            hyz = fmaf(g, b11, hyz);
+            hzz = fmaf(g, b20, hzz);
         }
         gy += r[1] * t.gsum;
         hyy += r[2] * t.gsum;
-        gx += r[3] * t.gsum;
-        hxy += r[4] * t.gsum;
-        hxx += r[5] * t.gsum;
+        gz += r[3] * t.gsum;
+        hyz += r[4] * t.gsum;
+        hzz += r[5] * t.gsum;
         const double s2 = sigma2;
         const double a00 = s2 * hxx, a11 = s2 * hyy, a22 = s2 * hzz, a01 = s2 * hxy, a02 = s2 * hxz, a12 = s2 * hyz;
         const double S = sqrt(a00 * a00 + a11 * a11 + a22 * a22 + 2.0 * (a01 * a01 + a02 * a02 + a12 * a12));
@@ -332,6 +309,87 @@ __global__ __launch_bounds__(256) void rho3_kernel(const float *__restrict__ in,
 }
 
 // ----------------------------------------------------------------- tensor
+__device__ __forceinline__ void cross3(const double *a, const double *b, double *c)
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+__device__ __forceinline__ double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+// Eigenpairs of the symmetric 3 x 3 matrix A (FP64): the eigenvalues from
+// the cubic; the eigenvector of the root farthest from the middle one (a
+// simple root unless all three coincide) as the longest cross product of two
+// rows of A - lambda I; the other two from the symmetric 2 x 2 restriction of
+// A to the plane orthogonal to it (rotation angle from atan2), which stays
+// well defined when those two roots coincide. nu[k] and column k of q.
+__device__ __forceinline__ void sym3_eigenpairs(const double (&A)[3][3], double (&nu)[3], double (&q)[3][3])
+{
+    double e0, e1, e2;
+    sym3_eigenvalues(A[0][0], A[1][1], A[2][2], A[0][1], A[0][2], A[1][2], e0, e1, e2);
+    const bool top = (e0 - e1) >= (e1 - e2);
+    const double lam = top ? e0 : e2;
+    double r0[3] = {A[0][0] - lam, A[0][1], A[0][2]};
+    double r1[3] = {A[1][0], A[1][1] - lam, A[1][2]};
+    double r2[3] = {A[2][0], A[2][1], A[2][2] - lam};
+    double c01[3], c02[3], c12[3];
+    cross3(r0, r1, c01);
+    cross3(r0, r2, c02);
+    cross3(r1, r2, c12);
+    const double n01 = dot3(c01, c01), n02 = dot3(c02, c02), n12 = dot3(c12, c12);
+    double v[3];
+    double nb = n01;
+    v[0] = c01[0], v[1] = c01[1], v[2] = c01[2];
+    if (n02 > nb) nb = n02, v[0] = c02[0], v[1] = c02[1], v[2] = c02[2];
+    if (n12 > nb) nb = n12, v[0] = c12[0], v[1] = c12[1], v[2] = c12[2];
+    double amax = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) amax = fmax(amax, fabs(A[i][j]));
+    if (!(nb > 1e-56 * amax * amax * amax * amax)) {
+        // all roots equal to working accuracy: any orthonormal basis
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            nu[i] = A[i][i];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) q[i][k] = i == k ? 1.0 : 0.0;
+        }
+        return;
+    }
+    const double inv = 1.0 / sqrt(nb);
+    v[0] *= inv, v[1] *= inv, v[2] *= inv;
+    // orthonormal basis (a, b) of the plane orthogonal to v
+    double ax[3] = {0.0, 0.0, 0.0};
+    ax[fabs(v[0]) < 0.6 ? 0 : 1] = 1.0;
+    double a[3], b[3];
+    cross3(v, ax, a);
+    const double ia = 1.0 / sqrt(dot3(a, a));
+    a[0] *= ia, a[1] *= ia, a[2] *= ia;
+    cross3(v, a, b);
+    double Aa[3], Ab[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        Aa[i] = A[i][0] * a[0] + A[i][1] * a[1] + A[i][2] * a[2];
+        Ab[i] = A[i][0] * b[0] + A[i][1] * b[1] + A[i][2] * b[2];
+    }
+    const double saa = dot3(a, Aa), sab = dot3(a, Ab), sbb = dot3(b, Ab);
+    const double th = 0.5 * atan2(2.0 * sab, saa - sbb);
+    const double c = cos(th), sn = sin(th);
+    const double mid = 0.5 * (saa + sbb), rad = sqrt(0.25 * (saa - sbb) * (saa - sbb) + sab * sab);
+    const int kv = top ? 0 : 2, k1 = top ? 1 : 0, k2 = top ? 2 : 1;
+    nu[kv] = lam;
+    nu[k1] = mid + rad;
+    nu[k2] = mid - rad;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        q[i][kv] = v[i];
+        q[i][k1] = c * a[i] + sn * b[i];
+        q[i][k2] = -sn * a[i] + c * b[i];
+    }
+}
+
 // Eigenpairs (nu_k, e_k) of H_rho in FP64 and mu_k of Eq. (7) with the mode
 // masks: planes [12][m] = Q (row-major, Q[3 i + k] = component i of e_k),
 // then mu_0, mu_1, mu_2.
@@ -343,18 +401,18 @@ __global__ __launch_bounds__(256) void eig3_kernel(const float *__restrict__ hr,
     const size_t m = (size_t)D * H * W;
     const double hxx = hr[v.o], hyy = hr[m + v.o], hzz = hr[2 * m + v.o];
     const double hxy = hr[3 * m + v.o], hxz = hr[4 * m + v.o], hyz = hr[5 * m + v.o];
-    double a[3][3] = {{hxx, hxy, hxz}, {hxy, hyy, hyz}, {hxz, hyz, hzz}}, q[3][3];
-    jacobi3(a, q, true);
+    const double a[3][3] = {{hxx, hxy, hxz}, {hxy, hyy, hyz}, {hxz, hyz, hzz}};
+    double nu[3], q[3][3];
+    sym3_eigenpairs(a, nu, q);
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int k = 0; k < 3; ++k) tens[(3 * i + k) * m + v.o] = (float)q[i][k];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const double nu = a[k][k];
-        double mu = 1.0 / (1.0 + nu * nu * inv_lam2);
-        if (mode == MF4D_RIDGE && nu >= 0.0) mu = 1.0;
-        if (mode == MF4D_VALLEY && nu <= 0.0) mu = 1.0;
+        double mu = 1.0 / (1.0 + nu[k] * nu[k] * inv_lam2);
+        if (mode == MF4D_RIDGE && nu[k] >= 0.0) mu = 1.0;
+        if (mode == MF4D_VALLEY && nu[k] <= 0.0) mu = 1.0;
         tens[(9 + k) * m + v.o] = (float)mu;
     }
 }
@@ -474,7 +532,7 @@ int validate3(int D, int H, int W, const mf4d_params *p)
 }
 
 struct Work3 {
-    float *X, *Y;        // pass planes [3][m], [6][m]
+    float *X, *Y;        // planes of the z pass [3][m] and the y pass [6][m]
     float2 *SF;          // [ns][m]
     float *N;            // [ns][6][m]
     uint8_t *idx;
@@ -528,11 +586,11 @@ int sweep3(const float *u, int D, int H, int W, const mf4d_params *p, const Work
         WinTaps t;
         window_taps(p->sigmas[k], &t);
         const float sigma2 = p->sigmas[k] * p->sigmas[k];
-        sweep3_x_kernel<<<g, kBlock3, 0, s>>>(u, w.X, D, H, W, t);
+        sweep3_z_kernel<<<g, kBlock3, 0, s>>>(u, w.X, D, H, W, t);
         CHECK_LAUNCH();
         sweep3_y_kernel<<<g, kBlock3, 0, s>>>(w.X, w.Y, D, H, W, t);
         CHECK_LAUNCH();
-        sweep3_z_kernel<<<g, kBlock3, 0, s>>>(w.Y, w.SF + k * m, w.N + (size_t)k * 6 * m, w.smax, D, H, W, t,
+        sweep3_x_kernel<<<g, kBlock3, 0, s>>>(w.Y, w.SF + k * m, w.N + (size_t)k * 6 * m, w.smax, D, H, W, t,
                                               sigma2, p->mode, inv2beta2);
         CHECK_LAUNCH();
     }
