@@ -1,6 +1,7 @@
 #!/bin/bash
 # Mutation check of the FP64 oracle (CPU only, not collected by pytest).
-# Plants one mistake at a time in a scratch copy of oracle/mf4d_oracle.c and
+# Plants one mistake at a time in a scratch copy of the oracle's C sources
+# (entries "file::sed-expression"; a bare expression means mf4d_oracle.c) and
 # runs the oracle's pin tests on it; each mistake should make a pin fail.
 # Usage: bash tests/oracle_mutations.sh   (from the repository root)
 set -u
@@ -29,16 +30,32 @@ muts=(
  's|if (!(vmax\[q\] >= theta)) break;|if (!(vmax[q] >= theta)) continue;|'
  's|if (d < bd) { bd = d; best = s; }|if (d <= bd) { bd = d; best = s; }|'
  's|for (int t = 1; t <= tmax; ++t) {|for (int t = 1; t < tmax; ++t) {|'
+ 'crease_oracle.c::s|return m < 0.0 ? 1 : -1;|return m > 0.0 ? 1 : -1;|'
+ 'crease_oracle.c::s|return m > 0.0 ? q <= 0.0 : q >= 0.0;|return m > 0.0 ? q >= 0.0 : q <= 0.0;|'
+ 'crease_oracle.c::s|double tt = dc\[a\] / (dc\[a\] - dc\[b\]);|double tt = 0.5;|'
+ 'crease_oracle.c::s|if (t > 1.0) t = 1.0;|if (t > 2.0) t = 2.0;|'
+ 'mf4d3d_oracle.c::s|out\[6 \* m + c\] = (v\[IX(z, ym, xm)\] + v\[IX(z, yp, xp)\] - v\[IX(z, yp, xm)\] - v\[IX(z, ym, xp)\]) / 4.0;|out[6 * m + c] = (v[IX(z, ym, xm)] + v[IX(z, yp, xp)] - v[IX(z, yp, xm)] - v[IX(z, ym, xp)]) / 2.0;|'
+ 'mf4d3d_oracle.c::s|double RB = fabs(n\[0\]) / sqrt(fabs(n\[1\] \* n\[2\]));|double RB = fabs(n[0]) / fabs(n[2]);|'
+ 'mf4d3d_oracle.c::s|double w = (i == j) ? mu\[i\] : 0.5 \* (mu\[i\] + mu\[j\]);|double w = (i == j) ? mu[i] : mu[i];|'
+ 'mf4d3d_oracle.c::s|const double rs2 = 1.0 / sqrt(2.0);|const double rs2 = 1.0;|'
+ 'mf4d3d_oracle.c::s|if (mode == RIDGE3 \&\& (n\[1\] > 0.0 \|\| n\[2\] > 0.0)) return 0.0;|if (mode == RIDGE3 \&\& (n[1] < 0.0 \|\| n[2] < 0.0)) return 0.0;|'
+ 'mf4d3d_oracle.c::s|double a = tp\[k == 0 ? 1 : 3\] / 4.0;|double a = tp[k == 0 ? 1 : 3] / 2.0;|'
+ 'mf4d3d_oracle.c::s|if (fabs(n\[j\]) < fabs(n\[i\]))|if (n[j] < n[i])|'
+ 'mf4d3d_oracle.c::s|double c = c_param > 0.0 ? c_param : 0.5 \* smax;|double c = c_param > 0.0 ? c_param : smax;|'
+ 'mf4d3d_oracle.c::s|double gn = sqrt(der\[p\] \* der\[p\] + der\[m + p\] \* der\[m + p\] + der\[2 \* m + p\] \* der\[2 \* m + p\]);|double gn = sqrt(der[p] * der[p] + der[m + p] * der[m + p]);|'
+ 'mf4d3d_oracle.c::s|R(z - 1, y, x) += tp\[8\]; R(z, y, x) -= 2.0 \* tp\[8\]; R(z + 1, y, x) += tp\[8\];|R(z - 1, y, x) += tp[8]; R(z, y, x) -= 2.0 * tp[8]; R(z + 1, y, x) += tp[4];|'
 )
-pins="tests/test_oracle_schedule.py tests/test_oracle_scalespace.py tests/test_oracle_tensor_operator.py tests/test_oracle_filter.py tests/test_oracle_ext.py"
+pins="tests/test_oracle_schedule.py tests/test_oracle_scalespace.py tests/test_oracle_tensor_operator.py tests/test_oracle_filter.py tests/test_oracle_ext.py tests/test_oracle_crease.py tests/test_oracle_3d.py"
 i=0
 for m in "${muts[@]}"; do
   i=$((i+1)); d=$(mktemp -d)
   cp -r "$root/oracle" "$root/tests" "$root/paper_1611_06906_amd" "$d/"
   rm -f "$d"/oracle/*.so
-  sed -i "$m" "$d/oracle/mf4d_oracle.c"
-  if cmp -s "$d/oracle/mf4d_oracle.c" "$root/oracle/mf4d_oracle.c"; then echo "MUT $i: pattern did not apply"; continue; fi
+  f=mf4d_oracle.c; e=$m
+  case "$m" in *.c::*) f=${m%%::*}; e=${m#*::};; esac
+  sed -i "$e" "$d/oracle/$f"
+  if cmp -s "$d/oracle/$f" "$root/oracle/$f"; then echo "MUT $i ($f): pattern did not apply"; rm -rf "$d"; continue; fi
   (cd "$d" && timeout 300 python -m pytest $pins -x -q -p no:cacheprovider > log 2>&1); rc=$?
-  if [ $rc -eq 0 ]; then echo "MUT $i: not caught"; else echo "MUT $i: caught by $(grep -m1 -o 'FAILED [^ ]*' "$d/log")"; fi
+  if [ $rc -eq 0 ]; then echo "MUT $i ($f): not caught"; else echo "MUT $i ($f): caught by $(grep -m1 -o 'FAILED [^ ]*' "$d/log")"; fi
   rm -rf "$d"
 done

@@ -120,6 +120,27 @@ def test_vesselness3_suppresses_plates_and_blobs(oracle_lib):
     assert math.isclose(S2, S_tube, rel_tol=1e-12) and math.isclose(v2, tube, rel_tol=1e-12)
 
 
+def test_vesselness3_general_closed_form(oracle_lib):
+    """Three distinct eigenvalues in a rotated frame: V equals Frangi's
+    formula evaluated by hand on the known eigenvalues (R_A = |n2|/|n3|,
+    R_B = |n1| / sqrt|n2 n3|), in every mode."""
+    rng = np.random.default_rng(11)
+    Q = np.linalg.qr(rng.normal(size=(3, 3)))[0]
+    for ev, ok in [((-0.2, -0.5, -1.0), (True, False, True)), ((0.3, 0.6, -0.9), (False, False, True)),
+                   ((0.1, 0.4, 0.8), (False, True, True))]:
+        A = Q @ np.diag(ev) @ Q.T
+        h = [A[0, 0], A[1, 1], A[2, 2], A[0, 1], A[0, 2], A[1, 2]]
+        n = sorted(ev, key=abs)
+        S = math.sqrt(sum(x * x for x in ev))
+        c = 0.7
+        ra, rb = abs(n[1]) / abs(n[2]), abs(n[0]) / math.sqrt(abs(n[1] * n[2]))
+        want = (1 - math.exp(-ra * ra / 0.5)) * math.exp(-rb * rb / 0.5) * (1 - math.exp(-S * S / (2 * c * c)))
+        for mode in (0, 1, 2):
+            v, S_out = oracle_lib.vesselness3_px(h, 1.0, mode, c)
+            assert math.isclose(S_out, S, rel_tol=1e-12)
+            assert math.isclose(v, want if ok[mode] else 0.0, rel_tol=1e-10, abs_tol=1e-15), (ev, mode)
+
+
 def _vec(A):
     return A.reshape(9)
 
