@@ -11,9 +11,10 @@
  * ---------------------------------------
  *  - Images are contiguous row-major float32 [H][W] in DEVICE memory, x = column
  *    (the paper's index i), y = row (index j), pixel spacing 1. The caller owns
- *    all buffers; the library never allocates or frees caller memory and keeps
- *    no device memory of its own. Scratch space comes from a caller-provided
- *    device workspace of at least mf4d_workspace_bytes() bytes.
+ *    all buffers; the library never allocates or frees caller memory. Scratch
+ *    space comes from a caller-provided device workspace of at least
+ *    mf4d_workspace_bytes() bytes; the one exception is mf4d_filter_noalloc,
+ *    whose scratch is a fixed array the library keeps on each GPU.
  *  - mf4d_params, its sigmas array and all double* schedule arrays are HOST
  *    memory; they are read during the call only.
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
@@ -375,27 +376,29 @@ int mf4d3d_scale_select(const float *u, int D, int H, int W, const mf4d_params *
 /* Normalised, integrated Hessian at the scales idx (device uint8
  * [D][H][W], values >= nscales clamped to nscales - 1).
  *   hrho_out    device float32 [6][D][H][W]: xx, yy, zz, xy, xz, yz.
- *   dparams_out device float32 [12][D][H][W] (nullable): the tensor as
+ *   dparams_out device float32 [D][H][W][12] (nullable): the tensor as
  *               mf4d3d_dtensor writes it.
  * Errors as mf4d3d_scale_select. */
 int mf4d3d_tensor(const float *u, int D, int H, int W, const uint8_t *idx, const mf4d_params *p, float *hrho_out,
                   float *dparams_out, void *ws, size_t ws_bytes, void *stream);
 
 /* The tensor of each voxel from its H_rho (device float32 [6][D][H][W]):
- * dparams_out device float32 [12][D][H][W], planes 3 i + k = component i of
- * the unit eigenvector e_k (k = 0..2), then mu_0, mu_1, mu_2 (lambda and mode
- * from p). Errors: MF4D_EINVAL, MF4D_EHIP. */
+ * dparams_out device float32 [D][H][W][12], 12 values per voxel (16-byte
+ * aligned base): entry 3 i + k = component i of the unit eigenvector e_k
+ * (k = 0..2), then mu_0, mu_1, mu_2 (lambda and mode from p).
+ * Errors: MF4D_EINVAL (also for a base not 16-byte aligned), MF4D_EHIP. */
 int mf4d3d_dtensor(const float *hrho, int D, int H, int W, const mf4d_params *p, float *dparams_out, void *stream);
 
-/* n FED substeps (Eq. (21)) u <- u - tau_i L^T D L u in place, with D from
- * dparams (as mf4d3d_dtensor writes it); taus host, n doubles in the order
- * applied (each cast to float32).
- *   u          device float32 [D][H][W], in/out.
- *   t_scratch  device float32 [6][D][H][W]: T = D L u of the current substep.
- * Errors: MF4D_EINVAL (sizes, NULL, n outside [1, MF4D_MAX_SUBSTEPS], a tau
- * not positive and finite), MF4D_EHIP. */
-int mf4d3d_fed_cycle_tensor(float *u, int D, int H, int W, const float *dparams, const double *taus, int n,
-                            float *t_scratch, void *stream);
+/* n FED substeps (Eq. (21)) u <- u - tau_i L^T D L u, with D from dparams
+ * (device float32 [D][H][W][12] as mf4d3d_dtensor writes it, 16-byte
+ * aligned); taus host, n doubles in the order applied (each cast to
+ * float32).
+ *   u      device float32 [D][H][W], in/out: the result always lands here.
+ *   u_tmp  device float32 [D][H][W] scratch (must not alias u).
+ * Errors: MF4D_EINVAL (sizes, NULL, aliasing, n outside
+ * [1, MF4D_MAX_SUBSTEPS], a tau not positive and finite), MF4D_EHIP. */
+int mf4d3d_fed_cycle_tensor(float *u, float *u_tmp, int D, int H, int W, const float *dparams, const double *taus,
+                            int n, void *stream);
 
 /* The whole filter on a volume: M cycles of scale selection, integrated
  * Hessian, tensor and n FED substeps (the schedule of mf4d_fed_plan).

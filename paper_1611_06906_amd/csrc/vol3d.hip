@@ -391,8 +391,8 @@ __device__ __forceinline__ void sym3_eigenpairs(const double (&A)[3][3], double 
 }
 
 // Eigenpairs (nu_k, e_k) of H_rho in FP64 and mu_k of Eq. (7) with the mode
-// masks: planes [12][m] = Q (row-major, Q[3 i + k] = component i of e_k),
-// then mu_0, mu_1, mu_2.
+// masks: 12 values per voxel ([m][12], the substep reads them together) = Q
+// (row-major, Q[3 i + k] = component i of e_k), then mu_0, mu_1, mu_2.
 __global__ __launch_bounds__(256) void eig3_kernel(const float *__restrict__ hr, float *__restrict__ tens, int mode,
                                                    double inv_lam2, int D, int H, int W)
 {
@@ -404,56 +404,47 @@ __global__ __launch_bounds__(256) void eig3_kernel(const float *__restrict__ hr,
     const double a[3][3] = {{hxx, hxy, hxz}, {hxy, hyy, hyz}, {hxz, hyz, hzz}};
     double nu[3], q[3][3];
     sym3_eigenpairs(a, nu, q);
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) tens[(3 * i + k) * m + v.o] = (float)q[i][k];
+    float mu[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        double mu = 1.0 / (1.0 + nu[k] * nu[k] * inv_lam2);
-        if (mode == MF4D_RIDGE && nu[k] >= 0.0) mu = 1.0;
-        if (mode == MF4D_VALLEY && nu[k] <= 0.0) mu = 1.0;
-        tens[(9 + k) * m + v.o] = (float)mu;
+        double mk = 1.0 / (1.0 + nu[k] * nu[k] * inv_lam2);
+        if (mode == MF4D_RIDGE && nu[k] >= 0.0) mk = 1.0;
+        if (mode == MF4D_VALLEY && nu[k] <= 0.0) mk = 1.0;
+        mu[k] = (float)mk;
     }
+    float4 *p = (float4 *)(tens + 12 * v.o);
+    p[0] = make_float4((float)q[0][0], (float)q[0][1], (float)q[0][2], (float)q[1][0]);
+    p[1] = make_float4((float)q[1][1], (float)q[1][2], (float)q[2][0], (float)q[2][1]);
+    p[2] = make_float4((float)q[2][2], mu[0], mu[1], mu[2]);
 }
 
 // ---------------------------------------------------------------- substep
-// T = D h at interior voxels (0 elsewhere): h the second differences of u
-// (cross stencils for the mixed terms), D h = Q (M o (Q^T h Q)) Q^T with
-// M_kk = mu_k and M_kl = (mu_k + mu_l) / 2 -- the action of the eigentensor
-// expansion on a symmetric h (the antisymmetric eigentensors have weight 0).
-// T planes [6][m]: xx, yy, zz, xy, xz, yz.
-__global__ __launch_bounds__(256) void tens3_kernel(const float *__restrict__ u, const float *__restrict__ tens,
-                                                    float *__restrict__ T, int D, int H, int W)
+// One FED substep u_out = u_in - tau L^T T, T = D h, fused: a workgroup owns
+// a tile of 32 x 8 output columns (x, y) and marches along z over a segment
+// of planes. For each output plane z it loads u plane z + 2 of the tile with
+// a 2-voxel xy halo into an LDS ring of three planes, forms T of plane z + 1
+// on the tile with a 1-voxel halo into a ring of three T planes (one thread
+// per T position, its 12 tensor values loaded one plane ahead), and then
+// gathers L^T T at plane z. T is D h at interior voxels and 0 elsewhere
+// (also outside the volume), h the second differences of u (cross stencils
+// for the mixed terms), D h = Q (M o (Q^T h Q)) Q^T with M_kk = mu_k and
+// M_kl = (mu_k + mu_l) / 2. Neighbouring tiles recompute their shared halo,
+// so u_out must not alias u_in.
+constexpr int kFX = 32, kFY = 8;                  // output tile
+constexpr int kTX = kFX + 2, kTY = kFY + 2;       // T region
+constexpr int kUX = kFX + 4, kUY = kFY + 4;       // u region
+constexpr int kZSeg = 64;                         // planes per workgroup
+constexpr int kFThreads = 384;                    // >= the T region's 340 positions
+
+__device__ __forceinline__ void tensor_action(const float (&h)[3][3], const float (&tq)[12], float (&T)[6])
 {
-    const Vox v = voxel(D, H, W);
-    if (!v.inside) return;
-    const size_t plane = (size_t)H * W, m = plane * D;
-    const size_t o = v.o;
-    if (v.x < 1 || v.x > W - 2 || v.y < 1 || v.y > H - 2 || v.z < 1 || v.z > D - 2) {
-#pragma unroll
-        for (int k = 0; k < 6; ++k) T[k * m + o] = 0.f;
-        return;
-    }
-    const size_t sy = W, sz = plane;
-    const float c2 = 2.f * u[o];
-    float h[3][3];
-    h[0][0] = u[o - 1] - c2 + u[o + 1];
-    h[1][1] = u[o - sy] - c2 + u[o + sy];
-    h[2][2] = u[o - sz] - c2 + u[o + sz];
-    h[0][1] = 0.25f * ((u[o - sy - 1] + u[o + sy + 1]) - (u[o + sy - 1] + u[o - sy + 1]));
-    h[0][2] = 0.25f * ((u[o - sz - 1] + u[o + sz + 1]) - (u[o + sz - 1] + u[o - sz + 1]));
-    h[1][2] = 0.25f * ((u[o - sz - sy] + u[o + sz + sy]) - (u[o + sz - sy] + u[o - sz + sy]));
-    h[1][0] = h[0][1];
-    h[2][0] = h[0][2];
-    h[2][1] = h[1][2];
     float q[3][3], mu[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) q[i][k] = tens[(3 * i + k) * m + o];
+        for (int k = 0; k < 3; ++k) q[i][k] = tq[3 * i + k];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) mu[k] = tens[(9 + k) * m + o];
+    for (int k = 0; k < 3; ++k) mu[k] = tq[9 + k];
     // B = h Q, A = Q^T B (in the eigenbasis), weighted by M
     float B[3][3], A[3][3];
 #pragma unroll
@@ -464,8 +455,8 @@ __global__ __launch_bounds__(256) void tens3_kernel(const float *__restrict__ u,
     for (int k = 0; k < 3; ++k)
 #pragma unroll
         for (int l = k; l < 3; ++l) {
-            const float s = q[0][k] * B[0][l] + q[1][k] * B[1][l] + q[2][k] * B[2][l];
-            A[k][l] = (k == l ? mu[k] : 0.5f * (mu[k] + mu[l])) * s;
+            const float sv = q[0][k] * B[0][l] + q[1][k] * B[1][l] + q[2][k] * B[2][l];
+            A[k][l] = (k == l ? mu[k] : 0.5f * (mu[k] + mu[l])) * sv;
             A[l][k] = A[k][l];
         }
     // T = Q A Q^T
@@ -475,36 +466,118 @@ __global__ __launch_bounds__(256) void tens3_kernel(const float *__restrict__ u,
 #pragma unroll
         for (int l = 0; l < 3; ++l) C[i][l] = q[i][0] * A[0][l] + q[i][1] * A[1][l] + q[i][2] * A[2][l];
     auto Tij = [&](int i, int j) { return C[i][0] * q[j][0] + C[i][1] * q[j][1] + C[i][2] * q[j][2]; };
-    T[o] = Tij(0, 0);
-    T[m + o] = Tij(1, 1);
-    T[2 * m + o] = Tij(2, 2);
-    T[3 * m + o] = Tij(0, 1);
-    T[4 * m + o] = Tij(0, 2);
-    T[5 * m + o] = Tij(1, 2);
+    T[0] = Tij(0, 0);
+    T[1] = Tij(1, 1);
+    T[2] = Tij(2, 2);
+    T[3] = Tij(0, 1);
+    T[4] = Tij(0, 2);
+    T[5] = Tij(1, 2);
 }
 
-// u -= tau L^T T in place: the transposed stencils gather T from the
-// neighbours (T is zero off the interior; neighbours outside the volume
-// contribute nothing). The cross stencils enter twice (xy and yx), each with
-// weight 1/4.
-__global__ __launch_bounds__(256) void upd3_kernel(float *__restrict__ u, const float *__restrict__ T, float tau, int D,
-                                                   int H, int W)
+__global__ __launch_bounds__(kFThreads) void fed3_kernel(const float *__restrict__ u, float *__restrict__ uo,
+                                                   const float *__restrict__ tens, float tau, int D, int H, int W,
+                                                   int tiles_x, int tiles_y)
 {
-    const Vox v = voxel(D, H, W);
-    if (!v.inside) return;
+    __shared__ float su[3][kUY][kUX];
+    __shared__ float sT[3][6][kTY][kTX];
+    const int tid = threadIdx.x;
+    const int b = blockIdx.x;
+    const int tx = b % tiles_x, ty = (b / tiles_x) % tiles_y, zs = b / (tiles_x * tiles_y);
+    const int x0 = tx * kFX, y0 = ty * kFY, z0 = zs * kZSeg, z1 = min(D, z0 + kZSeg);
     const size_t plane = (size_t)H * W, m = plane * D;
-    auto at = [&](int k, int dz, int dy, int dx) -> float {
-        const int z = v.z + dz, y = v.y + dy, x = v.x + dx;
-        if (z < 0 || z >= D || y < 0 || y >= H || x < 0 || x >= W) return 0.f;
-        return T[k * m + v.o + (ptrdiff_t)dz * (ptrdiff_t)plane + (ptrdiff_t)dy * W + dx];
+    auto slot = [](int z) { return (z + 3) % 3; };   // z >= -3
+    // u plane z of the u region (0 outside the volume)
+    auto load_u = [&](int z) {
+        const int sl = slot(z);
+        for (int i = tid; i < kUY * kUX; i += kFThreads) {
+            const int ly = i / kUX, lx = i - ly * kUX;
+            const int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
+            float v = 0.f;
+            if (z >= 0 && z < D && gx >= 0 && gx < W && gy >= 0 && gy < H)
+                v = u[(size_t)z * plane + (size_t)gy * W + gx];
+            su[sl][ly][lx] = v;
+        }
     };
-    float r = (at(0, 0, 0, -1) + at(0, 0, 0, 1)) - 2.f * at(0, 0, 0, 0);
-    r += (at(1, 0, -1, 0) + at(1, 0, 1, 0)) - 2.f * at(1, 0, 0, 0);
-    r += (at(2, -1, 0, 0) + at(2, 1, 0, 0)) - 2.f * at(2, 0, 0, 0);
-    r += 0.5f * ((at(3, 0, -1, -1) + at(3, 0, 1, 1)) - (at(3, 0, 1, -1) + at(3, 0, -1, 1)));
-    r += 0.5f * ((at(4, -1, 0, -1) + at(4, 1, 0, 1)) - (at(4, 1, 0, -1) + at(4, -1, 0, 1)));
-    r += 0.5f * ((at(5, -1, -1, 0) + at(5, 1, 1, 0)) - (at(5, 1, -1, 0) + at(5, -1, 1, 0)));
-    u[v.o] = u[v.o] - tau * r;
+    // this thread's T position and its tensor values at plane z (0 where T is 0)
+    const int tly = tid / kTX, tlx = tid - tly * kTX;
+    const int tgx = x0 - 1 + tlx, tgy = y0 - 1 + tly;
+    const bool tpos = tid < kTY * kTX;
+    auto load_tens = [&](int z, float (&tq)[12]) {
+        const bool in = tpos && z >= 1 && z <= D - 2 && tgx >= 1 && tgx <= W - 2 && tgy >= 1 && tgy <= H - 2;
+        const size_t o = in ? (size_t)z * plane + (size_t)tgy * W + tgx : 0;
+        const float4 *p = (const float4 *)(tens + 12 * o);   // 48 bytes per voxel, 16-byte aligned
+        const float4 a = in ? p[0] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 b = in ? p[1] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 c = in ? p[2] : make_float4(0.f, 0.f, 0.f, 0.f);
+        tq[0] = a.x, tq[1] = a.y, tq[2] = a.z, tq[3] = a.w;
+        tq[4] = b.x, tq[5] = b.y, tq[6] = b.z, tq[7] = b.w;
+        tq[8] = c.x, tq[9] = c.y, tq[10] = c.z, tq[11] = c.w;
+    };
+    // T plane z of the T region from u planes z - 1 .. z + 1 in the ring
+    auto make_T = [&](int z, const float (&tq)[12]) {
+        const int s0 = slot(z - 1), s1 = slot(z), s2 = slot(z + 1), st = slot(z);
+        if (tpos) {
+            const int ly = tly, lx = tlx;
+            const int gx = tgx, gy = tgy;
+            float T[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            if (z >= 1 && z <= D - 2 && gx >= 1 && gx <= W - 2 && gy >= 1 && gy <= H - 2) {
+                const int ux = lx + 1, uy = ly + 1;   // the voxel in the u region
+                const float c2 = 2.f * su[s1][uy][ux];
+                float h[3][3];
+                h[0][0] = su[s1][uy][ux - 1] - c2 + su[s1][uy][ux + 1];
+                h[1][1] = su[s1][uy - 1][ux] - c2 + su[s1][uy + 1][ux];
+                h[2][2] = su[s0][uy][ux] - c2 + su[s2][uy][ux];
+                h[0][1] = 0.25f * ((su[s1][uy - 1][ux - 1] + su[s1][uy + 1][ux + 1]) -
+                                   (su[s1][uy + 1][ux - 1] + su[s1][uy - 1][ux + 1]));
+                h[0][2] = 0.25f * ((su[s0][uy][ux - 1] + su[s2][uy][ux + 1]) - (su[s2][uy][ux - 1] + su[s0][uy][ux + 1]));
+                h[1][2] = 0.25f * ((su[s0][uy - 1][ux] + su[s2][uy + 1][ux]) - (su[s2][uy - 1][ux] + su[s0][uy + 1][ux]));
+                h[1][0] = h[0][1];
+                h[2][0] = h[0][2];
+                h[2][1] = h[1][2];
+                tensor_action(h, tq, T);
+            }
+#pragma unroll
+            for (int k = 0; k < 6; ++k) sT[st][k][ly][lx] = T[k];
+        }
+    };
+    // prologue: T of planes z0 - 1 and z0
+    float tq[12];
+    load_tens(z0 - 1, tq);
+    load_u(z0 - 2);
+    load_u(z0 - 1);
+    load_u(z0);
+    __syncthreads();
+    make_T(z0 - 1, tq);
+    load_tens(z0, tq);
+    __syncthreads();
+    load_u(z0 + 1);   // into the slot of plane z0 - 2
+    __syncthreads();
+    make_T(z0, tq);
+    load_tens(z0 + 1, tq);
+    const bool out = tid < kFX * kFY;
+    const int ox = tid % kFX, oy = out ? tid / kFX : 0;   // this thread's output column
+    const int gx = x0 + ox, gy = y0 + oy;
+    const int lx = ox + 1, ly = oy + 1;         // in the T region
+    for (int z = z0; z < z1; ++z) {
+        __syncthreads();   // the previous plane's gather has read the ring slots reused below
+        load_u(z + 2);     // into the slot of plane z - 1
+        __syncthreads();
+        make_T(z + 1, tq); // into the slot of plane z - 2
+        load_tens(z + 2, tq);   // in flight during the gather and the next plane's u load
+        __syncthreads();
+        if (out && gx < W && gy < H) {
+            const int tm = slot(z - 1), t0 = slot(z), tp = slot(z + 1);
+            float r = (sT[t0][0][ly][lx - 1] + sT[t0][0][ly][lx + 1]) - 2.f * sT[t0][0][ly][lx];
+            r += (sT[t0][1][ly - 1][lx] + sT[t0][1][ly + 1][lx]) - 2.f * sT[t0][1][ly][lx];
+            r += (sT[tm][2][ly][lx] + sT[tp][2][ly][lx]) - 2.f * sT[t0][2][ly][lx];
+            r += 0.5f * ((sT[t0][3][ly - 1][lx - 1] + sT[t0][3][ly + 1][lx + 1]) -
+                         (sT[t0][3][ly + 1][lx - 1] + sT[t0][3][ly - 1][lx + 1]));
+            r += 0.5f * ((sT[tm][4][ly][lx - 1] + sT[tp][4][ly][lx + 1]) - (sT[tp][4][ly][lx - 1] + sT[tm][4][ly][lx + 1]));
+            r += 0.5f * ((sT[tm][5][ly - 1][lx] + sT[tp][5][ly + 1][lx]) - (sT[tp][5][ly - 1][lx] + sT[tm][5][ly + 1][lx]));
+            const size_t o = (size_t)z * plane + (size_t)gy * W + gx;
+            uo[o] = su[slot(z)][oy + 2][ox + 2] - tau * r;
+        }
+    }
 }
 
 // ------------------------------------------------------------------ host
@@ -512,6 +585,8 @@ dim3 grid3(int D, int H, int W) { return dim3((W + kBX - 1) / kBX, (H + kBY - 1)
 const dim3 kBlock3(kBX, kBY, 1);
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 
 bool valid_dims(int D, int H, int W)
 {
@@ -539,7 +614,7 @@ struct Work3 {
     float *G1, *G2;      // [6][m] each: gathered N and the blur's ping-pong
     float *hrho;         // [6][m]
     float *tens;         // [12][m]
-    float *T;            // [6][m]
+    float *utmp;         // [m]: the substeps' ping-pong image
     unsigned *smax;
 };
 
@@ -562,7 +637,7 @@ size_t layout3(int D, int H, int W, int ns, Work3 *w, char *base)
     t.G2 = (float *)take(6 * m * 4);
     t.hrho = (float *)take(6 * m * 4);
     t.tens = (float *)take(12 * m * 4);
-    t.T = (float *)take(6 * m * 4);
+    t.utmp = (float *)take(m * 4);
     t.smax = (unsigned *)take(256);
     if (w) *w = t;
     return off;
@@ -620,15 +695,21 @@ int integrate3(int D, int H, int W, const mf4d_params *p, const uint8_t *idx, co
     return MF4D_OK;
 }
 
-int substeps3(float *u, int D, int H, int W, const float *tens, const float *taus32, int n, float *T, hipStream_t s)
+// n substeps from u back into u, ping-ponging through tmp (one plane of
+// the T scratch); an odd count ends with a copy back.
+int substeps3(float *u, int D, int H, int W, const float *tens, const float *taus32, int n, float *tmp, hipStream_t s)
 {
-    const dim3 g = grid3(D, H, W);
+    const int tiles_x = (W + kFX - 1) / kFX, tiles_y = (H + kFY - 1) / kFY, segs = (D + kZSeg - 1) / kZSeg;
+    const dim3 grid(tiles_x * tiles_y * segs);
+    float *src = u, *dst = tmp;
     for (int i = 0; i < n; ++i) {
-        tens3_kernel<<<g, kBlock3, 0, s>>>(u, tens, T, D, H, W);
+        fed3_kernel<<<grid, kFThreads, 0, s>>>(src, dst, tens, taus32[i], D, H, W, tiles_x, tiles_y);
         CHECK_LAUNCH();
-        upd3_kernel<<<g, kBlock3, 0, s>>>(u, T, taus32[i], D, H, W);
-        CHECK_LAUNCH();
+        float *t = src;
+        src = dst;
+        dst = t;
     }
+    if (src != u) CHECK_HIP(launch_copy_f32(src, u, (size_t)D * H * W, s));
     return MF4D_OK;
 }
 
@@ -665,7 +746,7 @@ int mf4d3d_tensor(const float *u, int D, int H, int W, const uint8_t *idx, const
 {
     int st = validate3(D, H, W, p);
     if (st != MF4D_OK) return st;
-    if (!u || !idx || !hrho_out || !ws) return MF4D_EINVAL;
+    if (!u || !idx || !hrho_out || !ws || (dparams_out && !aligned16(dparams_out))) return MF4D_EINVAL;
     if (ws_bytes < layout3(D, H, W, p->nscales, nullptr, nullptr)) return MF4D_ENOMEM;
     hipStream_t s = (hipStream_t)stream;
     Work3 w;
@@ -679,7 +760,7 @@ int mf4d3d_dtensor(const float *hrho, int D, int H, int W, const mf4d_params *p,
 {
     int st = validate3(D, H, W, p);
     if (st != MF4D_OK) return st;
-    if (!hrho || !dparams_out) return MF4D_EINVAL;
+    if (!hrho || !dparams_out || !aligned16(dparams_out)) return MF4D_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const double inv_lam2 = 1.0 / ((double)p->lambda * (double)p->lambda);
     eig3_kernel<<<grid3(D, H, W), kBlock3, 0, s>>>(hrho, dparams_out, p->mode, inv_lam2, D, H, W);
@@ -687,16 +768,17 @@ int mf4d3d_dtensor(const float *hrho, int D, int H, int W, const mf4d_params *p,
     return MF4D_OK;
 }
 
-int mf4d3d_fed_cycle_tensor(float *u, int D, int H, int W, const float *dparams, const double *taus, int n,
-                            float *t_scratch, void *stream)
+int mf4d3d_fed_cycle_tensor(float *u, float *u_tmp, int D, int H, int W, const float *dparams, const double *taus,
+                            int n, void *stream)
 {
-    if (!valid_dims(D, H, W) || !u || !dparams || !taus || !t_scratch || n < 1 || n > MF4D_MAX_SUBSTEPS)
+    if (!valid_dims(D, H, W) || !u || !u_tmp || u == u_tmp || !dparams || !aligned16(dparams) || !taus || n < 1 ||
+        n > MF4D_MAX_SUBSTEPS)
         return MF4D_EINVAL;
     for (int i = 0; i < n; ++i)
         if (!(taus[i] > 0.0) || !std::isfinite(taus[i])) return MF4D_EINVAL;
     std::vector<float> t32(n);
     for (int i = 0; i < n; ++i) t32[i] = (float)taus[i];
-    return substeps3(u, D, H, W, dparams, t32.data(), n, t_scratch, (hipStream_t)stream);
+    return substeps3(u, D, H, W, dparams, t32.data(), n, u_tmp, (hipStream_t)stream);
 }
 
 int mf4d3d_filter(const float *u_in, float *u_out, int D, int H, int W, const mf4d_params *p, void *ws,
@@ -726,7 +808,7 @@ int mf4d3d_filter(const float *u_in, float *u_out, int D, int H, int W, const mf
         CHECK_LAUNCH();
         st = integrate3(D, H, W, p, w.idx, w, w.hrho, w.tens, s);
         if (st != MF4D_OK) return st;
-        st = substeps3(u_out, D, H, W, w.tens, t32.data(), n, w.T, s);
+        st = substeps3(u_out, D, H, W, w.tens, t32.data(), n, w.utmp, s);
         if (st != MF4D_OK) return st;
     }
     return MF4D_OK;

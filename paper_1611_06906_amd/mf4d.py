@@ -185,7 +185,7 @@ def lib():
         L.mf4d3d_tensor.restype = i
         L.mf4d3d_dtensor.argtypes = [vp, i, i, i, P(mf4d_params), vp, vp]
         L.mf4d3d_dtensor.restype = i
-        L.mf4d3d_fed_cycle_tensor.argtypes = [vp, i, i, i, vp, P(d), i, vp, vp]
+        L.mf4d3d_fed_cycle_tensor.argtypes = [vp, vp, i, i, i, vp, P(d), i, vp]
         L.mf4d3d_fed_cycle_tensor.restype = i
         L.mf4d3d_filter.argtypes = [vp, vp, i, i, i, P(mf4d_params), vp, sz, vp]
         L.mf4d3d_filter.restype = i
@@ -598,7 +598,7 @@ def mf4d3d_tensor(u, idx, params: Params, hrho_out, dparams_out=None, ws=None, s
     D, H, W = _dhw(_dev(u, torch.float32, name="u"))
     _dev(idx, torch.uint8, (D, H, W), "idx")
     _dev(hrho_out, torch.float32, (6, D, H, W), "hrho_out")
-    _dev(dparams_out, torch.float32, (12, D, H, W), "dparams_out")
+    _dev(dparams_out, torch.float32, (D, H, W, 12), "dparams_out")
     if ws is None:
         ws = workspace3(D, H, W, params, u.device)
     _dev(ws, torch.uint8, name="ws")
@@ -612,22 +612,22 @@ def mf4d3d_dtensor(hrho, params: Params, dparams_out, stream=None):
     if hrho.dim() != 4 or hrho.shape[0] != 6:
         raise ValueError("hrho must be [6, D, H, W]")
     D, H, W = int(hrho.shape[1]), int(hrho.shape[2]), int(hrho.shape[3])
-    _dev(dparams_out, torch.float32, (12, D, H, W), "dparams_out")
+    _dev(dparams_out, torch.float32, (D, H, W, 12), "dparams_out")
     st = params.struct()
     _check(lib().mf4d3d_dtensor(_ptr(hrho), D, H, W, ctypes.byref(st), _ptr(dparams_out), _stream(stream)),
            "mf4d3d_dtensor")
 
 
-def mf4d3d_fed_cycle_tensor(u, dparams, taus, t_scratch=None, stream=None):
+def mf4d3d_fed_cycle_tensor(u, dparams, taus, u_tmp=None, stream=None):
     D, H, W = _dhw(_dev(u, torch.float32, name="u"))
-    _dev(dparams, torch.float32, (12, D, H, W), "dparams")
-    if t_scratch is None:
-        t_scratch = torch.empty((6, D, H, W), dtype=torch.float32, device=u.device)
-    _dev(t_scratch, torch.float32, (6, D, H, W), "t_scratch")
+    _dev(dparams, torch.float32, (D, H, W, 12), "dparams")
+    if u_tmp is None:
+        u_tmp = torch.empty_like(u)
+    _dev(u_tmp, torch.float32, (D, H, W), "u_tmp")
     t = np.ascontiguousarray(np.asarray(taus, dtype=np.float64))
-    _check(lib().mf4d3d_fed_cycle_tensor(_ptr(u), D, H, W, _ptr(dparams),
+    _check(lib().mf4d3d_fed_cycle_tensor(_ptr(u), _ptr(u_tmp), D, H, W, _ptr(dparams),
                                          t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(t),
-                                         _ptr(t_scratch), _stream(stream)), "mf4d3d_fed_cycle_tensor")
+                                         _stream(stream)), "mf4d3d_fed_cycle_tensor")
 
 
 def mf4d3d_filter(u_in, u_out, params: Params, ws=None, stream=None):

@@ -132,10 +132,12 @@ def test_volume_validation_rejects_before_launch(m):
     nb = m.mf4d3d_workspace_bytes(8, 9, 10, P())
     assert L.mf4d3d_filter(one, one, 8, 9, 10, ctypes.byref(st), one, nb - 1, None) == m.MF4D_ENOMEM
     assert L.mf4d3d_filter(None, one, 8, 9, 10, ctypes.byref(st), one, nb, None) == m.MF4D_EINVAL
+    two = ctypes.c_void_p(32)
     taus = (ctypes.c_double * 2)(0.01, -0.01)
-    assert L.mf4d3d_fed_cycle_tensor(one, 8, 9, 10, one, taus, 2, one, None) == m.MF4D_EINVAL
-    assert L.mf4d3d_fed_cycle_tensor(one, 8, 9, 10, one, taus, 0, one, None) == m.MF4D_EINVAL
-    assert L.mf4d3d_fed_cycle_tensor(one, 8, 9, 10, one, taus, 1, None, None) == m.MF4D_EINVAL
+    assert L.mf4d3d_fed_cycle_tensor(one, two, 8, 9, 10, one, taus, 2, None) == m.MF4D_EINVAL
+    assert L.mf4d3d_fed_cycle_tensor(one, two, 8, 9, 10, one, taus, 0, None) == m.MF4D_EINVAL
+    assert L.mf4d3d_fed_cycle_tensor(one, None, 8, 9, 10, one, taus, 1, None) == m.MF4D_EINVAL
+    assert L.mf4d3d_fed_cycle_tensor(one, one, 8, 9, 10, one, taus, 1, None) == m.MF4D_EINVAL   # aliasing
     # the workspace grows with the volume and the number of scales
     a = m.mf4d3d_workspace_bytes(16, 16, 16, P())
     assert m.mf4d3d_workspace_bytes(32, 32, 32, P()) > 7.9 * a

@@ -170,15 +170,15 @@ def test_dtensor3_action_parity(env, mode, lam):
     hr[:, 0, 0, 1] = [0.01, 0.01, 0.01, 0, 0, 0]
     hr[:, 0, 0, 2] = [0.02, 0.02, -0.01, 0, 0, 0]
     p = m.Params([1.0], mode=mode, lam=lam, tau_max=TAU3)
-    dp = torch.empty((12,) + shape, dtype=torch.float32, device=env["dev"])
+    dp = torch.empty(shape + (12,), dtype=torch.float32, device=env["dev"])
     m.mf4d3d_dtensor(_to(env, hr), p, dp)
     torch.cuda.synchronize()
     dp = dp.cpu().numpy().astype(np.float64)
     Dall = o.dtensor3(hr.astype(np.float64), float(np.float32(lam)), mode)
     worst, worst_q = 0.0, 0.0
     for z, y, x in np.ndindex(shape):
-        Q = dp[:9, z, y, x].reshape(3, 3)
-        mu = dp[9:, z, y, x]
+        Q = dp[z, y, x, :9].reshape(3, 3)
+        mu = dp[z, y, x, 9:]
         worst_q = max(worst_q, np.abs(Q.T @ Q - np.eye(3)).max())
         for _ in range(3):
             h = rng.normal(size=(3, 3))
@@ -201,7 +201,7 @@ def test_fed_cycle3_parity(env):
     hr = o.tensor3(u, sel["idx"], sig).astype(np.float32)
     taus, _, _ = o.fed_schedule(8, TAU3)
     p = m.Params(sig, mode=2, tau_max=TAU3)
-    dp = torch.empty((12,) + u.shape, dtype=torch.float32, device=env["dev"])
+    dp = torch.empty(u.shape + (12,), dtype=torch.float32, device=env["dev"])
     m.mf4d3d_dtensor(_to(env, hr), p, dp)
     ug = _to(env, u)
     m.mf4d3d_fed_cycle_tensor(ug, dp, taus)
