@@ -27,6 +27,7 @@ Prints one JSON line:
             passes of one scale on the matrix cores, split-BF16 products):
             algorithmic flops (8 filters x 99 taps x 2 per pixel) against the
             FP32-equivalent peak of split-BF16 products (BF16 peak / 6)
+  hbm_copy_probe  a plain 1 GiB device copy: the HBM rate the box reaches in practice
   cpu_baseline  the FP64 oracle on a bounded sample (the first 3 cycles of the same image)
   extensions  batched_256 (256 uneven images in one batch plan vs per-image
             calls), learned_2048 (the learned selection vs the exact sweep)
@@ -536,6 +537,18 @@ def main():
     mf4d.mf4d_fed_cycle(uc, ut, hrho, p, taus[:1])
     torch.cuda.synchronize()
 
+    # a plain device copy of 1 GiB (torch's copy kernel): the HBM rate this
+    # box reaches in practice, against which the rooflines can be read
+    csrc_ = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    cdst = torch.empty_like(csrc_)
+    cdst.copy_(csrc_)
+    ms_copy = time_stream(torch, lambda: cdst.copy_(csrc_), 5)
+    copy_bytes = 2 * csrc_.numel() * 4
+    hbm_copy_probe = {"kernel": "torch copy_ of 1 GiB float32 (read + write)", "bytes": copy_bytes, "ms": ms_copy,
+                      "GB/s": copy_bytes / (ms_copy * 1e-3) / 1e9,
+                      "frac_of_peak": copy_bytes / (ms_copy * 1e-3) / HBM_PEAK}
+    del csrc_, cdst
+
     stages = None
     if not args.no_stages:
         sel_ms = time_stream(torch, lambda: mf4d.mf4d_scale_select(u_in, p, idx, None, None, ws), 3)
@@ -601,6 +614,7 @@ def main():
         "roofline_selection": roofline_selection,
         "roofline_single_substep": roofline_single,
         "roofline_sweep": roofline_sweep,
+        "hbm_copy_probe": hbm_copy_probe,
         "cpu_baseline": cpu,
         "stages": stages,
         "extensions": extensions,
