@@ -490,7 +490,7 @@ def main():
                 "traffic_unit": "B per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
                 "traffic_over_algorithmic": (traffic / (SUBSTEP_BYTES_PER_PX * m)) if traffic else None,
                 "us_per_launch": us_launch, "bytes_per_px_launch": SUBSTEP_BYTES_PER_PX,
-                "px_per_launch": m}
+                "px_per_launch": m, "target_frac": 0.6, "meets_target": hbm / HBM_PEAK >= 0.6}
     roofline_alu = {"bound": "alu", "kernel": roofline["kernel"], "achieved": flops / 1e12,
                     "peak": VALU_PEAK / 1e12, "unit": "TFLOP/s", "frac": flops / VALU_PEAK,
                     "flops_per_px_substep": SUBSTEP_FLOPS_PER_PX, "us_per_launch": us_launch,

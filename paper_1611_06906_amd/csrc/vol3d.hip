@@ -167,7 +167,10 @@ __device__ __forceinline__ double tube_factor(double h00, double h11, double h22
     if (mode == MF4D_VALLEY && (e1 < 0.0 || e2 < 0.0)) return 0.0;
     const double ra = fabs(e1) / fabs(e2);
     const double rb2 = (e0 * e0) / fabs(e1 * e2);
-    return (1.0 - exp(-(ra * ra) / (2.0 * kAlpha3 * kAlpha3))) * exp(-rb2 * inv2beta2);
+    // the two factors in float (F is stored as float): 1 - e^-x as -expm1
+    const float fa = -expm1f(-(float)((ra * ra) / (2.0 * kAlpha3 * kAlpha3)));
+    const float fb = expf(-(float)(rb2 * inv2beta2));
+    return (double)(fa * fb);
 }
 
 // Pass along x and the per-voxel outputs of one scale: the gradient and
@@ -179,22 +182,36 @@ __global__ __launch_bounds__(256) void sweep3_x_kernel(const float *__restrict__
                                                        int D, int H, int W, WinTaps t, float sigma2, int mode,
                                                        double inv2beta2)
 {
+    // the block's 4 rows of the six planes, columns x0 - R .. x0 + 63 + R
+    // (reflected), staged in LDS: [6][kBY][SW]
+    extern __shared__ float sy[];
     const Vox v = voxel(D, H, W);
+    const int R = t.R, SW = kBX + 2 * R;
+    const size_t m = (size_t)D * H * W;
+    {
+        const int x0 = blockIdx.x * kBX;
+        const bool row_in = v.y < H;
+        const size_t row = ((size_t)v.z * H + (row_in ? v.y : 0)) * W;
+        for (int i = threadIdx.x; i < SW; i += kBX) {
+            const int gx = x0 - R + i;
+            const int xi = (gx >= 0 && gx < W) ? gx : sym_index(gx, W);
+#pragma unroll
+            for (int j = 0; j < 6; ++j) sy[(j * kBY + threadIdx.y) * SW + i] = row_in ? Y[j * m + row + xi] : 0.f;
+        }
+    }
+    __syncthreads();
     float Sv = 0.f;
     if (v.inside) {
-        const size_t m = (size_t)D * H * W;
-        const size_t row = v.o - v.x;   // voxel (z, y, 0)
+        const float *base = sy + threadIdx.y * SW + threadIdx.x;   // column x - R of plane 0
+        const int PS = kBY * SW;                                    // plane stride
         float r[6];
 #pragma unroll
-        for (int j = 0; j < 6; ++j) r[j] = Y[j * m + v.o];
-        const int R = t.R;
-        const bool inner = v.x - R >= 0 && v.x + R < W;
+        for (int j = 0; j < 6; ++j) r[j] = base[j * PS + R];
         float gx = 0.f, gy = 0.f, gz = 0.f, hxx = 0.f, hyy = 0.f, hzz = 0.f, hxy = 0.f, hxz = 0.f, hyz = 0.f;
         for (int k = 0; k <= 2 * R; ++k) {
-            const int xi = inner ? v.x + k - R : sym_index(v.x + k - R, W);
-            const size_t q = row + xi;
-            const float b00 = Y[q] - r[0], b01 = Y[m + q] - r[1], b02 = Y[2 * m + q] - r[2];
-            const float b10 = Y[3 * m + q] - r[3], b11 = Y[4 * m + q] - r[4], b20 = Y[5 * m + q] - r[5];
+            const float *q = base + k;
+            const float b00 = q[0] - r[0], b01 = q[PS] - r[1], b02 = q[2 * PS] - r[2];
+            const float b10 = q[3 * PS] - r[3], b11 = q[4 * PS] - r[4], b20 = q[5 * PS] - r[5];
             const float g = t.g[k], d1 = t.d1[k], d2 = t.d2[k];
             gx = fmaf(d1, b00, gx);
             hxx = fmaf(d2, b00, hxx);
@@ -665,8 +682,9 @@ int sweep3(const float *u, int D, int H, int W, const mf4d_params *p, const Work
         CHECK_LAUNCH();
         sweep3_y_kernel<<<g, kBlock3, 0, s>>>(w.X, w.Y, D, H, W, t);
         CHECK_LAUNCH();
-        sweep3_x_kernel<<<g, kBlock3, 0, s>>>(w.Y, w.SF + k * m, w.N + (size_t)k * 6 * m, w.smax, D, H, W, t,
-                                              sigma2, p->mode, inv2beta2);
+        const size_t lds = sizeof(float) * 6 * kBY * (kBX + 2 * t.R);
+        sweep3_x_kernel<<<g, kBlock3, lds, s>>>(w.Y, w.SF + k * m, w.N + (size_t)k * 6 * m, w.smax, D, H, W, t,
+                                                sigma2, p->mode, inv2beta2);
         CHECK_LAUNCH();
     }
     return MF4D_OK;
