@@ -468,11 +468,14 @@ def main():
     uc = u_in.clone()
     ut = torch.empty_like(uc)
     spl = SUBSTEPS_PER_LAUNCH
-    # two cycles' steps per call: an even number of full launches, so the
-    # timing holds only the substep kernel (no remainder launch, no copy-back)
-    taus2 = np.concatenate([taus, taus])
-    launches = 2 * n // spl
-    assert (2 * n) % spl == 0 and launches % 2 == 0
+    # k cycles' steps per call, k the least with k n a multiple of 2 spl: an
+    # even number of full launches, so the timing holds only the substep
+    # kernel (no remainder launch, no copy-back); k = 2 at n = 20
+    import math
+    kcyc = 2 * spl // math.gcd(n, 2 * spl)
+    taus2 = np.concatenate([taus] * kcyc)
+    launches = kcyc * n // spl
+    assert (kcyc * n) % spl == 0 and launches % 2 == 0
     cyc = lambda: mf4d.mf4d_fed_cycle_tensor(uc, ut, dpar, taus2, spl)
     cyc()
     reps = 10
@@ -497,7 +500,7 @@ def main():
                     "peak_note": "FP32 vector without packed FP32: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz"}
     # the same kernel at one substep per launch is HBM-bound: report it too
     ms1 = time_stream(torch, lambda: mf4d.mf4d_fed_cycle_tensor(uc, ut, dpar, taus2, 1), reps)
-    t1 = ms1 * 1e-3 / (2 * n)
+    t1 = ms1 * 1e-3 / (kcyc * n)
     roofline_single = {"bound": "hbm", "kernel": "fed_stream_kernel<1> (one column per lane)", "achieved": SUBSTEP_BYTES_PER_PX * m / t1 / 1e9,
                        "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": SUBSTEP_BYTES_PER_PX * m / t1 / HBM_PEAK,
                        "us_per_launch": t1 * 1e6}
