@@ -407,8 +407,11 @@ def main():
     ap.add_argument("--workload", default="creases4096")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stages", action="store_true")
-    ap.add_argument("--no-extensions", action="store_true", help="skip the batched comparison")
+    ap.add_argument("--no-extensions", action="store_true", help="skip the extension comparisons (batched, learned, volume)")
     ap.add_argument("--eager", action="store_true", help="time eager mf4d_filter calls instead of graph replays")
+    ap.add_argument("--only", choices=("batched", "learned", "volume"),
+                    help="run only this extension comparison and print its JSON line (for profiling)")
+    ap.add_argument("--learned-patches", type=int, default=20000, help="training crops of the learned comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -418,6 +421,17 @@ def main():
     import numpy as np
     import torch
     from paper_1611_06906_amd import mf4d, synth
+
+    if args.only:
+        dev = torch.device("cuda:0")
+        if args.only == "batched":
+            res = batched_comparison(torch, mf4d, synth, dev)
+        elif args.only == "learned":
+            res = learned_comparison(torch, mf4d, synth, dev, patches=args.learned_patches)
+        else:
+            res = volume_comparison(torch, mf4d, synth, dev)
+        print(json.dumps({args.only: res}), flush=True)
+        return
 
     w = synth.WORKLOADS[args.workload]()
     t0 = time.time()
@@ -575,7 +589,7 @@ def main():
     if not args.no_extensions:
         extensions = {"batched_256": batched_comparison(torch, mf4d, synth, dev)}
         print(f"[bench] batched: {json.dumps(extensions['batched_256'])}", file=sys.stderr, flush=True)
-        extensions["learned_2048"] = learned_comparison(torch, mf4d, synth, dev)
+        extensions["learned_2048"] = learned_comparison(torch, mf4d, synth, dev, patches=args.learned_patches)
         print(f"[bench] learned: {json.dumps(extensions['learned_2048'])}", file=sys.stderr, flush=True)
         extensions["volume_256"] = volume_comparison(torch, mf4d, synth, dev)
         print(f"[bench] volume: {json.dumps(extensions['volume_256'])}", file=sys.stderr, flush=True)

@@ -34,6 +34,17 @@ __device__ __forceinline__ float from_right(float v)
 }
 
 typedef float nt_f2 __attribute__((ext_vector_type(2)));   // 8-byte nontemporal loads
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// Raw buffer resource over n floats at p (n < 2^29): a load or store through
+// it takes the lane's byte offset as a vector operand and the row's as a
+// scalar one, so no per-lane address arithmetic is spent on a row. The third
+// descriptor word is the one of the gfx9 family (untyped 32-bit data).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float *p, size_t n)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, (int)(n * 4), 0x00020000);
+}
+constexpr int kBufNontemporal = 2;   // cache-policy bit of a buffer access: nontemporal
 
 // v where m is all ones, +0 where m is 0 (a bitwise select the compiler
 // cannot turn into a branch; for finite v the same values as a conditional)
@@ -155,13 +166,28 @@ __device__ __forceinline__ void fed_stream_wave(const float *__restrict__ u, flo
 // shifts per pixel and the share of halo columns. Every column runs the
 // arithmetic of fed_stream_wave in the same order, so both forms give the
 // same values bit for bit.
-// PAIR: the strip lies inside the image, W is even and the planes are 8-byte
-// aligned, so each lane loads and stores its two columns as one 8-byte pair
-// (the same values as two 4-byte accesses).
-template <int S, bool PAIR>
+// Odd segments walk their rows upwards (up = true). The 2 S halo rows two
+// neighbouring segments share are then read by both at about the same time
+// (both at the end of their walks, or both at the start), so the second read
+// finds them in the L2 cache instead of HBM. Walking up, the ring slots of the
+// older and newer rows hold rows p + 1 and p - 1 instead of p - 1 and p + 1:
+// the sums over the two are unchanged (addition commutes) and the two
+// differences (the cross derivative, and T_xy(p - 1) - T_xy(p + 1)) change
+// sign exactly, which the direction-signed factors (+-1/4, +-1/2) undo
+// exactly. Both directions therefore give the same values (an exact zero may
+// differ in sign).
+// PAIR: the strip lies inside the image, W is even, the planes are 8-byte
+// aligned and hold fewer than 2^29 pixels, so each lane loads and stores its
+// two columns as one 8-byte buffer access (the same values as two 4-byte
+// accesses), addressed as the row's offset (scalar) plus the lane's.
+// INNER (with PAIR): every column of the strip and every row the segment
+// loads is an interior pixel, so no value needs masking: the masks of the
+// general form are all ones there, and skipping them gives the same bits.
+template <int S, bool PAIR, bool INNER>
 __device__ __forceinline__ void fed_stream_wave2_body(const float *__restrict__ u, float *__restrict__ uo,
                                                       const float *__restrict__ coef, int H, int W,
-                                                      const FedTaus &taus, int strip, int seg, int seg_rows)
+                                                      const FedTaus &taus, int strip, int seg, int seg_rows,
+                                                      bool up)
 {
 #pragma clang fp contract(off)   // fused multiply-adds are written out: every launch shape rounds alike
     constexpr int HALO = 2 * S;                           // columns
@@ -202,26 +228,38 @@ __device__ __forceinline__ void fed_stream_wave2_body(const float *__restrict__ 
     for (int j = 0; j < NC; ++j)
         cma[j] = cea[j] = cpa[j] = cqa[j] = cha[j] = cmb[j] = ceb[j] = cpb[j] = cqb[j] = chb[j] = 0.f;
 
-    const int y0 = ys - 2 * S;          // first row loaded
+    const int y0 = ys - 2 * S;          // first row needed
     const int y1 = ye + 2 * S;          // one past the last row needed
+    const int dir = up ? -1 : 1;        // row step of the walk
+    const int yfirst = up ? y1 - 1 : y0;
+    const float q4 = up ? -0.25f : 0.25f, h2 = up ? -0.5f : 0.5f;
+    const unsigned lbyte = 4u * (unsigned)xa;   // PAIR: 0 <= xa < W
+    __amdgpu_buffer_rsrc_t bu, bm, ba, be, bo;
+    if (PAIR) {
+        bu = plane_rsrc(u, plane);
+        bm = plane_rsrc(coef, plane);
+        ba = plane_rsrc(coef + plane, plane);
+        be = plane_rsrc(coef + 2 * plane, plane);
+        bo = plane_rsrc(uo, plane);
+    }
     auto issue = [&](int y, int d) {
         const size_t r = (size_t)min(max(y, 0), H - 1) * W;
         if (PAIR) {
-            const size_t oa = r + xa;
+            const unsigned rb = 4u * (unsigned)r;   // r < 2^29
             // the launch's input image is read here for the last time (the
             // tensor planes are read again by the cycle's later launches)
-            const nt_f2 v0 = __builtin_nontemporal_load((const nt_f2 *)(u + oa));
-            const float2 v1 = *(const float2 *)(coef + oa);
-            const float2 v2 = *(const float2 *)(coef + plane + oa);
-            const float2 v3 = *(const float2 *)(coef + 2 * plane + oa);
-            qa0[d] = v0.x;
-            qb0[d] = v0.y;
-            qa1[d] = v1.x;
-            qb1[d] = v1.y;
-            qa2[d] = v2.x;
-            qb2[d] = v2.y;
-            qa3[d] = v3.x;
-            qb3[d] = v3.y;
+            const u32x2 v0 = __builtin_amdgcn_raw_buffer_load_b64(bu, lbyte, rb, kBufNontemporal);
+            const u32x2 v1 = __builtin_amdgcn_raw_buffer_load_b64(bm, lbyte, rb, 0);
+            const u32x2 v2 = __builtin_amdgcn_raw_buffer_load_b64(ba, lbyte, rb, 0);
+            const u32x2 v3 = __builtin_amdgcn_raw_buffer_load_b64(be, lbyte, rb, 0);
+            qa0[d] = __uint_as_float(v0.x);
+            qb0[d] = __uint_as_float(v0.y);
+            qa1[d] = __uint_as_float(v1.x);
+            qb1[d] = __uint_as_float(v1.y);
+            qa2[d] = __uint_as_float(v2.x);
+            qb2[d] = __uint_as_float(v2.y);
+            qa3[d] = __uint_as_float(v3.x);
+            qb3[d] = __uint_as_float(v3.y);
         } else {
             const size_t oa = r + xca, ob = r + xcb;
             qa0[d] = __builtin_nontemporal_load(u + oa);
@@ -235,7 +273,7 @@ __device__ __forceinline__ void fed_stream_wave2_body(const float *__restrict__ 
         }
     };
 #pragma unroll
-    for (int d = 0; d < D; ++d) issue(y0 + d, d);
+    for (int d = 0; d < D; ++d) issue(yfirst + dir * d, d);
 
     // flux of one column from its u_{k-1} rows: the sums of the left and
     // right neighbours of the old, centre and new rows (lco, lcn, lcc: left
@@ -246,28 +284,32 @@ __device__ __forceinline__ void fed_stream_wave2_body(const float *__restrict__ 
 #pragma clang fp contract(off)
         const float hxx = fmaf(-2.f, cc, lcrc);
         const float hyy = fmaf(-2.f, cc, co + cn);
-        const float hxy = 0.25f * (lorn - lnro);
+        const float hxy = q4 * (lorn - lnro);
         const float bxy = be * hxy;
         txx = fmaf(mpa, hxx, bxy);
         txy = fmaf(mb, hxy, beh * (hxx + hyy));
         tyy = fmaf(mma, hyy, bxy);
     };
 
-    for (int yb = y0; yb < y1; yb += U) {
+    for (int sb = 0; sb < y1 - y0; sb += U) {
 #pragma clang loop unroll(full)
         for (int t = 0; t < U; ++t) {
-            const int y = yb + t;
+            const int y = yfirst + dir * (sb + t);
             const int qs = t % D;
             const bool yin = y >= 0 && y < H;
-            const float na = keep(qa0[qs], mask_of(ina && yin));
-            const float nb = keep(qb0[qs], mask_of(inb && yin));
+            const float na = INNER ? qa0[qs] : keep(qa0[qs], mask_of(ina && yin));
+            const float nb = INNER ? qb0[qs] : keep(qb0[qs], mask_of(inb && yin));
             // zero tensor off the interior: the flux T = D h vanishes there
             const bool yint = y >= 1 && y <= H - 2;
             const unsigned ona = mask_of(inta && yint), onb = mask_of(intb && yint);
             {
                 const int ci = t % NC;
-                const float ma = keep(qa1[qs], ona), aa = keep(qa2[qs], ona), ea = keep(qa3[qs], ona);
-                const float mb = keep(qb1[qs], onb), ab = keep(qb2[qs], onb), eb = keep(qb3[qs], onb);
+                const float ma = INNER ? qa1[qs] : keep(qa1[qs], ona);
+                const float aa = INNER ? qa2[qs] : keep(qa2[qs], ona);
+                const float ea = INNER ? qa3[qs] : keep(qa3[qs], ona);
+                const float mb = INNER ? qb1[qs] : keep(qb1[qs], onb);
+                const float ab = INNER ? qb2[qs] : keep(qb2[qs], onb);
+                const float eb = INNER ? qb3[qs] : keep(qb3[qs], onb);
                 cma[ci] = ma;
                 cea[ci] = ea;
                 cpa[ci] = ma + aa;
@@ -279,7 +321,7 @@ __device__ __forceinline__ void fed_stream_wave2_body(const float *__restrict__ 
                 cqb[ci] = mb - ab;
                 chb[ci] = eb * 0.5f;
             }
-            issue(y + D, qs);
+            issue(y + dir * D, qs);
             {
                 const int w0 = t % 3;
                 ua[0][w0] = na;
@@ -301,17 +343,17 @@ __device__ __forceinline__ void fed_stream_wave2_body(const float *__restrict__ 
                 flux(pa[wo] + from_right(pa[wn]), pa[wn] + from_right(pa[wo]), pa[wc] + from_right(pa[wc]), pb[wo],
                      pb[wc], pb[wn], cmb[ci], ceb[ci], cpb[ci], cqb[ci], chb[ci], txb[k - 1][tw], tyb[k - 1][tw],
                      tzb[k - 1][tw]);
-                // u_k at row p = y - 2k
-                const int p = y - 2 * k;
+                // u_k at row p = y - 2k (walking up: y + 2k)
+                const int p = y - dir * 2 * k;
                 const int sn = tw;
                 const int sc = (t - 2 * k + 300) % 3;
                 const int so = (t - 2 * k - 1 + 300) % 3;
                 const float dxa = tya[k - 1][so] - tya[k - 1][sn];
                 const float dxb = tyb[k - 1][so] - tyb[k - 1][sn];
-                const float ela = fmaf(0.5f, dxa, txa[k - 1][sc]);
-                const float era = fmaf(-0.5f, dxa, txa[k - 1][sc]);
-                const float elb = fmaf(0.5f, dxb, txb[k - 1][sc]);
-                const float erb = fmaf(-0.5f, dxb, txb[k - 1][sc]);
+                const float ela = fmaf(h2, dxa, txa[k - 1][sc]);
+                const float era = fmaf(-h2, dxa, txa[k - 1][sc]);
+                const float elb = fmaf(h2, dxb, txb[k - 1][sc]);
+                const float erb = fmaf(-h2, dxb, txb[k - 1][sc]);
                 // column a: el at x-1 is column b of the lane to the left, er at x+1 is column b
                 const float rxa = fmaf(-2.f, txa[k - 1][sc], from_left(elb) + erb);
                 const float rxb = fmaf(-2.f, txb[k - 1][sc], ela + from_right(era));
@@ -327,7 +369,8 @@ __device__ __forceinline__ void fed_stream_wave2_body(const float *__restrict__ 
                 } else if (p >= ys && p < ye) {
                     const size_t r = (size_t)p * W;
                     if (PAIR) {
-                        if (own) *(float2 *)(uo + r + xa) = make_float2(nva, nvb);
+                        const u32x2 o = {__float_as_uint(nva), __float_as_uint(nvb)};
+                        if (own) __builtin_amdgcn_raw_buffer_store_b64(o, bo, lbyte, 4u * (unsigned)r, 0);
                     } else {
                         if (sta) uo[r + xa] = nva;
                         if (stb) uo[r + xb] = nvb;
@@ -344,10 +387,16 @@ __device__ __forceinline__ void fed_stream_wave2(const float *__restrict__ u, fl
                                                  const FedTaus &taus, int strip, int seg, int seg_rows)
 {
     const int x0 = strip * (128 - 4 * S) - 2 * S;   // first column of the strip
-    const bool pair = (W & 1) == 0 && x0 >= 0 && x0 + 128 <= W &&
+    const bool pair = (W & 1) == 0 && x0 >= 0 && x0 + 128 <= W && (size_t)H * W < ((size_t)1 << 29) &&
                       (((uintptr_t)u | (uintptr_t)uo | (uintptr_t)coef) & 7) == 0;
-    if (pair) fed_stream_wave2_body<S, true>(u, uo, coef, H, W, taus, strip, seg, seg_rows);
-    else fed_stream_wave2_body<S, false>(u, uo, coef, H, W, taus, strip, seg, seg_rows);
+    // interior: columns x0 .. x0 + 127 and the loaded rows ys - 2 S .. ye + 2 S - 1
+    // all lie in 1 .. W - 2 and 1 .. H - 2
+    const int ys = seg * seg_rows, ye = min(ys + seg_rows, H);
+    const bool inner = pair && x0 >= 1 && x0 + 128 <= W - 1 && ys - 2 * S >= 1 && ye + 2 * S <= H - 1;
+    const bool up = (seg & 1) != 0;
+    if (inner) fed_stream_wave2_body<S, true, true>(u, uo, coef, H, W, taus, strip, seg, seg_rows, up);
+    else if (pair) fed_stream_wave2_body<S, true, false>(u, uo, coef, H, W, taus, strip, seg, seg_rows, up);
+    else fed_stream_wave2_body<S, false, false>(u, uo, coef, H, W, taus, strip, seg, seg_rows, up);
 }
 
 }  // namespace tiles

@@ -465,12 +465,15 @@ def test_fed_cycle_tensor_parity(env, mode, shape):
             assert np.array_equal(outs[0], o2)   # temporal blocking changes no value
 
 
-@pytest.mark.parametrize("shape", [(67, 131), (130, 70), (5, 200), (3, 3), (300, 257), (70, 360), (4, 360)])
+@pytest.mark.parametrize("shape", [(67, 131), (130, 70), (5, 200), (3, 3), (300, 257), (70, 360), (4, 360),
+                                   (160, 472)])
 def test_stream_forms_bitwise(env, shape, monkeypatch):
     """The streaming substep kernel with two columns per lane equals the
     one-column form bit for bit, for 1-4 substeps per launch and any
-    number of rows per wave (at widths 360 the inner strips use the paired
-    8-byte accesses, the outer ones the single ones)."""
+    number of rows per wave (at widths 360 and 472 the inner strips use the
+    paired 8-byte accesses, the outer ones the single ones; at 160 x 472 with
+    16 or 40 rows per wave most waves lie wholly inside the image and take
+    the form without masks)."""
     o, m, torch, synth = env["o"], env["m"], env["torch"], env["synth"]
     H, W = shape
     _log(f"stream forms {shape}")
