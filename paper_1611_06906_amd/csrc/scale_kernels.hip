@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void vpass_mfma_kernel(const float *__restrict
     block_max_to(v, smax_bits);
 }
 
-template <int NC>
+template <int NC, bool CS = fused_csplit_default(NC)>
 __global__ __launch_bounds__(256, 2) void sweep_fused_kernel(const float *__restrict__ u, int H, int W, WinTaps t,
                                                           float sigma2, float inv2beta2, int mode,
                                                           float *__restrict__ SA, float *__restrict__ No,
@@ -84,8 +84,8 @@ __global__ __launch_bounds__(256, 2) void sweep_fused_kernel(const float *__rest
             any = any || ((need.bits[by * need.bx + strip] >> need.scale) & 1);
         if (!any) return;
     }
-    const float v = sweep_fused_tile<NC>(u, H, W, t, sigma2, inv2beta2, mode, SA, No, strip * kVMW, ys, ye,
-                                         (float *)lds4);
+    const float v = sweep_fused_tile<NC, CS>(u, H, W, t, sigma2, inv2beta2, mode, SA, No, strip * kVMW, ys, ye,
+                                             (float *)lds4);
     block_max_to(v, smax_bits);
 }
 
@@ -159,6 +159,11 @@ int sweep_engine(const WinTaps &t)
     return nc <= kFusedMaxChunks ? kSweepFused : kSweepSplit;
 }
 
+// The fused kernel splits C once per ring row at 2, 4 and 6 chunks, and at 8
+// when the scales run concurrently: there it takes one workgroup per CU anyway
+// (below), so the larger LDS costs it nothing.
+static bool fused_csplit(int nc, bool shared) { return fused_csplit_default(nc) || (nc == 8 && shared); }
+
 int fused_seg_rows(int H, int W, int nc, bool shared)
 {
     if (const char *e = std::getenv("MF4D_VSEG_ROWS")) {   // any multiple of the step gives the same values
@@ -170,7 +175,8 @@ int fused_seg_rows(int H, int W, int nc, bool shared)
     // window. When the scales of a cycle run concurrently, the kernels bound
     // by the matrix cores (6 chunks or more) take one workgroup per CU, which
     // leaves registers and LDS on every CU to the memory-bound small scales.
-    const int per_cu = (shared && nc >= 6) ? 1 : nc <= 3 ? 4 : (nc == 4 ? 3 : 2);
+    int per_cu = (shared && nc >= 6) ? 1 : nc <= 3 ? 4 : (nc == 4 ? 3 : 2);
+    per_cu = std::max(1, std::min(per_cu, (int)(kLdsPerCu / fused_lds(nc, fused_csplit(nc, shared)))));   // what the LDS holds
     const int strips = (W + kVMW - 1) / kVMW, steps = (H + kVMStep - 1) / kVMStep;
     const int segs = std::max(1, std::min(steps, (256 * per_cu + strips - 1) / strips));
     return kVMStep * ((steps + segs - 1) / segs);
@@ -192,12 +198,22 @@ hipError_t launch_sweep_scale(const float *u, float *hA, float *hB, float *hC, i
     const int nblk = segs * ((W + kVMW - 1) / kVMW);
     const int per = (nblk + 7) / 8;
     switch (sweep_chunks(t)) {
-#define MF4D_FU(NC)                                                                                           \
-    case NC:                                                                                                  \
-        hipLaunchKernelGGL(sweep_fused_kernel<NC>, dim3(8 * per), dim3(256), fused_lds(NC), s, u, H, W, t, sigma2, \
-                           inv2beta2, mode, out.SA, out.N, smax_bits, segs, seg_rows, nblk, per, need); \
+#define MF4D_FU(NC, CS)                                                                                       \
+        hipLaunchKernelGGL((sweep_fused_kernel<NC, CS>), dim3(8 * per), dim3(256), fused_lds(NC, CS), s, u, H, W, t, \
+                           sigma2, inv2beta2, mode, out.SA, out.N, smax_bits, segs, seg_rows, nblk, per, need); \
         break;
-        MF4D_FU(2) MF4D_FU(3) MF4D_FU(4) MF4D_FU(5) MF4D_FU(6) MF4D_FU(7) MF4D_FU(8)
+    case 2: MF4D_FU(2, true)
+    case 3: MF4D_FU(3, false)
+    case 4: MF4D_FU(4, true)
+    case 5: MF4D_FU(5, false)
+    case 6: MF4D_FU(6, true)
+    case 7: MF4D_FU(7, false)
+    case 8:
+        if (fused_csplit(8, shared)) {
+            MF4D_FU(8, true)
+        } else {
+            MF4D_FU(8, false)
+        }
 #undef MF4D_FU
     default: return hipErrorInvalidValue;
     }

@@ -35,6 +35,7 @@ constexpr int kMfmaMaxChunks = 9;      // K <= 144: radius R <= 64
 constexpr int kFusedMaxChunks = 8;     // LDS of two fused workgroups per CU
 constexpr int kHMW = 256, kHMH = 16;   // horizontal tile: output columns x rows (4 waves x 4 blocks)
 constexpr int kVMW = 32, kVMStep = 32; // vertical strip width and rows per step (4 waves x one block)
+constexpr size_t kLdsPerCu = 160 * 1024; // LDS per compute unit (gfx950)
 
 __host__ __device__ constexpr int mfma_chunks_for(int R) { return (16 + 2 * R + 15) / 16; }
 
@@ -384,9 +385,24 @@ __device__ __forceinline__ float vpass_mfma_tile(const float *__restrict__ A, co
 // of the FP32 form at sigma = 16, but not the bits of the FP32 split passes.
 // Odd chunk counts keep FP32 products: 32-input slices would read past the
 // staged row.
-__host__ __device__ constexpr size_t fused_lds(int nc) { return sizeof(float) * 4 * kVMW * (16 * nc + 16 + 4); }
+// LDS of the fused sweep: the ring planes of the horizontal results A and B
+// (FP32), that of C (FP32, or with cs its three BF16 parts, pitch fused_cpitch
+// halves: 8 mod 16, so a lane's 16-byte window reads fall on distinct banks)
+// and the staged rows of u.
+// cs (split-BF16 products only): C is split once, as its row enters the ring.
+// That takes its splits out of the window reads but needs 1.5x its LDS, so at
+// 8 chunks (84 instead of 76 KB) a compute unit holds one workgroup instead of
+// two; the default keeps FP32 C there, for launches that have the chip alone.
+__host__ __device__ constexpr bool fused_csplit_default(int nc) { return nc % 2 == 0 && nc < 8; }
+__host__ __device__ constexpr int fused_cpitch(int nc) { return 16 * nc + 24; }
+__host__ __device__ constexpr size_t fused_lds(int nc, bool cs)
+{
+    return cs ? sizeof(float) * 3 * kVMW * (16 * nc + 16 + 4) + sizeof(uint16_t) * 3 * kVMW * fused_cpitch(nc)
+              : sizeof(float) * 4 * kVMW * (16 * nc + 16 + 4);
+}
+__host__ __device__ constexpr size_t fused_lds(int nc) { return fused_lds(nc, fused_csplit_default(nc)); }
 
-template <int NC>
+template <int NC, bool CS = fused_csplit_default(NC)>
 __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, int H, int W, const WinTaps &t,
                                                   float sigma2, float inv2beta2, int mode, float *__restrict__ SA,
                                                   float *__restrict__ No, int x0, int ys,
@@ -401,7 +417,17 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
     constexpr int UP = UW + 4;        // staged row pitch (4 mod 8 floats)
     constexpr int NG = UW / 16;       // 16-column groups of a staged row
     constexpr int NU = 2 * NG;        // staged values per thread: row 16 h + tid / 16, column 16 g + tid % 16
-    float *ring = lds, *us = lds + 3 * PL;
+    // even chunk counts: split-BF16 products over NC / 2 slices of 32 inputs
+    constexpr bool BF = (NC % 2 == 0);
+    static_assert(BF || !CS, "C is split only for split-BF16 products");
+    constexpr int CP = fused_cpitch(NC);   // CS: pitch of a C part plane (halves)
+    constexpr int CPL = kVMW * CP;         // CS: halves per C part plane
+    // CS: C is kept as its three BF16 parts ([3][kVMW][CP]), formed once as its
+    // row enters the ring: C enters the vertical products unshifted, so every
+    // window that reads a row splits it the same way (the same bits)
+    float *ring = lds;
+    uint16_t *cpart = (uint16_t *)(lds + 2 * PL);
+    float *us = CS ? (float *)(cpart + 3 * CPL) : lds + 3 * PL;
     const int R = t.R;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: the ring slots below are scalar
@@ -410,8 +436,6 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
     const int JL = last_slices<NC>(R);
     const int cb = 16 * (wv & 1), rb = 16 * (wv >> 1);   // this wave's block: columns cb.., rows rb..
     const bool xin = (x0 - R >= 0) && (x0 - R + UW <= W);
-    // even chunk counts: split-BF16 products over NC / 2 slices of 32 inputs
-    constexpr bool BF = (NC % 2 == 0);
     constexpr int NSL = BF ? NC / 2 : 1;
     constexpr int NCF = BF ? 1 : NC;
     float ag[NCF][4], a1[NCF][4], a2[NCF][4];
@@ -501,10 +525,20 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
     auto ring_put = [&](int slot, const f4 &hg, const f4 &h1, const f4 &h2) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            float *cp = ring + (cb + 4 * kq + i) * P + slot;
+            const int c = cb + 4 * kq + i;
+            float *cp = ring + c * P + slot;
             cp[0] = hg[i];
             cp[PL] = h1[i];
-            cp[2 * PL] = h2[i];
+            if constexpr (CS) {
+                // the three BF16 parts of split3, as their upper halves
+                const float x = h2[i], h = bf_trunc(x), r = x - h, m = bf_trunc(r);
+                uint16_t *q = cpart + c * CP + slot;
+                q[0] = (uint16_t)(__float_as_uint(h) >> 16);
+                q[CPL] = (uint16_t)(__float_as_uint(m) >> 16);
+                q[2 * CPL] = (uint16_t)(__float_as_uint(r - m) >> 16);
+            } else {
+                cp[2 * PL] = h2[i];
+            }
         }
     };
     // prologue: the first window, rows ys - R .. ys - R + RS - 1, 32 rows at a time
@@ -565,7 +599,14 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
                 BF3 va, vb, vc;
                 split8(*(const f4 *)q - aref, *(const f4 *)(q + 4) - aref, va);
                 split8(*(const f4 *)(q + PL) - bref, *(const f4 *)(q + PL + 4) - bref, vb);
-                split8(*(const f4 *)(q + 2 * PL), *(const f4 *)(q + 2 * PL + 4), vc);
+                if constexpr (CS) {
+                    const uint16_t *qc = cpart + col * CP + sg;
+                    vc.h.v = *(const bf8 *)qc;
+                    vc.m.v = *(const bf8 *)(qc + CPL);
+                    vc.l.v = *(const bf8 *)(qc + 2 * CPL);
+                } else {
+                    split8(*(const f4 *)(q + 2 * PL), *(const f4 *)(q + 2 * PL + 4), vc);
+                }
                 cuy = mfma_bf3(b1[sl], va, cuy);
                 cuyy = mfma_bf3(b2[sl], va, cuyy);
                 cux = mfma_bf3(bg[sl], vb, cux);
