@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void vpass_mfma_kernel(const float *__restrict
     block_max_to(v, smax_bits);
 }
 
-template <int NC, bool CS = fused_csplit_default(NC)>
+template <int NC, int LV = fused_level_default(NC)>
 __global__ __launch_bounds__(256, 2) void sweep_fused_kernel(const float *__restrict__ u, int H, int W, WinTaps t,
                                                           float sigma2, float inv2beta2, int mode,
                                                           float *__restrict__ SA, float *__restrict__ No,
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256, 2) void sweep_fused_kernel(const float *__rest
             any = any || ((need.bits[by * need.bx + strip] >> need.scale) & 1);
         if (!any) return;
     }
-    const float v = sweep_fused_tile<NC, CS>(u, H, W, t, sigma2, inv2beta2, mode, SA, No, strip * kVMW, ys, ye,
+    const float v = sweep_fused_tile<NC, LV>(u, H, W, t, sigma2, inv2beta2, mode, SA, No, strip * kVMW, ys, ye,
                                              (float *)lds4);
     block_max_to(v, smax_bits);
 }
@@ -159,10 +159,10 @@ int sweep_engine(const WinTaps &t)
     return nc <= kFusedMaxChunks ? kSweepFused : kSweepSplit;
 }
 
-// The fused kernel splits C once per ring row at 2, 4 and 6 chunks, and at 8
-// when the scales run concurrently: there it takes one workgroup per CU anyway
-// (below), so the larger LDS costs it nothing.
-static bool fused_csplit(int nc, bool shared) { return fused_csplit_default(nc) || (nc == 8 && shared); }
+// Split level of the fused kernel (which ring planes are split once per row):
+// the default per chunk count, and level 2 at 8 chunks when the scales run
+// concurrently, where that kernel takes one workgroup per CU anyway (below).
+static int fused_level(int nc, bool shared) { return (nc == 8 && shared) ? 2 : fused_level_default(nc); }
 
 int fused_seg_rows(int H, int W, int nc, bool shared)
 {
@@ -176,7 +176,7 @@ int fused_seg_rows(int H, int W, int nc, bool shared)
     // by the matrix cores (6 chunks or more) take one workgroup per CU, which
     // leaves registers and LDS on every CU to the memory-bound small scales.
     int per_cu = (shared && nc >= 6) ? 1 : nc <= 3 ? 4 : (nc == 4 ? 3 : 2);
-    per_cu = std::max(1, std::min(per_cu, (int)(kLdsPerCu / fused_lds(nc, fused_csplit(nc, shared)))));   // what the LDS holds
+    per_cu = std::max(1, std::min(per_cu, (int)(kLdsPerCu / fused_lds(nc, fused_level(nc, shared)))));   // what the LDS holds
     const int strips = (W + kVMW - 1) / kVMW, steps = (H + kVMStep - 1) / kVMStep;
     const int segs = std::max(1, std::min(steps, (256 * per_cu + strips - 1) / strips));
     return kVMStep * ((steps + segs - 1) / segs);
@@ -198,21 +198,21 @@ hipError_t launch_sweep_scale(const float *u, float *hA, float *hB, float *hC, i
     const int nblk = segs * ((W + kVMW - 1) / kVMW);
     const int per = (nblk + 7) / 8;
     switch (sweep_chunks(t)) {
-#define MF4D_FU(NC, CS)                                                                                       \
-        hipLaunchKernelGGL((sweep_fused_kernel<NC, CS>), dim3(8 * per), dim3(256), fused_lds(NC, CS), s, u, H, W, t, \
+#define MF4D_FU(NC, LV)                                                                                       \
+        hipLaunchKernelGGL((sweep_fused_kernel<NC, LV>), dim3(8 * per), dim3(256), fused_lds(NC, LV), s, u, H, W, t, \
                            sigma2, inv2beta2, mode, out.SA, out.N, smax_bits, segs, seg_rows, nblk, per, need); \
         break;
-    case 2: MF4D_FU(2, true)
-    case 3: MF4D_FU(3, false)
-    case 4: MF4D_FU(4, true)
-    case 5: MF4D_FU(5, false)
-    case 6: MF4D_FU(6, true)
-    case 7: MF4D_FU(7, false)
+    case 2: MF4D_FU(2, fused_level_default(2))
+    case 3: MF4D_FU(3, 0)
+    case 4: MF4D_FU(4, fused_level_default(4))
+    case 5: MF4D_FU(5, 0)
+    case 6: MF4D_FU(6, fused_level_default(6))
+    case 7: MF4D_FU(7, 0)
     case 8:
-        if (fused_csplit(8, shared)) {
-            MF4D_FU(8, true)
+        if (fused_level(8, shared) == 2) {
+            MF4D_FU(8, 2)
         } else {
-            MF4D_FU(8, false)
+            MF4D_FU(8, fused_level_default(8))
         }
 #undef MF4D_FU
     default: return hipErrorInvalidValue;

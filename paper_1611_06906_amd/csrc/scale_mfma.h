@@ -385,24 +385,31 @@ __device__ __forceinline__ float vpass_mfma_tile(const float *__restrict__ A, co
 // of the FP32 form at sigma = 16, but not the bits of the FP32 split passes.
 // Odd chunk counts keep FP32 products: 32-input slices would read past the
 // staged row.
-// LDS of the fused sweep: the ring planes of the horizontal results A and B
-// (FP32), that of C (FP32, or with cs its three BF16 parts, pitch fused_cpitch
-// halves: 8 mod 16, so a lane's 16-byte window reads fall on distinct banks)
-// and the staged rows of u.
-// cs (split-BF16 products only): C is split once, as its row enters the ring.
-// That takes its splits out of the window reads but needs 1.5x its LDS, so at
-// 8 chunks (84 instead of 76 KB) a compute unit holds one workgroup instead of
-// two; the default keeps FP32 C there, for launches that have the chip alone.
-__host__ __device__ constexpr bool fused_csplit_default(int nc) { return nc % 2 == 0 && nc < 8; }
-__host__ __device__ constexpr int fused_cpitch(int nc) { return 16 * nc + 24; }
-__host__ __device__ constexpr size_t fused_lds(int nc, bool cs)
+// Split level of the fused sweep (split-BF16 products only): which ring planes
+// hold their three BF16 parts, formed once as a row enters the ring, instead
+// of FP32 values split by every window that reads them. Level 1: C (the second
+// x-difference); level 2: C and B (the first). Both enter the vertical products
+// unshifted, so every window would split a row the same way: the products are
+// the same bits at every level. A part plane takes 1.5x the LDS of an FP32
+// one, so the level is chosen per chunk count by what keeps the workgroups per
+// CU: 2 at 2 and 6 chunks, 1 at 4 (level 2 would drop it from three to two),
+// 0 at 8 (84 KB at level 1 would drop it from two to one). Concurrent scales
+// run 8 chunks at one workgroup per CU anyway, so they take level 2 there.
+__host__ __device__ constexpr int fused_level_default(int nc)
 {
-    return cs ? sizeof(float) * 3 * kVMW * (16 * nc + 16 + 4) + sizeof(uint16_t) * 3 * kVMW * fused_cpitch(nc)
-              : sizeof(float) * 4 * kVMW * (16 * nc + 16 + 4);
+    return nc % 2 ? 0 : (nc == 4 ? 1 : (nc == 8 ? 0 : 2));
 }
-__host__ __device__ constexpr size_t fused_lds(int nc) { return fused_lds(nc, fused_csplit_default(nc)); }
+__host__ __device__ constexpr int fused_cpitch(int nc) { return 16 * nc + 24; }   // part plane pitch (halves)
+// LDS: the FP32 ring planes (A, and B and C below their levels), the part
+// planes (pitch 8 mod 16 halves: a lane's 16-byte window reads fall on distinct
+// banks) and the staged rows of u (the size of an FP32 ring plane)
+__host__ __device__ constexpr size_t fused_lds(int nc, int lv)
+{
+    return sizeof(float) * (4 - lv) * kVMW * (16 * nc + 16 + 4) + sizeof(uint16_t) * 3 * lv * kVMW * fused_cpitch(nc);
+}
+__host__ __device__ constexpr size_t fused_lds(int nc) { return fused_lds(nc, fused_level_default(nc)); }
 
-template <int NC, bool CS = fused_csplit_default(NC)>
+template <int NC, int LV = fused_level_default(NC)>
 __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, int H, int W, const WinTaps &t,
                                                   float sigma2, float inv2beta2, int mode, float *__restrict__ SA,
                                                   float *__restrict__ No, int x0, int ys,
@@ -419,15 +426,15 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
     constexpr int NU = 2 * NG;        // staged values per thread: row 16 h + tid / 16, column 16 g + tid % 16
     // even chunk counts: split-BF16 products over NC / 2 slices of 32 inputs
     constexpr bool BF = (NC % 2 == 0);
-    static_assert(BF || !CS, "C is split only for split-BF16 products");
-    constexpr int CP = fused_cpitch(NC);   // CS: pitch of a C part plane (halves)
-    constexpr int CPL = kVMW * CP;         // CS: halves per C part plane
-    // CS: C is kept as its three BF16 parts ([3][kVMW][CP]), formed once as its
-    // row enters the ring: C enters the vertical products unshifted, so every
-    // window that reads a row splits it the same way (the same bits)
+    static_assert(LV >= 0 && LV <= 2 && (BF || LV == 0), "planes are split only for split-BF16 products");
+    constexpr int CP = fused_cpitch(NC);   // pitch of a part plane (halves)
+    constexpr int CPL = kVMW * CP;         // halves per part plane
+    // FP32 planes A, then B (LV < 2) and C (LV < 1) at ring + PL, ring + 2 PL;
+    // then the part planes [3][kVMW][CP] of C (LV >= 1) and B (LV >= 2)
     float *ring = lds;
-    uint16_t *cpart = (uint16_t *)(lds + 2 * PL);
-    float *us = CS ? (float *)(cpart + 3 * CPL) : lds + 3 * PL;
+    uint16_t *cpart = (uint16_t *)(lds + (3 - LV) * PL);
+    uint16_t *bpart = cpart + 3 * CPL;
+    float *us = (float *)(cpart + 3 * LV * CPL);
     const int R = t.R;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: the ring slots below are scalar
@@ -522,23 +529,23 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
             }
         hg = hg + ref * gsum;
     };
+    // the three BF16 parts of split3 of x, as their upper halves
+    auto put_parts = [&](uint16_t *q, float x) {
+        const float h = bf_trunc(x), r = x - h, m = bf_trunc(r);
+        q[0] = (uint16_t)(__float_as_uint(h) >> 16);
+        q[CPL] = (uint16_t)(__float_as_uint(m) >> 16);
+        q[2 * CPL] = (uint16_t)(__float_as_uint(r - m) >> 16);
+    };
     auto ring_put = [&](int slot, const f4 &hg, const f4 &h1, const f4 &h2) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int c = cb + 4 * kq + i;
             float *cp = ring + c * P + slot;
             cp[0] = hg[i];
-            cp[PL] = h1[i];
-            if constexpr (CS) {
-                // the three BF16 parts of split3, as their upper halves
-                const float x = h2[i], h = bf_trunc(x), r = x - h, m = bf_trunc(r);
-                uint16_t *q = cpart + c * CP + slot;
-                q[0] = (uint16_t)(__float_as_uint(h) >> 16);
-                q[CPL] = (uint16_t)(__float_as_uint(m) >> 16);
-                q[2 * CPL] = (uint16_t)(__float_as_uint(r - m) >> 16);
-            } else {
-                cp[2 * PL] = h2[i];
-            }
+            if constexpr (LV >= 2) put_parts(bpart + c * CP + slot, h1[i]);
+            else cp[PL] = h1[i];
+            if constexpr (LV >= 1) put_parts(cpart + c * CP + slot, h2[i]);
+            else cp[2 * PL] = h2[i];
         }
     };
     // prologue: the first window, rows ys - R .. ys - R + RS - 1, 32 rows at a time
@@ -586,7 +593,9 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
         const int y0 = yb + rb;
         const int s0 = (y0 - ys) % RS;           // slot of row y0 - R
         const int sr = (y0 - ys + R) % RS;       // slot of row y0
-        const float aref = rA[sr], bref = rB[sr];
+        // split-BF16 products take B unshifted: it already vanishes exactly on
+        // rows that are constant around the block (the horizontal shift)
+        const float aref = rA[sr], bref = BF ? 0.f : rB[sr];
         f4 cuy = {0.f, 0.f, 0.f, 0.f}, cuyy = cuy, cux = cuy, cuxy = cuy, cuxx = cuy;
         if constexpr (BF) {
             // window rows 32 sl + 8 kq .. + 7 of this lane: an 8-slot group that
@@ -598,8 +607,15 @@ __device__ __forceinline__ float sweep_fused_tile(const float *__restrict__ u, i
                 const float *q = rA + sg;
                 BF3 va, vb, vc;
                 split8(*(const f4 *)q - aref, *(const f4 *)(q + 4) - aref, va);
-                split8(*(const f4 *)(q + PL) - bref, *(const f4 *)(q + PL + 4) - bref, vb);
-                if constexpr (CS) {
+                if constexpr (LV >= 2) {
+                    const uint16_t *qb = bpart + col * CP + sg;
+                    vb.h.v = *(const bf8 *)qb;
+                    vb.m.v = *(const bf8 *)(qb + CPL);
+                    vb.l.v = *(const bf8 *)(qb + 2 * CPL);
+                } else {
+                    split8(*(const f4 *)(q + PL), *(const f4 *)(q + PL + 4), vb);
+                }
+                if constexpr (LV >= 1) {
                     const uint16_t *qc = cpart + col * CP + sg;
                     vc.h.v = *(const bf8 *)qc;
                     vc.m.v = *(const bf8 *)(qc + CPL);
