@@ -504,10 +504,13 @@ def test_stream_forms_bitwise(env, shape, monkeypatch):
 @pytest.mark.parametrize("shape", [(200, 230), (1100, 70)])
 def test_concurrent_scales_bitwise(env, monkeypatch, shape):
     """Scales swept concurrently on side streams give the same bits as one
-    after another on the caller's stream (filter and selection)."""
+    after another on the caller's stream (filter and selection). The scales
+    span 2 to 8 chunks; at 8 the concurrent launch keeps the first- and
+    second-difference planes as BF16 parts in its ring (split level 2) and the
+    lone one as FP32 values (level 0)."""
     H, W = shape
     w = env["synth"].ridges128(H=H, W=W)
-    w.sigmas = [1.0, 2.0, 4.0, 8.0, 12.0]
+    w.sigmas = [1.0, 2.0, 4.0, 8.0, 12.0, 16.0]
     w.mode = 2
     w.cycles = 2
     u = _large_image(env, H, W, seed=9)
