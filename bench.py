@@ -77,6 +77,27 @@ def source_digest(kernel):
     return h.hexdigest()[:16]
 
 
+def trace_mean_us(kernel, row):
+    """Mean duration (us) of the summary row `row` of `kernel` in the committed
+    kernel trace, or None if the kernel's sources changed since it was taken."""
+    prof = os.path.join(ROOT, "profiles", "creases4096_kernel_trace.txt")
+    try:
+        text = open(prof).read()
+        digest = source_digest(kernel)
+    except (OSError, KeyError):
+        return None
+    if f"{kernel} sources sha256 prefix: {digest}" not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith(row + " "):
+            nums = line[len(row):].split()   # count, mean, min, max, total
+            try:
+                return float(nums[1])
+            except (IndexError, ValueError):
+                return None
+    return None
+
+
 def counter_traffic(kernel, row=None):
     """HBM bytes per launch of `kernel` (its summary row `row`, default the
     kernel itself) from the committed rocprofv3 counter summary
@@ -508,6 +529,11 @@ def main():
                 "traffic_over_algorithmic": (traffic / (SUBSTEP_BYTES_PER_PX * m)) if traffic else None,
                 "us_per_launch": us_launch, "bytes_per_px_launch": SUBSTEP_BYTES_PER_PX,
                 "px_per_launch": m, "target_frac": 0.6, "meets_target": hbm / HBM_PEAK >= 0.6}
+    # the same kernel's launches inside the filter (after each cycle's sweep)
+    # run slower than back to back; their mean from the committed kernel trace
+    in_filter = trace_mean_us(f"fed_stream2_kernel<{spl}>", f"fed_stream2_kernel<{spl}> [filter]")
+    roofline["us_per_launch_in_filter"] = in_filter
+    roofline["frac_in_filter"] = (SUBSTEP_BYTES_PER_PX * m / (in_filter * 1e-6) / HBM_PEAK) if in_filter else None
     roofline_alu = {"bound": "alu", "kernel": roofline["kernel"], "achieved": flops / 1e12,
                     "peak": VALU_PEAK / 1e12, "unit": "TFLOP/s", "frac": flops / VALU_PEAK,
                     "flops_per_px_substep": SUBSTEP_FLOPS_PER_PX, "us_per_launch": us_launch,

@@ -12,3 +12,19 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""   # no JSON line
+
+
+def test_committed_profiles_match_the_kernel_sources():
+    """The counter and trace summaries under profiles/ were taken on the
+    current sources of the kernels bench.py reports (their sha256 prefixes
+    match), so the bench line's traffic and in-filter figures are not null."""
+    sys.path.insert(0, ROOT)
+    import bench
+    fed = "fed_stream2_kernel<4>"
+    traffic = bench.counter_traffic(fed)
+    assert traffic is not None and 335e6 <= traffic <= 2 * 335.5e6   # at least the algorithmic bytes
+    assert bench.selection_traffic() is not None
+    assert bench.counter_traffic("sweep_fused_kernel<8>", "sweep_fused_kernel<8> [select]") is not None
+    t_filter = bench.trace_mean_us(fed, fed + " [filter]")
+    t_loop = bench.trace_mean_us(fed, fed + " [roofline loop]")
+    assert t_filter is not None and t_loop is not None and 0 < t_loop <= t_filter
