@@ -56,61 +56,126 @@ __device__ __forceinline__ Vox voxel(int D, int H, int W)
 // Inputs are shifted by the voxel's own value (constant lines give exact
 // zeros); each Gaussian output adds it back.
 //
-// Pass along z: Z = (G, D1 G, D2 G) u, planes [3][m].
+// Pass along z: Z = (G, D1 G, D2 G) u, planes [3][m]. A thread produces kLW
+// consecutive outputs of one (y, x) column and streams the column's inputs
+// through a kLW-entry register window (input z0 - R + i in slot i mod kLW),
+// so each input is loaded once for up to kLW outputs; every output takes its
+// taps in the same order as a one-output loop would, so the values are the
+// same.
+constexpr int kLW = 8;   // outputs per thread along the pass (z and y passes)
+
 __global__ __launch_bounds__(256) void sweep3_z_kernel(const float *__restrict__ u, float *__restrict__ Z, int D,
                                                        int H, int W, WinTaps t)
 {
-    const Vox v = voxel(D, H, W);
-    if (!v.inside) return;
+    const int x = blockIdx.x * kBX + threadIdx.x, y = blockIdx.y * kBY + threadIdx.y, z0 = blockIdx.z * kLW;
+    if (x >= W || y >= H) return;
     const size_t plane = (size_t)H * W, m = plane * D;
-    const size_t pos = v.o - (size_t)v.z * plane;   // voxel (0, y, x)
-    const float ref = u[v.o];
-    const int R = t.R;
-    const bool inner = v.z - R >= 0 && v.z + R < D;
-    float g = 0.f, d1 = 0.f, d2 = 0.f;
-    for (int k = 0; k <= 2 * R; ++k) {
-        const int zi = inner ? v.z + k - R : sym_index(v.z + k - R, D);
-        const float a = u[pos + (size_t)zi * plane] - ref;
-        g = fmaf(t.g[k], a, g);
-        d1 = fmaf(t.d1[k], a, d1);
-        d2 = fmaf(t.d2[k], a, d2);
+    const size_t pos = (size_t)y * W + x;   // voxel (0, y, x)
+    const int R = t.R, nt = 2 * R + 1;
+    const bool inner = z0 - R >= 0 && z0 + kLW - 1 + R < D;   // the same for the whole block
+    auto in = [&](int z) { return u[pos + (size_t)(inner ? z : sym_index(z, D)) * plane]; };
+    float ref[kLW], w[kLW], g[kLW], d1[kLW], d2[kLW];
+#pragma unroll
+    for (int j = 0; j < kLW; ++j) {
+        ref[j] = z0 + j < D ? u[pos + (size_t)(z0 + j) * plane] : 0.f;
+        w[j] = in(z0 - R + j);
+        g[j] = d1[j] = d2[j] = 0.f;
     }
-    Z[v.o] = g + ref * t.gsum;
-    Z[m + v.o] = d1;
-    Z[2 * m + v.o] = d2;
+    for (int t0 = 0; t0 < nt; t0 += kLW) {
+#pragma unroll
+        for (int t1 = 0; t1 < kLW; ++t1) {
+            const int k = t0 + t1;
+            if (k < nt) {
+                const float tg = t.g[k], td1 = t.d1[k], td2 = t.d2[k];
+#pragma unroll
+                for (int j = 0; j < kLW; ++j) {
+                    const float a = w[(j + t1) % kLW] - ref[j];   // input z0 + j + k - R
+                    g[j] = fmaf(tg, a, g[j]);
+                    d1[j] = fmaf(td1, a, d1[j]);
+                    d2[j] = fmaf(td2, a, d2[j]);
+                }
+                // replaces input z0 - R + k, used by no later tap; the last tap's
+                // replacement would be used by none (and may lie past the volume)
+                if (k + 1 < nt) w[t1] = in(z0 - R + k + kLW);
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kLW; ++j)
+        if (z0 + j < D) {
+            const size_t o = pos + (size_t)(z0 + j) * plane;
+            Z[o] = g[j] + ref[j] * t.gsum;
+            Z[m + o] = d1[j];
+            Z[2 * m + o] = d2[j];
+        }
 }
 
 // Pass along y: from Z0 = G u the outputs (G, D1 G, D2 G), from Z1 = D1 u the
 // outputs (G, D1 G), from Z2 = D2 u the output G. Y planes [6][m] in the
 // order Y00, Y01, Y02, Y10, Y11, Y20 (first digit: z filter, second: y filter).
+// A thread produces kLW consecutive outputs of one (z, x) row through three
+// register windows, as the z pass does.
 __global__ __launch_bounds__(256) void sweep3_y_kernel(const float *__restrict__ Z, float *__restrict__ Y, int D,
                                                        int H, int W, WinTaps t)
 {
-    const Vox v = voxel(D, H, W);
-    if (!v.inside) return;
+    const int x = blockIdx.x * kBX + threadIdx.x, y0 = (blockIdx.y * kBY + threadIdx.y) * kLW, z = blockIdx.z;
+    if (x >= W || y0 >= H) return;
     const size_t m = (size_t)D * H * W;
-    const size_t col = v.o - (size_t)v.y * W;   // voxel (z, 0, x)
-    const float r0 = Z[v.o], r1 = Z[m + v.o], r2 = Z[2 * m + v.o];
-    const int R = t.R;
-    const bool inner = v.y - R >= 0 && v.y + R < H;
-    float a00 = 0.f, a01 = 0.f, a02 = 0.f, a10 = 0.f, a11 = 0.f, a20 = 0.f;
-    for (int k = 0; k <= 2 * R; ++k) {
-        const int yi = inner ? v.y + k - R : sym_index(v.y + k - R, H);
-        const size_t q = col + (size_t)yi * W;
-        const float b0 = Z[q] - r0, b1 = Z[m + q] - r1, b2 = Z[2 * m + q] - r2;
-        a00 = fmaf(t.g[k], b0, a00);
-        a01 = fmaf(t.d1[k], b0, a01);
-        a02 = fmaf(t.d2[k], b0, a02);
-        a10 = fmaf(t.g[k], b1, a10);
-        a11 = fmaf(t.d1[k], b1, a11);
-        a20 = fmaf(t.g[k], b2, a20);
+    const size_t col = (size_t)z * H * W + x;   // voxel (z, 0, x)
+    const int R = t.R, nt = 2 * R + 1;
+    const bool inner = y0 - R >= 0 && y0 + kLW - 1 + R < H;
+    auto at = [&](int y) { return col + (size_t)(inner ? y : sym_index(y, H)) * W; };
+    float r0[kLW], r1[kLW], r2[kLW], w0[kLW], w1[kLW], w2[kLW];
+    float a00[kLW], a01[kLW], a02[kLW], a10[kLW], a11[kLW], a20[kLW];
+#pragma unroll
+    for (int j = 0; j < kLW; ++j) {
+        const size_t o = col + (size_t)(y0 + j < H ? y0 + j : H - 1) * W;
+        r0[j] = Z[o];
+        r1[j] = Z[m + o];
+        r2[j] = Z[2 * m + o];
+        const size_t q = at(y0 - R + j);
+        w0[j] = Z[q];
+        w1[j] = Z[m + q];
+        w2[j] = Z[2 * m + q];
+        a00[j] = a01[j] = a02[j] = a10[j] = a11[j] = a20[j] = 0.f;
     }
-    Y[v.o] = a00 + r0 * t.gsum;
-    Y[m + v.o] = a01;
-    Y[2 * m + v.o] = a02;
-    Y[3 * m + v.o] = a10 + r1 * t.gsum;
-    Y[4 * m + v.o] = a11;
-    Y[5 * m + v.o] = a20 + r2 * t.gsum;
+    for (int t0 = 0; t0 < nt; t0 += kLW) {
+#pragma unroll
+        for (int t1 = 0; t1 < kLW; ++t1) {
+            const int k = t0 + t1;
+            if (k < nt) {
+                const float tg = t.g[k], td1 = t.d1[k], td2 = t.d2[k];
+#pragma unroll
+                for (int j = 0; j < kLW; ++j) {
+                    const int sl = (j + t1) % kLW;   // input y0 + j + k - R
+                    const float b0 = w0[sl] - r0[j], b1 = w1[sl] - r1[j], b2 = w2[sl] - r2[j];
+                    a00[j] = fmaf(tg, b0, a00[j]);
+                    a01[j] = fmaf(td1, b0, a01[j]);
+                    a02[j] = fmaf(td2, b0, a02[j]);
+                    a10[j] = fmaf(tg, b1, a10[j]);
+                    a11[j] = fmaf(td1, b1, a11[j]);
+                    a20[j] = fmaf(tg, b2, a20[j]);
+                }
+                if (k + 1 < nt) {   // as in the z pass: the last tap's replacement is never used
+                    const size_t q = at(y0 - R + k + kLW);
+                    w0[t1] = Z[q];
+                    w1[t1] = Z[m + q];
+                    w2[t1] = Z[2 * m + q];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kLW; ++j)
+        if (y0 + j < H) {
+            const size_t o = col + (size_t)(y0 + j) * W;
+            Y[o] = a00[j] + r0[j] * t.gsum;
+            Y[m + o] = a01[j];
+            Y[2 * m + o] = a02[j];
+            Y[3 * m + o] = a10[j] + r1[j] * t.gsum;
+            Y[4 * m + o] = a11[j];
+            Y[5 * m + o] = a20[j] + r2[j] * t.gsum;
+        }
 }
 
 // Eigenvalues of the symmetric 3 x 3 matrix (a00, a11, a22, a01, a02, a12)
@@ -501,7 +566,7 @@ __global__ __launch_bounds__(kFThreads) void fed3_kernel(const float *__restrict
     const int b = blockIdx.x;
     const int tx = b % tiles_x, ty = (b / tiles_x) % tiles_y, zs = b / (tiles_x * tiles_y);
     const int x0 = tx * kFX, y0 = ty * kFY, z0 = zs * kZSeg, z1 = min(D, z0 + kZSeg);
-    const size_t plane = (size_t)H * W, m = plane * D;
+    const size_t plane = (size_t)H * W;
     auto slot = [](int z) { return (z + 3) % 3; };   // z >= -3
     // u plane z of the u region (0 outside the volume)
     auto load_u = [&](int z) {
@@ -672,15 +737,18 @@ int sweep3(const float *u, int D, int H, int W, const mf4d_params *p, const Work
 {
     const size_t m = (size_t)D * H * W;
     const dim3 g = grid3(D, H, W);
+    // z and y passes: kLW outputs per thread along the pass
+    const dim3 gz((W + kBX - 1) / kBX, (H + kBY - 1) / kBY, (D + kLW - 1) / kLW);
+    const dim3 gy((W + kBX - 1) / kBX, ((H + kLW - 1) / kLW + kBY - 1) / kBY, D);
     CHECK_HIP(launch_fill_u32(w.smax, 0u, 1, s));
     const double inv2beta2 = 1.0 / (2.0 * (double)p->beta * (double)p->beta);
     for (int k = 0; k < p->nscales; ++k) {
         WinTaps t;
         window_taps(p->sigmas[k], &t);
         const float sigma2 = p->sigmas[k] * p->sigmas[k];
-        sweep3_z_kernel<<<g, kBlock3, 0, s>>>(u, w.X, D, H, W, t);
+        sweep3_z_kernel<<<gz, kBlock3, 0, s>>>(u, w.X, D, H, W, t);
         CHECK_LAUNCH();
-        sweep3_y_kernel<<<g, kBlock3, 0, s>>>(w.X, w.Y, D, H, W, t);
+        sweep3_y_kernel<<<gy, kBlock3, 0, s>>>(w.X, w.Y, D, H, W, t);
         CHECK_LAUNCH();
         const size_t lds = sizeof(float) * 6 * kBY * (kBX + 2 * t.R);
         sweep3_x_kernel<<<g, kBlock3, lds, s>>>(w.Y, w.SF + k * m, w.N + (size_t)k * 6 * m, w.smax, D, H, W, t,
