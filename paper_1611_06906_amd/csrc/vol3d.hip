@@ -198,8 +198,11 @@ __device__ __forceinline__ void sym3_eigenvalues(double a00, double a11, double 
     const double det = b00 * (b11 * b22 - a12 * a12) - a01 * (a01 * b22 - a12 * a02) + a02 * (a01 * a12 - b11 * a02);
     const double r = fmin(1.0, fmax(-1.0, det / (2.0 * p2 * p)));
     const double phi = acos(r) / 3.0;
-    e0 = q + 2.0 * p * cos(phi);
-    e2 = q + 2.0 * p * cos(phi + 2.0943951023931957);   // + 2 pi / 3
+    double sphi, cphi;
+    sincos(phi, &sphi, &cphi);
+    e0 = q + 2.0 * p * cphi;
+    // cos(phi + 2 pi / 3) = -cos(phi) / 2 - sin(phi) sqrt(3) / 2
+    e2 = q + 2.0 * p * (-0.5 * cphi - 0.86602540378443865 * sphi);
     e1 = 3.0 * q - e0 - e2;
 }
 
@@ -461,9 +464,23 @@ __device__ __forceinline__ void sym3_eigenpairs(const double (&A)[3][3], double 
         Ab[i] = A[i][0] * b[0] + A[i][1] * b[1] + A[i][2] * b[2];
     }
     const double saa = dot3(a, Aa), sab = dot3(a, Ab), sbb = dot3(b, Ab);
-    const double th = 0.5 * atan2(2.0 * sab, saa - sbb);
-    const double c = cos(th), sn = sin(th);
-    const double mid = 0.5 * (saa + sbb), rad = sqrt(0.25 * (saa - sbb) * (saa - sbb) + sab * sab);
+    // the rotation by theta = atan2(2 sab, saa - sbb) / 2 in (-pi/2, pi/2]
+    // from its half-angle forms (cos 2 theta = d / rad, sin 2 theta = sab /
+    // rad), each taken where it does not cancel: c = cos theta >= 0, and sn
+    // has the sign of sab (of +pi/2 where sab = 0 and d < 0); rad = hypot(d,
+    // sab) does not underflow where the two roots nearly coincide
+    const double d = 0.5 * (saa - sbb);
+    const double mid = 0.5 * (saa + sbb), rad = hypot(d, sab);
+    double c = 1.0, sn = 0.0;
+    if (rad > 0.0) {
+        if (d >= 0.0) {
+            c = sqrt((rad + d) / (2.0 * rad));
+            sn = sab / (2.0 * rad * c);
+        } else {
+            sn = copysign(sqrt((rad - d) / (2.0 * rad)), sab);
+            c = sab / (2.0 * rad * sn);
+        }
+    }
     const int kv = top ? 0 : 2, k1 = top ? 1 : 0, k2 = top ? 2 : 1;
     nu[kv] = lam;
     nu[k1] = mid + rad;
