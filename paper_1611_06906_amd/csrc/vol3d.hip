@@ -33,6 +33,15 @@ __device__ __forceinline__ int sym_index(int i, int n)
     return j < n ? j : p - 1 - j;
 }
 
+// Consecutive workgroups go to the 8 XCDs in turn: renumber them so that
+// each XCD takes a contiguous run of tiles (a bijection for any grid size),
+// and the halo lines that neighbouring tiles share stay in its L2.
+__device__ __forceinline__ int xcd_block()
+{
+    const int nb = gridDim.x, q8 = nb >> 3, r8 = nb & 7, xcd = blockIdx.x & 7;
+    return (xcd < r8 ? xcd * (q8 + 1) : r8 * (q8 + 1) + (xcd - r8) * q8) + (blockIdx.x >> 3);
+}
+
 struct Vox {
     int x, y, z;
     size_t o;        // linear index
@@ -397,6 +406,128 @@ __global__ __launch_bounds__(256) void rho3_kernel(const float *__restrict__ in,
     for (int k = 0; k < 6; ++k) out[k * m + v.o] = acc[k];
 }
 
+// H_rho from N at the chosen scales in one kernel, for integration radii
+// RR <= 2: a workgroup owns a kIX x kIY tile of output columns and marches
+// along z over a segment of planes. Per plane it gathers N at each voxel's
+// chosen scale over the tile and an RR-voxel xy halo into LDS, blurs it along
+// x (halo rows included) into LDS and then along y into a per-thread register
+// window of the last 2 RR + 1 planes, and blurs the window along z into the
+// output plane RR behind. Each voxel takes the same operations in the same
+// order as gather3_kernel and the three rho3_kernel passes (x, y, z;
+// reflection per axis), so the values are the same, without writing and
+// reading the gathered and the partly blurred planes.
+// Where neighbouring voxels chose different scales, each 128-byte line of a
+// gathered row brings in the lines of every scale present, so the kernel's
+// fetch is several times its algorithmic bytes; in a tile 64 voxels wide
+// the x halo's extra lines are two of a row's four (32 wide: two of three).
+constexpr int kIX = 64, kIY = 16, kIZSeg = 32;
+
+template <int RR>
+__global__ __launch_bounds__(kIX * kIY) void integrate3_kernel(const float *__restrict__ N, const uint8_t *__restrict__ idx,
+                                                         int ns, float *__restrict__ out, int D, int H, int W,
+                                                         RhoTaps t, int tiles_x, int tiles_y)
+{
+    constexpr int AX = kIX + 2 * RR, AY = kIY + 2 * RR, NR = 2 * RR + 1, NT = kIX * kIY;
+    constexpr int NIT = (AY * AX + NT - 1) / NT;   // gathered positions per thread
+    __shared__ float sa[6][AY][AX];                // gathered N of one plane with the xy halo
+    __shared__ float sb[6][AY][kIX];               // blurred along x
+    const int tid = threadIdx.x;
+    const int b = xcd_block();
+    const int tx = b % tiles_x, ty = (b / tiles_x) % tiles_y, zs = b / (tiles_x * tiles_y);
+    const int x0 = tx * kIX, y0 = ty * kIY, z0 = zs * kIZSeg, z1 = min(D, z0 + kIZSeg);
+    const int pend = z1 + RR;                      // planes z0 - RR .. pend - 1
+    const size_t m = (size_t)D * H * W, plane = (size_t)H * W;
+    const int lx = tid % kIX, ly = tid / kIX;      // this thread's output column and row
+    // The in-plane offsets of this thread's gathered positions (reflected at
+    // the volume's sides), the scale indices loaded two planes ahead and N
+    // loaded one plane ahead, so the loads of both are in flight while the
+    // planes before them are blurred.
+    size_t ofs[NIT];
+    int sidx[NIT];
+    float pre[NIT][6];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int i = min(tid + it * NT, AY * AX - 1);
+        const int ay = i / AX, ax = i - ay * AX;
+        ofs[it] = (size_t)sym_index(y0 - RR + ay, H) * W + sym_index(x0 - RR + ax, W);
+    }
+    // (the indices are clamped only where they are used: a use right after
+    // the load would wait for every load issued before it, N's included)
+    auto fetch_idx = [&](int q) {
+        const size_t zo = (size_t)sym_index(q, D) * plane;
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) sidx[it] = idx[zo + ofs[it]];
+    };
+    auto fetch_n = [&](int q) {
+        const size_t zo = (size_t)sym_index(q, D) * plane;
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const float *src = N + (size_t)min(sidx[it], ns - 1) * 6 * m + zo + ofs[it];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) pre[it][k] = src[k * m];
+        }
+    };
+    fetch_idx(z0 - RR);
+    fetch_n(z0 - RR);
+    if (z0 - RR + 1 < pend) fetch_idx(z0 - RR + 1);
+    float win[NR][6];   // plane q blurred along x and y, in slot (q - z0 + RR) mod NR
+    for (int pb = z0 - RR; pb < pend; pb += NR) {
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+            const int p = pb + u;
+            if (p >= pend) break;
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) {
+                const int i = tid + it * NT;
+                if (i < AY * AX) {
+                    const int ay = i / AX, ax = i - ay * AX;
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) sa[k][ay][ax] = pre[it][k];
+                }
+            }
+            __syncthreads();
+            if (p + 1 < pend) {
+                fetch_n(p + 1);
+                if (p + 2 < pend) fetch_idx(p + 2);
+            }
+            for (int i = tid; i < AY * kIX; i += NT) {
+                const int ay = i / kIX, ox = i - ay * kIX;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    float acc = t.g[0] * sa[k][ay][ox + RR];
+#pragma unroll
+                    for (int j = 1; j <= RR; ++j) acc = fmaf(t.g[j], sa[k][ay][ox + RR - j] + sa[k][ay][ox + RR + j], acc);
+                    sb[k][ay][ox] = acc;
+                }
+            }
+            __syncthreads();
+            // sb is rewritten only after the next plane's first barrier, and
+            // sa only after every thread has passed this one
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                float acc = t.g[0] * sb[k][ly + RR][lx];
+#pragma unroll
+                for (int j = 1; j <= RR; ++j) acc = fmaf(t.g[j], sb[k][ly + RR - j][lx] + sb[k][ly + RR + j][lx], acc);
+                win[u][k] = acc;
+            }
+            // output plane z = p - RR from the window's planes z - RR .. z + RR
+            const int z = p - RR;
+            if (z >= z0) {
+                const int x = x0 + lx, y = y0 + ly;
+                const int c = (u + NR - RR) % NR;   // a constant once unrolled
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    float acc = t.g[0] * win[c][k];
+#pragma unroll
+                    for (int j = 1; j <= RR; ++j)
+                        acc = fmaf(t.g[j], win[(c + NR - j) % NR][k] + win[(c + j) % NR][k], acc);
+                    if (x < W && y < H) out[k * m + (size_t)z * plane + (size_t)y * W + x] = acc;
+                }
+            }
+        }
+    }
+}
+
 // ----------------------------------------------------------------- tensor
 __device__ __forceinline__ void cross3(const double *a, const double *b, double *c)
 {
@@ -411,8 +542,9 @@ __device__ __forceinline__ double dot3(const double *a, const double *b) { retur
 // the cubic; the eigenvector of the root farthest from the middle one (a
 // simple root unless all three coincide) as the longest cross product of two
 // rows of A - lambda I; the other two from the symmetric 2 x 2 restriction of
-// A to the plane orthogonal to it (rotation angle from atan2), which stays
-// well defined when those two roots coincide. nu[k] and column k of q.
+// A to the plane orthogonal to it (its rotation from the half-angle forms),
+// which stays well defined when those two roots coincide. nu[k] and column k
+// of q.
 __device__ __forceinline__ void sym3_eigenpairs(const double (&A)[3][3], double (&nu)[3], double (&q)[3][3])
 {
     double e0, e1, e2;
@@ -584,7 +716,7 @@ __global__ __launch_bounds__(kFThreads) void fed3_kernel(const float *__restrict
     __shared__ float su[3][kUY][kUX];
     __shared__ float sT[3][6][kTY][kTX];
     const int tid = threadIdx.x;
-    const int b = blockIdx.x;
+    const int b = xcd_block();
     const int tx = b % tiles_x, ty = (b / tiles_x) % tiles_y, zs = b / (tiles_x * tiles_y);
     const int x0 = tx * kFX, y0 = ty * kFY, z0 = zs * kZSeg, z1 = min(D, z0 + kZSeg);
     const size_t plane = (size_t)H * W;
@@ -786,14 +918,25 @@ int integrate3(int D, int H, int W, const mf4d_params *p, const uint8_t *idx, co
     const dim3 g = grid3(D, H, W);
     RhoTaps rt;
     rho_taps(p->rho, &rt);
-    gather3_kernel<<<g, kBlock3, 0, s>>>(w.N, idx, p->nscales, w.G1, D, H, W);
-    CHECK_LAUNCH();
-    rho3_kernel<0><<<g, kBlock3, 0, s>>>(w.G1, w.G2, D, H, W, rt);
-    CHECK_LAUNCH();
-    rho3_kernel<1><<<g, kBlock3, 0, s>>>(w.G2, w.G1, D, H, W, rt);
-    CHECK_LAUNCH();
-    rho3_kernel<2><<<g, kBlock3, 0, s>>>(w.G1, hrho, D, H, W, rt);
-    CHECK_LAUNCH();
+    if (rt.r <= 2) {   // one fused kernel (the same values as the passes below)
+        const int tiles_x = (W + kIX - 1) / kIX, tiles_y = (H + kIY - 1) / kIY, segs = (D + kIZSeg - 1) / kIZSeg;
+        const dim3 gi(tiles_x * tiles_y * segs);
+        switch (rt.r) {
+        case 0: integrate3_kernel<0><<<gi, kIX * kIY, 0, s>>>(w.N, idx, p->nscales, hrho, D, H, W, rt, tiles_x, tiles_y); break;
+        case 1: integrate3_kernel<1><<<gi, kIX * kIY, 0, s>>>(w.N, idx, p->nscales, hrho, D, H, W, rt, tiles_x, tiles_y); break;
+        default: integrate3_kernel<2><<<gi, kIX * kIY, 0, s>>>(w.N, idx, p->nscales, hrho, D, H, W, rt, tiles_x, tiles_y); break;
+        }
+        CHECK_LAUNCH();
+    } else {
+        gather3_kernel<<<g, kBlock3, 0, s>>>(w.N, idx, p->nscales, w.G1, D, H, W);
+        CHECK_LAUNCH();
+        rho3_kernel<0><<<g, kBlock3, 0, s>>>(w.G1, w.G2, D, H, W, rt);
+        CHECK_LAUNCH();
+        rho3_kernel<1><<<g, kBlock3, 0, s>>>(w.G2, w.G1, D, H, W, rt);
+        CHECK_LAUNCH();
+        rho3_kernel<2><<<g, kBlock3, 0, s>>>(w.G1, hrho, D, H, W, rt);
+        CHECK_LAUNCH();
+    }
     if (tens) {
         const double inv_lam2 = 1.0 / ((double)p->lambda * (double)p->lambda);
         eig3_kernel<<<g, kBlock3, 0, s>>>(hrho, tens, p->mode, inv_lam2, D, H, W);

@@ -132,13 +132,16 @@ def test_scale_select3_fixed_c_and_zero(env):
     assert float(c.item()) == 0.0 and int(idx.max().item()) == 0
 
 
-@pytest.mark.parametrize("rho", [0.5, 0.0])
-def test_tensor3_parity(env, rho):
+@pytest.mark.parametrize("rho,shape", [(0.5, (30, 33, 37)), (0.0, (30, 33, 37)), (0.3, (70, 20, 40)),
+                                       (0.5, (70, 20, 40)), (1.0, (30, 33, 37))])
+def test_tensor3_parity(env, rho, shape):
     """H_rho at the oracle's indices against the oracle (relative to its
-    largest component)."""
+    largest component): integration radii 0, 1 and 2 (one fused z-marching
+    kernel; 70 planes take three z segments, the last one ragged) and 3 (the
+    separable passes)."""
     m, o, torch = env["m"], env["o"], env["torch"]
     sig = [1.0, 1.5, 2.2]
-    u = _volume(env, (30, 33, 37), 21, 2)
+    u = _volume(env, shape, 21, 2)
     sel = o.scale_select3(u, sig, 2)
     ref = o.tensor3(u, sel["idx"], sig, rho=rho)
     p = m.Params(sig, mode=2, rho=rho, tau_max=TAU3)
@@ -146,7 +149,7 @@ def test_tensor3_parity(env, rho):
     m.mf4d3d_tensor(_to(env, u), _to(env, sel["idx"]), p, hr)
     torch.cuda.synchronize()
     err = np.abs(hr.cpu().numpy() - ref).max()
-    _log(f"[3d tensor] rho {rho}: max err {err:.3e} of scale {np.abs(ref).max():.3e}")
+    _log(f"[3d tensor] rho {rho} {shape}: max err {err:.3e} of scale {np.abs(ref).max():.3e}")
     assert err <= 2e-6 * np.abs(ref).max() + 1e-9
 
 
