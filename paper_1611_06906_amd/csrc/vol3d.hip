@@ -22,6 +22,7 @@ namespace {
 
 constexpr double kTauLimit3 = 1.0 / 27.0;   // stencil bound 3 * 16 + 6 * 1 = 54, tau <= 2 / 54
 constexpr double kAlpha3 = 0.5;             // Frangi's plate/line parameter of the tube measure
+typedef float vf2 __attribute__((ext_vector_type(2)));   // 8-byte nontemporal accesses
 constexpr int kBX = 64, kBY = 4;
 
 // Half-sample symmetric extension for any i (period 2n).
@@ -196,9 +197,9 @@ __global__ __launch_bounds__(256) void sweep3_y_kernel(const float *__restrict__
 __device__ __forceinline__ void sym3_eigenvalues(double a00, double a11, double a22, double a01, double a02,
                                                  double a12, double &e0, double &e1, double &e2)
 {
-    const double q = (a00 + a11 + a22) / 3.0;
+    const double q = (a00 + a11 + a22) * (1.0 / 3.0);
     const double b00 = a00 - q, b11 = a11 - q, b22 = a22 - q;
-    const double p2 = (b00 * b00 + b11 * b11 + b22 * b22 + 2.0 * (a01 * a01 + a02 * a02 + a12 * a12)) / 6.0;
+    const double p2 = (b00 * b00 + b11 * b11 + b22 * b22 + 2.0 * (a01 * a01 + a02 * a02 + a12 * a12)) * (1.0 / 6.0);
     if (!(p2 > 0.0)) {
         e0 = e1 = e2 = q;
         return;
@@ -206,7 +207,7 @@ __device__ __forceinline__ void sym3_eigenvalues(double a00, double a11, double 
     const double p = sqrt(p2);
     const double det = b00 * (b11 * b22 - a12 * a12) - a01 * (a01 * b22 - a12 * a02) + a02 * (a01 * a12 - b11 * a02);
     const double r = fmin(1.0, fmax(-1.0, det / (2.0 * p2 * p)));
-    const double phi = acos(r) / 3.0;
+    const double phi = acos(r) * (1.0 / 3.0);
     double sphi, cphi;
     sincos(phi, &sphi, &cphi);
     e0 = q + 2.0 * p * cphi;
@@ -242,10 +243,11 @@ __device__ __forceinline__ double tube_factor(double h00, double h11, double h22
     if (e1 * e2 == 0.0) return 0.0;
     if (mode == MF4D_RIDGE && (e1 > 0.0 || e2 > 0.0)) return 0.0;
     if (mode == MF4D_VALLEY && (e1 < 0.0 || e2 < 0.0)) return 0.0;
-    const double ra = fabs(e1) / fabs(e2);
-    const double rb2 = (e0 * e0) / fabs(e1 * e2);
+    const double a1 = fabs(e1), a2 = fabs(e2), inv = 1.0 / (a1 * a2 * a2);
+    const double ra2 = a1 * a1 * a1 * inv;   // R_A^2 = n2^2 / n3^2
+    const double rb2 = e0 * e0 * a2 * inv;   // R_B^2 = n1^2 / |n2 n3|
     // the two factors in float (F is stored as float): 1 - e^-x as -expm1
-    const float fa = -expm1f(-(float)((ra * ra) / (2.0 * kAlpha3 * kAlpha3)));
+    const float fa = -expm1f(-(float)(ra2 * (0.5 / (kAlpha3 * kAlpha3))));
     const float fb = expf(-(float)(rb2 * inv2beta2));
     return (double)(fa * fb);
 }
@@ -310,14 +312,17 @@ __global__ __launch_bounds__(256) void sweep3_x_kernel(const float *__restrict__
         const double S = sqrt(a00 * a00 + a11 * a11 + a22 * a22 + 2.0 * (a01 * a01 + a02 * a02 + a12 * a12));
         const double F = tube_factor(a00, a11, a22, a01, a02, a12, mode, inv2beta2);
         Sv = (float)S;
-        SF[v.o] = make_float2(Sv, (float)F);
+        // written once and read once after every scale is done (SF by the
+        // argmax, N gathered by the integration): nontemporal, so that they do
+        // not evict the planes the next passes read
+        __builtin_nontemporal_store(vf2{Sv, (float)F}, (vf2 *)(SF + v.o));
         const float f = 1.f / sqrtf(1.f + sqrtf(gx * gx + gy * gy + gz * gz));
-        N[v.o] = hxx * f;
-        N[m + v.o] = hyy * f;
-        N[2 * m + v.o] = hzz * f;
-        N[3 * m + v.o] = hxy * f;
-        N[4 * m + v.o] = hxz * f;
-        N[5 * m + v.o] = hyz * f;
+        __builtin_nontemporal_store(hxx * f, N + v.o);
+        __builtin_nontemporal_store(hyy * f, N + m + v.o);
+        __builtin_nontemporal_store(hzz * f, N + 2 * m + v.o);
+        __builtin_nontemporal_store(hxy * f, N + 3 * m + v.o);
+        __builtin_nontemporal_store(hxz * f, N + 4 * m + v.o);
+        __builtin_nontemporal_store(hyz * f, N + 5 * m + v.o);
     }
     // block maximum of S, then one atomic (S >= 0: float order = bit order).
     // The maximum only grows, so a block whose value does not exceed the one
@@ -356,7 +361,7 @@ __global__ __launch_bounds__(256) void argmax3_kernel(const float2 *__restrict__
     if (c > 0.f) {
         const float inv2c2 = 1.f / (2.f * c * c);
         for (int s = 0; s < ns; ++s) {
-            const float2 sf = SF[s * m + v.o];
+            const vf2 sf = __builtin_nontemporal_load((const vf2 *)(SF + s * m + v.o));
             const float val = sf.y * -expm1f(-(sf.x * sf.x) * inv2c2);
             if (s == 0 || val > bv) {
                 bv = val;
