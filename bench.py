@@ -239,9 +239,9 @@ def batched_comparison(torch, mf4d, synth, dev, reps=2):
             "substeps_per_launch": tune[0], "rows_per_wave": tune[1]}
 
 
-# one substep of the volume filter moves u in (4 B), the tensor planes (Q,
-# mu: 48 B) and u out (4 B) per voxel
-VOLUME_SUBSTEP_BYTES = 56
+# one substep of the volume filter moves u in (4 B), the tensor (the six
+# entries of the symmetric P: 24 B) and u out (4 B) per voxel
+VOLUME_SUBSTEP_BYTES = 32
 
 
 def volume_comparison(torch, mf4d, synth, dev, reps=3):
@@ -265,7 +265,7 @@ def volume_comparison(torch, mf4d, synth, dev, reps=3):
     m = D * H * W
     idx = torch.empty((D, H, W), dtype=torch.uint8, device=dev)
     hr = torch.empty((6, D, H, W), dtype=torch.float32, device=dev)
-    dp = torch.empty((D, H, W, 12), dtype=torch.float32, device=dev)
+    dp = torch.empty((D, H, W, 6), dtype=torch.float32, device=dev)
     mf4d.mf4d3d_scale_select(ui, p, idx, None, None, ws)
     mf4d.mf4d3d_tensor(ui, idx, p, hr, dp, ws)
     taus = mf4d.mf4d_fed_plan(p)[1]

@@ -376,21 +376,22 @@ int mf4d3d_scale_select(const float *u, int D, int H, int W, const mf4d_params *
 /* Normalised, integrated Hessian at the scales idx (device uint8
  * [D][H][W], values >= nscales clamped to nscales - 1).
  *   hrho_out    device float32 [6][D][H][W]: xx, yy, zz, xy, xz, yz.
- *   dparams_out device float32 [D][H][W][12] (nullable): the tensor as
+ *   dparams_out device float32 [D][H][W][6] (nullable): the tensor as
  *               mf4d3d_dtensor writes it.
  * Errors as mf4d3d_scale_select. */
 int mf4d3d_tensor(const float *u, int D, int H, int W, const uint8_t *idx, const mf4d_params *p, float *hrho_out,
                   float *dparams_out, void *ws, size_t ws_bytes, void *stream);
 
 /* The tensor of each voxel from its H_rho (device float32 [6][D][H][W]):
- * dparams_out device float32 [D][H][W][12], 12 values per voxel (16-byte
- * aligned base): entry 3 i + k = component i of the unit eigenvector e_k
- * (k = 0..2), then mu_0, mu_1, mu_2 (lambda and mode from p).
- * Errors: MF4D_EINVAL (also for a base not 16-byte aligned), MF4D_EHIP. */
+ * dparams_out device float32 [D][H][W][6], 6 values per voxel (8-byte
+ * aligned base): the symmetric P = sum_k mu_k e_k e_k^T as xx, yy, zz, xy,
+ * xz, yz (mu_k from lambda and mode of p). With the weights above, the
+ * tensor's action on a symmetric h is (P h + h P) / 2, so P determines it.
+ * Errors: MF4D_EINVAL (also for a base not 8-byte aligned), MF4D_EHIP. */
 int mf4d3d_dtensor(const float *hrho, int D, int H, int W, const mf4d_params *p, float *dparams_out, void *stream);
 
 /* n FED substeps (Eq. (21)) u <- u - tau_i L^T D L u, with D from dparams
- * (device float32 [D][H][W][12] as mf4d3d_dtensor writes it, 16-byte
+ * (device float32 [D][H][W][6] as mf4d3d_dtensor writes it, 8-byte
  * aligned); taus host, n doubles in the order applied (each cast to
  * float32).
  *   u      device float32 [D][H][W], in/out: the result always lands here.

@@ -631,8 +631,10 @@ __device__ __forceinline__ void sym3_eigenpairs(const double (&A)[3][3], double 
 }
 
 // Eigenpairs (nu_k, e_k) of H_rho in FP64 and mu_k of Eq. (7) with the mode
-// masks: 12 values per voxel ([m][12], the substep reads them together) = Q
-// (row-major, Q[3 i + k] = component i of e_k), then mu_0, mu_1, mu_2.
+// masks, stored as P = sum_k mu_k e_k e_k^T: 6 values per voxel ([m][6], the
+// substep reads them together: xx, yy, zz, xy, xz, yz). The tensor's weights
+// mu_k on e_k e_k^T and (mu_k + mu_l) / 2 on the symmetric pairs make its
+// action on a symmetric h equal to (P h + h P) / 2, so P is all it needs.
 __global__ __launch_bounds__(256) void eig3_kernel(const float *__restrict__ hr, float *__restrict__ tens, int mode,
                                                    double inv_lam2, int D, int H, int W)
 {
@@ -644,18 +646,19 @@ __global__ __launch_bounds__(256) void eig3_kernel(const float *__restrict__ hr,
     const double a[3][3] = {{hxx, hxy, hxz}, {hxy, hyy, hyz}, {hxz, hyz, hzz}};
     double nu[3], q[3][3];
     sym3_eigenpairs(a, nu, q);
-    float mu[3];
+    double mu[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         double mk = 1.0 / (1.0 + nu[k] * nu[k] * inv_lam2);
         if (mode == MF4D_RIDGE && nu[k] >= 0.0) mk = 1.0;
         if (mode == MF4D_VALLEY && nu[k] <= 0.0) mk = 1.0;
-        mu[k] = (float)mk;
+        mu[k] = mk;
     }
-    float4 *p = (float4 *)(tens + 12 * v.o);
-    p[0] = make_float4((float)q[0][0], (float)q[0][1], (float)q[0][2], (float)q[1][0]);
-    p[1] = make_float4((float)q[1][1], (float)q[1][2], (float)q[2][0], (float)q[2][1]);
-    p[2] = make_float4((float)q[2][2], mu[0], mu[1], mu[2]);
+    auto Pij = [&](int i, int j) { return mu[0] * q[i][0] * q[j][0] + mu[1] * q[i][1] * q[j][1] + mu[2] * q[i][2] * q[j][2]; };
+    float2 *p = (float2 *)(tens + 6 * v.o);   // 24 bytes per voxel, 8-byte aligned
+    p[0] = make_float2((float)Pij(0, 0), (float)Pij(1, 1));
+    p[1] = make_float2((float)Pij(2, 2), (float)Pij(0, 1));
+    p[2] = make_float2((float)Pij(0, 2), (float)Pij(1, 2));
 }
 
 // ---------------------------------------------------------------- substep
@@ -664,54 +667,30 @@ __global__ __launch_bounds__(256) void eig3_kernel(const float *__restrict__ hr,
 // of planes. For each output plane z it loads u plane z + 2 of the tile with
 // a 2-voxel xy halo into an LDS ring of three planes, forms T of plane z + 1
 // on the tile with a 1-voxel halo into a ring of three T planes (one thread
-// per T position, its 12 tensor values loaded one plane ahead), and then
+// per T position, its 6 tensor values loaded one plane ahead), and then
 // gathers L^T T at plane z. T is D h at interior voxels and 0 elsewhere
 // (also outside the volume), h the second differences of u (cross stencils
-// for the mixed terms), D h = Q (M o (Q^T h Q)) Q^T with M_kk = mu_k and
-// M_kl = (mu_k + mu_l) / 2. Neighbouring tiles recompute their shared halo,
-// so u_out must not alias u_in.
+// for the mixed terms). D h = Q (M o (Q^T h Q)) Q^T with M_kk = mu_k and
+// M_kl = (mu_k + mu_l) / 2; as M o G = (Lambda G + G Lambda) / 2 for any G,
+// that is (P h + h P) / 2 with P = Q Lambda Q^T. Neighbouring tiles
+// recompute their shared halo, so u_out must not alias u_in.
 constexpr int kFX = 32, kFY = 8;                  // output tile
 constexpr int kTX = kFX + 2, kTY = kFY + 2;       // T region
 constexpr int kUX = kFX + 4, kUY = kFY + 4;       // u region
 constexpr int kZSeg = 64;                         // planes per workgroup
 constexpr int kFThreads = 384;                    // >= the T region's 340 positions
 
-__device__ __forceinline__ void tensor_action(const float (&h)[3][3], const float (&tq)[12], float (&T)[6])
+// T = D h = (P h + h P) / 2 for symmetric h and P (xx, yy, zz, xy, xz, yz)
+__device__ __forceinline__ void tensor_action(const float (&h)[3][3], const float (&P)[6], float (&T)[6])
 {
-    float q[3][3], mu[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) q[i][k] = tq[3 * i + k];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) mu[k] = tq[9 + k];
-    // B = h Q, A = Q^T B (in the eigenbasis), weighted by M
-    float B[3][3], A[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) B[i][k] = h[i][0] * q[0][k] + h[i][1] * q[1][k] + h[i][2] * q[2][k];
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int l = k; l < 3; ++l) {
-            const float sv = q[0][k] * B[0][l] + q[1][k] * B[1][l] + q[2][k] * B[2][l];
-            A[k][l] = (k == l ? mu[k] : 0.5f * (mu[k] + mu[l])) * sv;
-            A[l][k] = A[k][l];
-        }
-    // T = Q A Q^T
-    float C[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int l = 0; l < 3; ++l) C[i][l] = q[i][0] * A[0][l] + q[i][1] * A[1][l] + q[i][2] * A[2][l];
-    auto Tij = [&](int i, int j) { return C[i][0] * q[j][0] + C[i][1] * q[j][1] + C[i][2] * q[j][2]; };
-    T[0] = Tij(0, 0);
-    T[1] = Tij(1, 1);
-    T[2] = Tij(2, 2);
-    T[3] = Tij(0, 1);
-    T[4] = Tij(0, 2);
-    T[5] = Tij(1, 2);
+    const float p00 = P[0], p11 = P[1], p22 = P[2], p01 = P[3], p02 = P[4], p12 = P[5];
+    const float h00 = h[0][0], h11 = h[1][1], h22 = h[2][2], h01 = h[0][1], h02 = h[0][2], h12 = h[1][2];
+    T[0] = p00 * h00 + p01 * h01 + p02 * h02;
+    T[1] = p01 * h01 + p11 * h11 + p12 * h12;
+    T[2] = p02 * h02 + p12 * h12 + p22 * h22;
+    T[3] = 0.5f * ((p00 * h01 + p01 * h11 + p02 * h12) + (p01 * h00 + p11 * h01 + p12 * h02));
+    T[4] = 0.5f * ((p00 * h02 + p01 * h12 + p02 * h22) + (p02 * h00 + p12 * h01 + p22 * h02));
+    T[5] = 0.5f * ((p01 * h02 + p11 * h12 + p12 * h22) + (p02 * h01 + p12 * h11 + p22 * h12));
 }
 
 __global__ __launch_bounds__(kFThreads) void fed3_kernel(const float *__restrict__ u, float *__restrict__ uo,
@@ -742,19 +721,17 @@ __global__ __launch_bounds__(kFThreads) void fed3_kernel(const float *__restrict
     const int tly = tid / kTX, tlx = tid - tly * kTX;
     const int tgx = x0 - 1 + tlx, tgy = y0 - 1 + tly;
     const bool tpos = tid < kTY * kTX;
-    auto load_tens = [&](int z, float (&tq)[12]) {
+    auto load_tens = [&](int z, float (&tq)[6]) {
         const bool in = tpos && z >= 1 && z <= D - 2 && tgx >= 1 && tgx <= W - 2 && tgy >= 1 && tgy <= H - 2;
         const size_t o = in ? (size_t)z * plane + (size_t)tgy * W + tgx : 0;
-        const float4 *p = (const float4 *)(tens + 12 * o);   // 48 bytes per voxel, 16-byte aligned
-        const float4 a = in ? p[0] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const float4 b = in ? p[1] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const float4 c = in ? p[2] : make_float4(0.f, 0.f, 0.f, 0.f);
-        tq[0] = a.x, tq[1] = a.y, tq[2] = a.z, tq[3] = a.w;
-        tq[4] = b.x, tq[5] = b.y, tq[6] = b.z, tq[7] = b.w;
-        tq[8] = c.x, tq[9] = c.y, tq[10] = c.z, tq[11] = c.w;
+        const float2 *p = (const float2 *)(tens + 6 * o);   // 24 bytes per voxel, 8-byte aligned
+        const float2 a = in ? p[0] : make_float2(0.f, 0.f);
+        const float2 b = in ? p[1] : make_float2(0.f, 0.f);
+        const float2 c = in ? p[2] : make_float2(0.f, 0.f);
+        tq[0] = a.x, tq[1] = a.y, tq[2] = b.x, tq[3] = b.y, tq[4] = c.x, tq[5] = c.y;
     };
     // T plane z of the T region from u planes z - 1 .. z + 1 in the ring
-    auto make_T = [&](int z, const float (&tq)[12]) {
+    auto make_T = [&](int z, const float (&tq)[6]) {
         const int s0 = slot(z - 1), s1 = slot(z), s2 = slot(z + 1), st = slot(z);
         if (tpos) {
             const int ly = tly, lx = tlx;
@@ -781,7 +758,7 @@ __global__ __launch_bounds__(kFThreads) void fed3_kernel(const float *__restrict
         }
     };
     // prologue: T of planes z0 - 1 and z0
-    float tq[12];
+    float tq[6];
     load_tens(z0 - 1, tq);
     load_u(z0 - 2);
     load_u(z0 - 1);
@@ -826,7 +803,7 @@ const dim3 kBlock3(kBX, kBY, 1);
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+bool aligned8(const void *p) { return ((uintptr_t)p & 7) == 0; }
 
 bool valid_dims(int D, int H, int W)
 {
@@ -853,7 +830,7 @@ struct Work3 {
     uint8_t *idx;
     float *G1, *G2;      // [6][m] each: gathered N and the blur's ping-pong
     float *hrho;         // [6][m]
-    float *tens;         // [12][m]
+    float *tens;         // [m][6]: P
     float *utmp;         // [m]: the substeps' ping-pong image
     unsigned *smax;
 };
@@ -876,7 +853,7 @@ size_t layout3(int D, int H, int W, int ns, Work3 *w, char *base)
     t.G1 = (float *)take(6 * m * 4);
     t.G2 = (float *)take(6 * m * 4);
     t.hrho = (float *)take(6 * m * 4);
-    t.tens = (float *)take(12 * m * 4);
+    t.tens = (float *)take(6 * m * 4);
     t.utmp = (float *)take(m * 4);
     t.smax = (unsigned *)take(256);
     if (w) *w = t;
@@ -1001,7 +978,7 @@ int mf4d3d_tensor(const float *u, int D, int H, int W, const uint8_t *idx, const
 {
     int st = validate3(D, H, W, p);
     if (st != MF4D_OK) return st;
-    if (!u || !idx || !hrho_out || !ws || (dparams_out && !aligned16(dparams_out))) return MF4D_EINVAL;
+    if (!u || !idx || !hrho_out || !ws || (dparams_out && !aligned8(dparams_out))) return MF4D_EINVAL;
     if (ws_bytes < layout3(D, H, W, p->nscales, nullptr, nullptr)) return MF4D_ENOMEM;
     hipStream_t s = (hipStream_t)stream;
     Work3 w;
@@ -1015,7 +992,7 @@ int mf4d3d_dtensor(const float *hrho, int D, int H, int W, const mf4d_params *p,
 {
     int st = validate3(D, H, W, p);
     if (st != MF4D_OK) return st;
-    if (!hrho || !dparams_out || !aligned16(dparams_out)) return MF4D_EINVAL;
+    if (!hrho || !dparams_out || !aligned8(dparams_out)) return MF4D_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const double inv_lam2 = 1.0 / ((double)p->lambda * (double)p->lambda);
     eig3_kernel<<<grid3(D, H, W), kBlock3, 0, s>>>(hrho, dparams_out, p->mode, inv_lam2, D, H, W);
@@ -1026,7 +1003,7 @@ int mf4d3d_dtensor(const float *hrho, int D, int H, int W, const mf4d_params *p,
 int mf4d3d_fed_cycle_tensor(float *u, float *u_tmp, int D, int H, int W, const float *dparams, const double *taus,
                             int n, void *stream)
 {
-    if (!valid_dims(D, H, W) || !u || !u_tmp || u == u_tmp || !dparams || !aligned16(dparams) || !taus || n < 1 ||
+    if (!valid_dims(D, H, W) || !u || !u_tmp || u == u_tmp || !dparams || !aligned8(dparams) || !taus || n < 1 ||
         n > MF4D_MAX_SUBSTEPS)
         return MF4D_EINVAL;
     for (int i = 0; i < n; ++i)

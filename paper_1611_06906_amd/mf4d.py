@@ -598,7 +598,7 @@ def mf4d3d_tensor(u, idx, params: Params, hrho_out, dparams_out=None, ws=None, s
     D, H, W = _dhw(_dev(u, torch.float32, name="u"))
     _dev(idx, torch.uint8, (D, H, W), "idx")
     _dev(hrho_out, torch.float32, (6, D, H, W), "hrho_out")
-    _dev(dparams_out, torch.float32, (D, H, W, 12), "dparams_out")
+    _dev(dparams_out, torch.float32, (D, H, W, 6), "dparams_out")
     if ws is None:
         ws = workspace3(D, H, W, params, u.device)
     _dev(ws, torch.uint8, name="ws")
@@ -612,7 +612,7 @@ def mf4d3d_dtensor(hrho, params: Params, dparams_out, stream=None):
     if hrho.dim() != 4 or hrho.shape[0] != 6:
         raise ValueError("hrho must be [6, D, H, W]")
     D, H, W = int(hrho.shape[1]), int(hrho.shape[2]), int(hrho.shape[3])
-    _dev(dparams_out, torch.float32, (D, H, W, 12), "dparams_out")
+    _dev(dparams_out, torch.float32, (D, H, W, 6), "dparams_out")
     st = params.struct()
     _check(lib().mf4d3d_dtensor(_ptr(hrho), D, H, W, ctypes.byref(st), _ptr(dparams_out), _stream(stream)),
            "mf4d3d_dtensor")
@@ -620,7 +620,7 @@ def mf4d3d_dtensor(hrho, params: Params, dparams_out, stream=None):
 
 def mf4d3d_fed_cycle_tensor(u, dparams, taus, u_tmp=None, stream=None):
     D, H, W = _dhw(_dev(u, torch.float32, name="u"))
-    _dev(dparams, torch.float32, (D, H, W, 12), "dparams")
+    _dev(dparams, torch.float32, (D, H, W, 6), "dparams")
     if u_tmp is None:
         u_tmp = torch.empty_like(u)
     _dev(u_tmp, torch.float32, (D, H, W), "u_tmp")

@@ -153,17 +153,16 @@ def test_tensor3_parity(env, rho, shape):
     assert err <= 2e-6 * np.abs(ref).max() + 1e-9
 
 
-def _gpu_action(Q, mu, h):
-    """T = Q (M o (Q^T h Q)) Q^T from the GPU's planes (host, FP64)."""
-    A = Q.T @ h @ Q
-    M = 0.5 * (mu[:, None] + mu[None, :])
-    return Q @ (M * A) @ Q.T
+def _sym(p6):
+    """The symmetric 3 x 3 matrix of six entries xx, yy, zz, xy, xz, yz."""
+    return np.array([[p6[0], p6[3], p6[4]], [p6[3], p6[1], p6[5]], [p6[4], p6[5], p6[2]]])
 
 
 @pytest.mark.parametrize("mode,lam", [(0, 0.005), (1, 0.01), (2, 0.005), (2, math.inf)])
 def test_dtensor3_action_parity(env, mode, lam):
-    """The tensor planes act on symmetric matrices as the oracle's literal
-    9 x 9 D built from the same H_rho; Q is orthonormal."""
+    """The tensor planes against the oracle's literal 9 x 9 D built from the
+    same H_rho: P equals D applied to the identity, and (P h + h P) / 2
+    equals D h for symmetric h."""
     m, o, torch = env["m"], env["o"], env["torch"]
     rng = np.random.default_rng(7 + mode)
     shape = (5, 6, 7)
@@ -173,24 +172,25 @@ def test_dtensor3_action_parity(env, mode, lam):
     hr[:, 0, 0, 1] = [0.01, 0.01, 0.01, 0, 0, 0]
     hr[:, 0, 0, 2] = [0.02, 0.02, -0.01, 0, 0, 0]
     p = m.Params([1.0], mode=mode, lam=lam, tau_max=TAU3)
-    dp = torch.empty(shape + (12,), dtype=torch.float32, device=env["dev"])
+    dp = torch.empty(shape + (6,), dtype=torch.float32, device=env["dev"])
     m.mf4d3d_dtensor(_to(env, hr), p, dp)
     torch.cuda.synchronize()
     dp = dp.cpu().numpy().astype(np.float64)
     Dall = o.dtensor3(hr.astype(np.float64), float(np.float32(lam)), mode)
-    worst, worst_q = 0.0, 0.0
+    eye = np.eye(3).reshape(9)
+    worst, worst_p = 0.0, 0.0
     for z, y, x in np.ndindex(shape):
-        Q = dp[z, y, x, :9].reshape(3, 3)
-        mu = dp[z, y, x, 9:]
-        worst_q = max(worst_q, np.abs(Q.T @ Q - np.eye(3)).max())
+        P = _sym(dp[z, y, x])
+        Dm = Dall[z, y, x].reshape(9, 9)
+        worst_p = max(worst_p, np.abs(P - (Dm @ eye).reshape(3, 3)).max())
         for _ in range(3):
             h = rng.normal(size=(3, 3))
             h = h + h.T
-            got = _gpu_action(Q, mu, h)
-            ref = (Dall[z, y, x].reshape(9, 9) @ h.reshape(9)).reshape(3, 3)
+            got = 0.5 * (P @ h + h @ P)
+            ref = (Dm @ h.reshape(9)).reshape(3, 3)
             worst = max(worst, np.abs(got - ref).max() / np.abs(h).max())
-    _log(f"[3d dtensor] mode {mode} lam {lam}: action err {worst:.3e}, |Q^T Q - I| {worst_q:.3e}")
-    assert worst <= 2e-6 and worst_q <= 1e-6
+    _log(f"[3d dtensor] mode {mode} lam {lam}: action err {worst:.3e}, P err {worst_p:.3e}")
+    assert worst <= 2e-6 and worst_p <= 1e-6
 
 
 def test_fed_cycle3_parity(env):
@@ -204,7 +204,7 @@ def test_fed_cycle3_parity(env):
     hr = o.tensor3(u, sel["idx"], sig).astype(np.float32)
     taus, _, _ = o.fed_schedule(8, TAU3)
     p = m.Params(sig, mode=2, tau_max=TAU3)
-    dp = torch.empty(u.shape + (12,), dtype=torch.float32, device=env["dev"])
+    dp = torch.empty(u.shape + (6,), dtype=torch.float32, device=env["dev"])
     m.mf4d3d_dtensor(_to(env, hr), p, dp)
     ug = _to(env, u)
     m.mf4d3d_fed_cycle_tensor(ug, dp, taus)

@@ -179,6 +179,36 @@ def test_dtensor3_eigenstructure(oracle_lib):
     assert np.allclose(Dm @ _vec(Hs), _vec(Hs), atol=1e-14)
 
 
+def test_dtensor3_compact_form(oracle_lib):
+    """The literal 9 x 9 D acts on every symmetric h as (P h + h P) / 2 with
+    P = D(I) (the weights (mu_k + mu_l) / 2 on the symmetric pairs make
+    M o G = (Lambda G + G Lambda) / 2), and P = sum_k mu_k e_k e_k^T: the six
+    entries of P determine the tensor's action on symmetric matrices. Also at
+    equal and zero eigenvalues and lambda = inf (P = I)."""
+    rng = np.random.default_rng(11)
+    cases = [rng.normal(scale=0.02, size=6) for _ in range(30)]
+    cases += [np.zeros(6), np.array([0.01, 0.01, 0.01, 0, 0, 0]), np.array([0.02, 0.02, -0.01, 0, 0, 0])]
+    for t, h6 in enumerate(cases):
+        for mode in (0, 1, 2):
+            lam = math.inf if t == 5 else 0.005 * (1 + t % 3)
+            Dm, mu = oracle_lib.dtensor3_px(h6, lam, mode)
+            P = (Dm @ _vec(np.eye(3))).reshape(3, 3)
+            assert np.allclose(P, P.T, atol=1e-15)
+            A = np.array([[h6[0], h6[3], h6[4]], [h6[3], h6[1], h6[5]], [h6[4], h6[5], h6[2]]])
+            w, V = np.linalg.eigh(A)
+            w, V = w[::-1], V[:, ::-1]
+            if np.min(np.abs(np.diff(w))) > 1e-9:   # simple eigenvalues: mu pairs with V's columns
+                assert np.allclose(P, (V * mu) @ V.T, atol=1e-12)
+            assert np.allclose(np.sort(np.linalg.eigvalsh(P)), np.sort(mu), atol=1e-12)
+            if lam == math.inf:
+                assert np.allclose(P, np.eye(3), atol=1e-14)
+            for _ in range(4):
+                h = rng.normal(size=(3, 3))
+                h = h + h.T
+                got = 0.5 * (P @ h + h @ P)
+                assert np.allclose((Dm @ _vec(h)).reshape(3, 3), got, atol=1e-12)
+
+
 def _dense_P3(oracle_lib, Dall, shape):
     m = int(np.prod(shape))
     P = np.zeros((m, m))
