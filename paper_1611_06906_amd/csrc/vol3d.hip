@@ -705,19 +705,41 @@ __global__ __launch_bounds__(kFThreads) void fed3_kernel(const float *__restrict
     const int x0 = tx * kFX, y0 = ty * kFY, z0 = zs * kZSeg, z1 = min(D, z0 + kZSeg);
     const size_t plane = (size_t)H * W;
     auto slot = [](int z) { return (z + 3) % 3; };   // z >= -3
-    // u plane z of the u region (0 outside the volume)
-    auto load_u = [&](int z) {
-        const int sl = slot(z);
-        for (int i = tid; i < kUY * kUX; i += kFThreads) {
-            const int ly = i / kUX, lx = i - ly * kUX;
-            const int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
-            float v = 0.f;
-            if (z >= 0 && z < D && gx >= 0 && gx < W && gy >= 0 && gy < H)
-                v = u[(size_t)z * plane + (size_t)gy * W + gx];
-            su[sl][ly][lx] = v;
-        }
+    // u of the u region, one plane ahead in registers: this thread's
+    // positions (their in-plane offsets, clamped into the volume, and whether
+    // they lie inside it) do not change with z. The loads are unconditional
+    // and the zero outside the volume is applied only at the LDS store, so
+    // nothing waits for them before then.
+    constexpr int kUN = (kUY * kUX + kFThreads - 1) / kFThreads;
+    size_t uoff[kUN];
+    bool uin[kUN];
+#pragma unroll
+    for (int k = 0; k < kUN; ++k) {
+        const int i = min(tid + k * kFThreads, kUY * kUX - 1);
+        const int ly = i / kUX, lx = i - ly * kUX;
+        const int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
+        uin[k] = tid + k * kFThreads < kUY * kUX && gx >= 0 && gx < W && gy >= 0 && gy < H;
+        uoff[k] = (size_t)min(max(gy, 0), H - 1) * W + min(max(gx, 0), W - 1);
+    }
+    float pu[kUN];
+    auto fetch_u = [&](int z) {
+        const size_t zo = (size_t)min(max(z, 0), D - 1) * plane;
+#pragma unroll
+        for (int k = 0; k < kUN; ++k) pu[k] = u[zo + uoff[k]];
     };
-    // this thread's T position and its tensor values at plane z (0 where T is 0)
+    auto store_u = [&](int z) {   // u plane z of the u region (0 outside the volume)
+        const bool zin = z >= 0 && z < D;
+        float *sp = &su[slot(z)][0][0];
+#pragma unroll
+        for (int k = 0; k < kUN; ++k)
+            if (tid + k * kFThreads < kUY * kUX) sp[tid + k * kFThreads] = zin && uin[k] ? pu[k] : 0.f;
+    };
+    auto load_u = [&](int z) {
+        fetch_u(z);
+        store_u(z);
+    };
+    // this thread's T position and its tensor values at plane z (loaded from
+    // voxel 0 where T is 0: make_T does not use them there)
     const int tly = tid / kTX, tlx = tid - tly * kTX;
     const int tgx = x0 - 1 + tlx, tgy = y0 - 1 + tly;
     const bool tpos = tid < kTY * kTX;
@@ -725,9 +747,7 @@ __global__ __launch_bounds__(kFThreads) void fed3_kernel(const float *__restrict
         const bool in = tpos && z >= 1 && z <= D - 2 && tgx >= 1 && tgx <= W - 2 && tgy >= 1 && tgy <= H - 2;
         const size_t o = in ? (size_t)z * plane + (size_t)tgy * W + tgx : 0;
         const float2 *p = (const float2 *)(tens + 6 * o);   // 24 bytes per voxel, 8-byte aligned
-        const float2 a = in ? p[0] : make_float2(0.f, 0.f);
-        const float2 b = in ? p[1] : make_float2(0.f, 0.f);
-        const float2 c = in ? p[2] : make_float2(0.f, 0.f);
+        const float2 a = p[0], b = p[1], c = p[2];
         tq[0] = a.x, tq[1] = a.y, tq[2] = b.x, tq[3] = b.y, tq[4] = c.x, tq[5] = c.y;
     };
     // T plane z of the T region from u planes z - 1 .. z + 1 in the ring
@@ -771,13 +791,15 @@ __global__ __launch_bounds__(kFThreads) void fed3_kernel(const float *__restrict
     __syncthreads();
     make_T(z0, tq);
     load_tens(z0 + 1, tq);
+    fetch_u(z0 + 2);
     const bool out = tid < kFX * kFY;
     const int ox = tid % kFX, oy = out ? tid / kFX : 0;   // this thread's output column
     const int gx = x0 + ox, gy = y0 + oy;
     const int lx = ox + 1, ly = oy + 1;         // in the T region
     for (int z = z0; z < z1; ++z) {
         __syncthreads();   // the previous plane's gather has read the ring slots reused below
-        load_u(z + 2);     // into the slot of plane z - 1
+        store_u(z + 2);    // into the slot of plane z - 1
+        fetch_u(z + 3);    // in flight during make_T and the gather
         __syncthreads();
         make_T(z + 1, tq); // into the slot of plane z - 2
         load_tens(z + 2, tq);   // in flight during the gather and the next plane's u load
