@@ -268,14 +268,31 @@ __global__ __launch_bounds__(256) void sweep3_x_kernel(const float *__restrict__
     const int R = t.R, SW = kBX + 2 * R;
     const size_t m = (size_t)D * H * W;
     {
+        // every load of a chunk of two columns per thread is issued before its
+        // LDS stores (from clamped, in-bounds addresses; rows past the volume
+        // store 0), so the thread waits for them once
         const int x0 = blockIdx.x * kBX;
         const bool row_in = v.y < H;
         const size_t row = ((size_t)v.z * H + (row_in ? v.y : 0)) * W;
-        for (int i = threadIdx.x; i < SW; i += kBX) {
+        auto col = [&](int i) {
             const int gx = x0 - R + i;
-            const int xi = (gx >= 0 && gx < W) ? gx : sym_index(gx, W);
+            return (gx >= 0 && gx < W) ? gx : sym_index(gx, W);
+        };
+        for (int base = 0; base < SW; base += 2 * kBX) {
+            const int ia = base + threadIdx.x, ib = ia + kBX;
+            const size_t xa = row + col(min(ia, SW - 1)), xb = row + col(min(ib, SW - 1));
+            float va[6], vb[6];
 #pragma unroll
-            for (int j = 0; j < 6; ++j) sy[(j * kBY + threadIdx.y) * SW + i] = row_in ? Y[j * m + row + xi] : 0.f;
+            for (int j = 0; j < 6; ++j) {
+                va[j] = Y[j * m + xa];
+                vb[j] = Y[j * m + xb];
+            }
+            float *dst = sy + threadIdx.y * SW;
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                if (ia < SW) dst[j * kBY * SW + ia] = row_in ? va[j] : 0.f;
+                if (ib < SW) dst[j * kBY * SW + ib] = row_in ? vb[j] : 0.f;
+            }
         }
     }
     __syncthreads();
