@@ -194,6 +194,33 @@ __global__ __launch_bounds__(256) void sweep3_y_kernel(const float *__restrict__
 // r = det(B) / 2p^3, the roots are q + 2p cos(acos(r)/3 + 2 pi k/3). The
 // error is a few ulp of |A| (about 1e-8 |A| where two roots nearly
 // coincide), far below that of the float32 Hessian.
+// sin and cos of x in [0, pi/3] from their Taylor series through x^19 and
+// x^18 (Horner in x^2): the truncation error there is below x^20/20! < 2e-18.
+__device__ __forceinline__ void sincos_small(double x, double &s, double &c)
+{
+    const double x2 = x * x;
+    double ps = 1.0 / 121645100408832000.0;               // 1/19!
+    ps = fma(ps, x2, -1.0 / 355687428096000.0);           // 1/17!
+    ps = fma(ps, x2, 1.0 / 1307674368000.0);              // 1/15!
+    ps = fma(ps, x2, -1.0 / 6227020800.0);                // 1/13!
+    ps = fma(ps, x2, 1.0 / 39916800.0);                   // 1/11!
+    ps = fma(ps, x2, -1.0 / 362880.0);                    // 1/9!
+    ps = fma(ps, x2, 1.0 / 5040.0);                       // 1/7!
+    ps = fma(ps, x2, -1.0 / 120.0);                       // 1/5!
+    ps = fma(ps, x2, 1.0 / 6.0);                          // 1/3!
+    s = fma(-x * x2, ps, x);
+    double pc = 1.0 / 6402373705728000.0;                 // 1/18!
+    pc = fma(pc, x2, -1.0 / 20922789888000.0);            // 1/16!
+    pc = fma(pc, x2, 1.0 / 87178291200.0);                // 1/14!
+    pc = fma(pc, x2, -1.0 / 479001600.0);                 // 1/12!
+    pc = fma(pc, x2, 1.0 / 3628800.0);                    // 1/10!
+    pc = fma(pc, x2, -1.0 / 40320.0);                     // 1/8!
+    pc = fma(pc, x2, 1.0 / 720.0);                        // 1/6!
+    pc = fma(pc, x2, -1.0 / 24.0);                        // 1/4!
+    pc = fma(pc, x2, 0.5);                                // 1/2!
+    c = fma(-x2, pc, 1.0);
+}
+
 __device__ __forceinline__ void sym3_eigenvalues(double a00, double a11, double a22, double a01, double a02,
                                                  double a12, double &e0, double &e1, double &e2)
 {
@@ -209,7 +236,7 @@ __device__ __forceinline__ void sym3_eigenvalues(double a00, double a11, double 
     const double r = fmin(1.0, fmax(-1.0, det / (2.0 * p2 * p)));
     const double phi = acos(r) * (1.0 / 3.0);
     double sphi, cphi;
-    sincos(phi, &sphi, &cphi);
+    sincos_small(phi, sphi, cphi);
     e0 = q + 2.0 * p * cphi;
     // cos(phi + 2 pi / 3) = -cos(phi) / 2 - sin(phi) sqrt(3) / 2
     e2 = q + 2.0 * p * (-0.5 * cphi - 0.86602540378443865 * sphi);
