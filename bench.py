@@ -65,6 +65,7 @@ CSRC = os.path.join(ROOT, "paper_1611_06906_amd", "csrc")
 KERNEL_SOURCES = {
     "fed_stream2_kernel<4>": ["fed_kernels.hip", "fed_tiles.h", "mf4d_internal.h", "../build.py"],
     "sweep_fused_kernel<8>": ["scale_kernels.hip", "scale_mfma.h", "scale_tiles.h", "mf4d_internal.h", "../build.py"],
+    "fed3_kernel": ["vol3d.hip", "mf4d_internal.h", "../build.py"],
 }
 
 
@@ -98,12 +99,12 @@ def trace_mean_us(kernel, row):
     return None
 
 
-def counter_traffic(kernel, row=None):
+def counter_traffic(kernel, row=None, summary="creases4096_hbm_counters.txt"):
     """HBM bytes per launch of `kernel` (its summary row `row`, default the
-    kernel itself) from the committed rocprofv3 counter summary
+    kernel itself) from the committed rocprofv3 counter summary `summary`
     (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, calibrated on a plain copy), or
     None if the kernel's sources changed since the counters were taken."""
-    prof = os.path.join(ROOT, "profiles", "creases4096_hbm_counters.txt")
+    prof = os.path.join(ROOT, "profiles", summary)
     try:
         text = open(prof).read()
         digest = source_digest(kernel)
@@ -283,6 +284,7 @@ def volume_comparison(torch, mf4d, synth, dev, reps=3):
                                  "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                                  "frac": VOLUME_SUBSTEP_BYTES * m / t / HBM_PEAK,
                                  "bytes_per_voxel": VOLUME_SUBSTEP_BYTES,
+                                 "traffic": counter_traffic("fed3_kernel", summary="volume256_hbm_counters.txt"),
                                  "kernel": "fed3_kernel (fused substep, 32 x 8 tiles streaming along z)"}}
 
 

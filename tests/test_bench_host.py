@@ -28,3 +28,8 @@ def test_committed_profiles_match_the_kernel_sources():
     t_filter = bench.trace_mean_us(fed, fed + " [filter]")
     t_loop = bench.trace_mean_us(fed, fed + " [roofline loop]")
     assert t_filter is not None and t_loop is not None and 0 < t_loop <= t_filter
+    # the volume substep's counters: at least its 32 algorithmic bytes per voxel
+    vol = bench.counter_traffic("fed3_kernel", summary="volume256_hbm_counters.txt")
+    assert vol is not None and 32 * 256 ** 3 <= vol <= 2 * 32 * 256 ** 3
+    assert "fed3_kernel sources sha256 prefix: " + bench.source_digest("fed3_kernel") in open(
+        os.path.join(ROOT, "profiles", "volume256_kernel_trace.txt")).read()
