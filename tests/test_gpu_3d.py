@@ -153,6 +153,28 @@ def test_tensor3_parity(env, rho, shape):
     assert err <= 2e-6 * np.abs(ref).max() + 1e-9
 
 
+@pytest.mark.parametrize("rho", [0.5, 1.0])
+def test_tensor3_clamps_indices(env, rho):
+    """Scale indices of nscales or more count as nscales - 1 (the fused
+    integration at radius 2 and the separable passes at radius 3): the same
+    H_rho as the oracle's on the clamped indices."""
+    m, o, torch = env["m"], env["o"], env["torch"]
+    sig = [1.0, 1.6]
+    u = _volume(env, (9, 21, 70), 5, 2)
+    rng = np.random.default_rng(3)
+    idx = rng.integers(0, 2, size=u.shape).astype(np.uint8)
+    big = rng.random(u.shape) < 0.3
+    idx[big] = rng.choice(np.array([2, 7, 255], np.uint8), size=int(big.sum()))
+    ref = o.tensor3(u, np.minimum(idx, len(sig) - 1), sig, rho=rho)
+    p = m.Params(sig, mode=2, rho=rho, tau_max=TAU3)
+    hr = torch.empty((6,) + u.shape, dtype=torch.float32, device=env["dev"])
+    m.mf4d3d_tensor(_to(env, u), _to(env, idx), p, hr)
+    torch.cuda.synchronize()
+    err = np.abs(hr.cpu().numpy() - ref).max()
+    _log(f"[3d tensor clamp] rho {rho}: max err {err:.3e} of scale {np.abs(ref).max():.3e}")
+    assert err <= 2e-6 * np.abs(ref).max() + 1e-9
+
+
 def _sym(p6):
     """The symmetric 3 x 3 matrix of six entries xx, yy, zz, xy, xz, yz."""
     return np.array([[p6[0], p6[3], p6[4]], [p6[3], p6[1], p6[5]], [p6[4], p6[5], p6[2]]])
