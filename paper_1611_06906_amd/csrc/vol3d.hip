@@ -687,6 +687,32 @@ __global__ __launch_bounds__(256) void eig3_kernel(const float *__restrict__ hr,
     const size_t m = (size_t)D * H * W;
     const double hxx = hr[v.o], hyy = hr[m + v.o], hzz = hr[2 * m + v.o];
     const double hxy = hr[3 * m + v.o], hxz = hr[4 * m + v.o], hyz = hr[5 * m + v.o];
+    float2 *p = (float2 *)(tens + 6 * v.o);   // 24 bytes per voxel, 8-byte aligned
+    if (mode == MF4D_BOTH) {
+        // Without the mode masks every mu_k is 1 / (1 + nu_k^2 / lambda^2), so
+        // P = (I + H^2 / lambda^2)^-1: the inverse of a symmetric positive
+        // definite M (eigenvalues >= 1), from its adjugate. The rounding of H^2
+        // enters M amplified by 1 / lambda^2, an error of about
+        // 1e-16 |H|^2 / lambda^2 in P; where that could exceed 1e-10 the
+        // eigenpairs below are used instead.
+        const double s = inv_lam2;
+        const double f2 = hxx * hxx + hyy * hyy + hzz * hzz + 2.0 * (hxy * hxy + hxz * hxz + hyz * hyz);
+        if (s * f2 <= 1e6) {
+            const double m00 = 1.0 + s * (hxx * hxx + hxy * hxy + hxz * hxz);
+            const double m11 = 1.0 + s * (hxy * hxy + hyy * hyy + hyz * hyz);
+            const double m22 = 1.0 + s * (hxz * hxz + hyz * hyz + hzz * hzz);
+            const double m01 = s * (hxx * hxy + hxy * hyy + hxz * hyz);
+            const double m02 = s * (hxx * hxz + hxy * hyz + hxz * hzz);
+            const double m12 = s * (hxy * hxz + hyy * hyz + hyz * hzz);
+            const double c00 = m11 * m22 - m12 * m12, c11 = m00 * m22 - m02 * m02, c22 = m00 * m11 - m01 * m01;
+            const double c01 = m02 * m12 - m01 * m22, c02 = m01 * m12 - m02 * m11, c12 = m01 * m02 - m00 * m12;
+            const double id = 1.0 / (m00 * c00 + m01 * c01 + m02 * c02);
+            p[0] = make_float2((float)(c00 * id), (float)(c11 * id));
+            p[1] = make_float2((float)(c22 * id), (float)(c01 * id));
+            p[2] = make_float2((float)(c02 * id), (float)(c12 * id));
+            return;
+        }
+    }
     const double a[3][3] = {{hxx, hxy, hxz}, {hxy, hyy, hyz}, {hxz, hyz, hzz}};
     double nu[3], q[3][3];
     sym3_eigenpairs(a, nu, q);
@@ -699,7 +725,6 @@ __global__ __launch_bounds__(256) void eig3_kernel(const float *__restrict__ hr,
         mu[k] = mk;
     }
     auto Pij = [&](int i, int j) { return mu[0] * q[i][0] * q[j][0] + mu[1] * q[i][1] * q[j][1] + mu[2] * q[i][2] * q[j][2]; };
-    float2 *p = (float2 *)(tens + 6 * v.o);   // 24 bytes per voxel, 8-byte aligned
     p[0] = make_float2((float)Pij(0, 0), (float)Pij(1, 1));
     p[1] = make_float2((float)Pij(2, 2), (float)Pij(0, 1));
     p[2] = make_float2((float)Pij(0, 2), (float)Pij(1, 2));

@@ -180,11 +180,13 @@ def _sym(p6):
     return np.array([[p6[0], p6[3], p6[4]], [p6[3], p6[1], p6[5]], [p6[4], p6[5], p6[2]]])
 
 
-@pytest.mark.parametrize("mode,lam", [(0, 0.005), (1, 0.01), (2, 0.005), (2, math.inf)])
+@pytest.mark.parametrize("mode,lam", [(0, 0.005), (1, 0.01), (2, 0.005), (2, math.inf), (2, 1e-5)])
 def test_dtensor3_action_parity(env, mode, lam):
     """The tensor planes against the oracle's literal 9 x 9 D built from the
     same H_rho: P equals D applied to the identity, and (P h + h P) / 2
-    equals D h for symmetric h."""
+    equals D h for symmetric h. In BOTH mode P is the inverse of
+    I + H^2 / lambda^2 where |H|^2 / lambda^2 <= 1e6 and comes from the
+    eigenpairs elsewhere (lambda = 1e-5: mostly the latter, both in a wave)."""
     m, o, torch = env["m"], env["o"], env["torch"]
     rng = np.random.default_rng(7 + mode)
     shape = (5, 6, 7)
