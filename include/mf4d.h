@@ -357,8 +357,9 @@ int mf4d_crease_match(const float *seg, const int8_t *type, int H, int W, const 
  *    at most 3 * 16 + 6 * 1 = 54, so 0 < tau_max <= 1/27.
  * Parameters are those of mf4d_params with tau_max <= 1/27, model =
  * MF4D_MAFOD, postprocess = 0, check = 0 and reselect_each_cycle = 1
- * (other values: MF4D_EINVAL). The eigen-solves run in FP64, everything else
- * in FP32. */
+ * (other values: MF4D_EINVAL). The eigen-solves (in BOTH mode, where every
+ * mu_k is 1 / (1 + nu_k^2 / lambda^2), mostly the inverse of
+ * I + H_rho^2 / lambda^2 instead) run in FP64, everything else in FP32. */
 
 /* Device workspace bytes of the calls below for a D x H x W volume (0 if the
  * sizes or params are invalid). */
