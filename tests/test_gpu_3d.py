@@ -263,6 +263,25 @@ def test_filter3_parity(env, mode):
     assert np.array_equal(ui.cpu().numpy(), u)   # the input is left alone
 
 
+def test_filter3_small_lambda(env):
+    """BOTH mode at lambda = 1e-5, where |H_rho|^2 / lambda^2 lies on both
+    sides of the bound that chooses between the inverse of
+    I + H_rho^2 / lambda^2 and the eigenpairs (about 43% of the voxels of the
+    first cycle take the inverse): the whole filter against the oracle."""
+    m, o, torch = env["m"], env["o"], env["torch"]
+    sig = [1.0, 1.5, 2.2]
+    u = _volume(env, (20, 26, 31), 77, 2)
+    p = m.Params(sig, mode=2, lam=1e-5, cycles=2, substeps=8, tau_max=TAU3)
+    ui = _to(env, u)
+    uo = torch.empty_like(ui)
+    m.mf4d3d_filter(ui, uo, p)
+    torch.cuda.synchronize()
+    ref = o.filter3(u, sig, 2, lam=1e-5, cycles=2, substeps=8)
+    ea, er = _err(uo.cpu().numpy(), ref)
+    _log(f"[3d filter] lambda 1e-5: max-abs {ea:.3e} rel-l2 {er:.3e}")
+    assert ea <= MAXABS and er <= RELL2
+
+
 @pytest.mark.parametrize("shape", [(3, 3, 3), (3, 5, 70), (5, 3, 4), (4, 66, 3)])
 def test_filter3_edge_shapes(env, shape):
     """The smallest volumes (one interior voxel or none along an axis) and
