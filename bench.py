@@ -30,8 +30,10 @@ Prints one JSON line:
   hbm_copy_probe  a plain 1 GiB device copy: the HBM rate the box reaches in practice
   cpu_baseline  the FP64 oracle on a bounded sample (the first 3 cycles of the same image)
   extensions  batched_256 (256 uneven images in one batch plan vs per-image
-            calls), learned_2048 (the learned selection vs the exact sweep)
-            and volume_256 (the filter on a 256^3 volume)
+            calls), learned_2048 (the learned selection vs the exact sweep),
+            volume_256 (the filter on a 256^3 volume) and aux_4096 (scale-image
+            postprocessing, l2-optimal stopping, crease extraction and matching
+            on the 4096^2 image)
 """
 from __future__ import annotations
 
@@ -288,6 +290,81 @@ def volume_comparison(torch, mf4d, synth, dev, reps=3):
                                  "kernel": "fed3_kernel (fused substep, 32 x 8 tiles streaming along z)"}}
 
 
+def _centreline_segments(lines):
+    """Ground-truth segments between consecutive centreline samples of the
+    generator's creases, as the matching takes them: (segs [n][4] as
+    (x0, y0, x1, y1), types [n] = the crease's sign)."""
+    import numpy as np
+    segs, types = [], []
+    for pts, sgn in lines:
+        pts = np.asarray(pts, np.float32)
+        if len(pts) >= 2:
+            segs.append(np.concatenate([pts[:-1], pts[1:]], axis=1))
+            types.append(np.full(len(pts) - 1, int(sgn), np.int32))
+    return np.ascontiguousarray(np.concatenate(segs)), np.ascontiguousarray(np.concatenate(types))
+
+
+def aux_comparison(torch, mf4d, synth, dev, reps=3, cycles=2):
+    """The paper's further steps on the 4096^2 creases image, each timed with
+    HIP events on the library's calls: scale-image postprocessing (Sec. 3.3,
+    theta = 0.13) and l2-optimal stopping against the noise-free image
+    (Sec. 4), as their cost per FED cycle over the plain filter (`cycles`
+    cycles of 20 substeps); crease extraction (Sec. 3.6) on the filtered
+    image and the matching of the ground-truth centreline segments (Sec. 4)
+    to its segments."""
+    import numpy as np
+    w = synth.creases4096()
+    t0 = time.time()
+    img, clean, lines = w.ground_truth()
+    print(f"[bench] aux: {w.name} with ground truth generated in {time.time() - t0:.1f}s", file=sys.stderr,
+          flush=True)
+    H, W = w.H, w.W
+    u = torch.from_numpy(img).to(dev)
+    gt = torch.from_numpy(clean).to(dev)
+    out = torch.empty_like(u)
+    p = mf4d.Params.from_workload(w, cycles=cycles)
+    pp = mf4d.Params.from_workload(w, cycles=cycles, postprocess=1, theta=0.13)
+    ws = mf4d.workspace(H, W, pp, dev)
+    l2 = torch.empty(cycles + 1, dtype=torch.float64, device=dev)
+    best = torch.empty(1, dtype=torch.int32, device=dev)
+    runs = {"plain": lambda: mf4d.mf4d_filter(u, out, p, ws),
+            "postprocess": lambda: mf4d.mf4d_filter(u, out, pp, ws),
+            "l2stop": lambda: mf4d.mf4d_filter_l2stop(u, out, p, gt, l2, best, ws)}
+    ms = {}
+    for k, f in runs.items():
+        f()
+        ms[k] = time_stream(torch, f, reps)
+    # extraction and matching on the plainly filtered image
+    runs["plain"]()
+    cws = torch.empty(int(mf4d.lib().mf4d_creases_workspace_bytes(H, W)), dtype=torch.uint8, device=dev)
+    seg = torch.empty((H - 1, W - 1, 2, 4), dtype=torch.float32, device=dev)
+    typ = torch.empty((H - 1, W - 1, 2), dtype=torch.int8, device=dev)
+    cre = lambda: mf4d.mf4d_creases(out, 1.0, 0.005, mf4d.MF4D_BOTH, seg, typ, ws=cws)
+    cre()
+    ms_cre = time_stream(torch, cre, reps)
+    gs, gt_types = _centreline_segments(lines)
+    gs_d, gtt_d = torch.from_numpy(gs).to(dev), torch.from_numpy(gt_types).to(dev)
+    dist = torch.empty(len(gs), dtype=torch.float32, device=dev)
+    match = torch.empty(len(gs), dtype=torch.int32, device=dev)
+    mat = lambda: mf4d.mf4d_crease_match(seg, typ, gs_d, gtt_d, 6.0, dist, match)
+    mat()
+    ms_mat = time_stream(torch, mat, reps)
+    torch.cuda.synchronize()
+    matched = float((match >= 0).float().mean().item())
+    # extraction reads u (4 B) and writes two segments and their types per cell (34 B)
+    cre_bytes = 4 * H * W + 34 * (H - 1) * (W - 1)
+    return {"image": [H, W], "cycles": cycles, "substeps": w.substeps,
+            "plain_filter_ms": ms["plain"],
+            "postprocess": {"filter_ms": ms["postprocess"],
+                            "ms_per_cycle_over_plain": (ms["postprocess"] - ms["plain"]) / cycles, "theta": 0.13},
+            "l2stop": {"filter_ms": ms["l2stop"], "ms_per_cycle_over_plain": (ms["l2stop"] - ms["plain"]) / cycles,
+                       "best_cycle": int(best.item())},
+            "creases": {"ms": ms_cre, "Mpx_per_s": H * W / (ms_cre * 1e-3) / 1e6,
+                        "algorithmic_GBs": cre_bytes / (ms_cre * 1e-3) / 1e9,
+                        "frac_hbm": cre_bytes / (ms_cre * 1e-3) / HBM_PEAK},
+            "match": {"ms": ms_mat, "gt_segments": len(gs), "matched_share": matched}}
+
+
 def _pool_image(args):
     """Training pool and test images of the learned comparison: fundus-type
     (config-2 recipe) or ridge-type (config-1 recipe, inverted so that its
@@ -432,7 +509,7 @@ def main():
     ap.add_argument("--no-stages", action="store_true")
     ap.add_argument("--no-extensions", action="store_true", help="skip the extension comparisons (batched, learned, volume)")
     ap.add_argument("--eager", action="store_true", help="time eager mf4d_filter calls instead of graph replays")
-    ap.add_argument("--only", choices=("batched", "learned", "volume"),
+    ap.add_argument("--only", choices=("batched", "learned", "volume", "aux"),
                     help="run only this extension comparison and print its JSON line (for profiling)")
     ap.add_argument("--learned-patches", type=int, default=20000, help="training crops of the learned comparison")
     args = ap.parse_args()
@@ -451,6 +528,8 @@ def main():
             res = batched_comparison(torch, mf4d, synth, dev)
         elif args.only == "learned":
             res = learned_comparison(torch, mf4d, synth, dev, patches=args.learned_patches)
+        elif args.only == "aux":
+            res = aux_comparison(torch, mf4d, synth, dev)
         else:
             res = volume_comparison(torch, mf4d, synth, dev)
         print(json.dumps({args.only: res}), flush=True)
@@ -621,6 +700,8 @@ def main():
         print(f"[bench] learned: {json.dumps(extensions['learned_2048'])}", file=sys.stderr, flush=True)
         extensions["volume_256"] = volume_comparison(torch, mf4d, synth, dev)
         print(f"[bench] volume: {json.dumps(extensions['volume_256'])}", file=sys.stderr, flush=True)
+        extensions["aux_4096"] = aux_comparison(torch, mf4d, synth, dev)
+        print(f"[bench] aux: {json.dumps(extensions['aux_4096'])}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:

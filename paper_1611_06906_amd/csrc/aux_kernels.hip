@@ -149,6 +149,11 @@ __global__ __launch_bounds__(256) void postprocess_kernel(const uint8_t *__restr
                                                           ScaleTable sig, float theta, int tmax,
                                                           uint8_t *__restrict__ out)
 {
+    // the scale table in LDS: the march looks it up with a per-lane index,
+    // which from the kernel arguments is a dependent memory load per step
+    __shared__ double ssig[MF4D_MAX_SCALES];
+    if (threadIdx.x < (unsigned)ns) ssig[threadIdx.x] = (double)sig.s[threadIdx.x];
+    __syncthreads();
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= W || y >= H) return;
@@ -177,20 +182,41 @@ __global__ __launch_bounds__(256) void postprocess_kernel(const uint8_t *__restr
         ex = -ey;
         ey = tx;
     }
-    double sum = (double)sig.s[s0];
+    double sum = ssig[s0];
     double cnt = 1.0;
+    // The march stops at the first step outside the image or off the vessel.
+    // Its loads are issued kPPChunk steps at a time (positions past the image
+    // or past tmax read the pixel itself and are never used), so the steps
+    // of a chunk wait for memory once instead of once each; the tests and the
+    // sums run in the same order as one step at a time.
+    constexpr int kPPChunk = 8;
     for (int dir = -1; dir <= 1; dir += 2) {
-        for (int t = 1; t <= tmax; ++t) {
-            const float ft = (float)(dir * t);
-            const int xx = x + (int)roundf(ft * ex);
-            const int yy = y + (int)roundf(ft * ey);
-            if (xx < 0 || xx >= W || yy < 0 || yy >= H) break;
-            const size_t q = (size_t)yy * W + xx;
-            if (!(vmax[q] >= theta)) break;
-            int sq = idx[q];
-            if (sq >= ns) sq = ns - 1;
-            sum += (double)sig.s[sq];
-            cnt += 1.0;
+        bool going = true;
+        for (int t0 = 1; going && t0 <= tmax; t0 += kPPChunk) {
+            float vq[kPPChunk];
+            int sq[kPPChunk];
+            bool inb[kPPChunk];
+#pragma unroll
+            for (int j = 0; j < kPPChunk; ++j) {
+                const int t = t0 + j;
+                const float ft = (float)(dir * t);
+                const int xx = x + (int)roundf(ft * ex);
+                const int yy = y + (int)roundf(ft * ey);
+                inb[j] = t <= tmax && xx >= 0 && xx < W && yy >= 0 && yy < H;
+                const size_t q = inb[j] ? (size_t)yy * W + xx : p;
+                vq[j] = vmax[q];
+                sq[j] = idx[q];
+            }
+#pragma unroll
+            for (int j = 0; j < kPPChunk; ++j) {
+                if (!going || !inb[j] || !(vq[j] >= theta)) {
+                    going = false;
+                    continue;
+                }
+                const int sj = sq[j] >= ns ? ns - 1 : sq[j];
+                sum += ssig[sj];
+                cnt += 1.0;
+            }
         }
     }
     int best = 0;
