@@ -33,3 +33,22 @@ def test_committed_profiles_match_the_kernel_sources():
     assert vol is not None and 32 * 256 ** 3 <= vol <= 2 * 32 * 256 ** 3
     assert "fed3_kernel sources sha256 prefix: " + bench.source_digest("fed3_kernel") in open(
         os.path.join(ROOT, "profiles", "volume256_kernel_trace.txt")).read()
+
+
+def test_bench_centreline_segments_match_the_oracle():
+    """The matching leg builds its ground-truth segments itself (the bench may
+    not call the oracle outside its CPU baseline): the same segments and
+    types as the oracle's construction, on the creases workload's centrelines
+    (at 512^2)."""
+    sys.path.insert(0, ROOT)
+    import numpy as np
+    import bench
+    import oracle
+    from paper_1611_06906_amd import synth
+    w = synth.creases4096(H=512, W=512)
+    _, _, lines = w.ground_truth()
+    segs, types = bench._centreline_segments(lines)
+    ref, ref_types = oracle.gt_segments(lines)
+    assert segs.shape == ref.shape and len(segs) > 1000
+    assert np.array_equal(types, ref_types)
+    assert np.array_equal(segs, ref.astype(np.float32))
