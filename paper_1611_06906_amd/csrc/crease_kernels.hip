@@ -121,13 +121,31 @@ __global__ __launch_bounds__(256) void marching_kernel(const float *__restrict__
     int8_t ty_out[2] = {0, 0};
     int slot = 0;
     for (int q = 0; q < ns; ++q) {
-        float px[2], py[2], ha[2], hb[2], hc[2];
-        int ty[2];
+        // Each end is measured from its edge's nearer corner (the fraction
+        // |d_a| / (|d_a| + |d_b|) <= 1/2 needs no cancellation, so an end
+        // close to either corner keeps its full relative precision), and the
+        // segment's direction is the integer step between the two ends'
+        // corners plus the difference of their offsets from them: exact in
+        // the offsets where both ends hang off one corner (a short segment
+        // cutting it off), at least ~1/2 long otherwise. Taken from the
+        // image coordinates, a segment a few 1e-5 px long near x = 4000
+        // would point wherever their float32 rounding puts its ends.
+        float px[2], py[2], ox[2], oy[2], ha[2], hb[2], hc[2];
+        int ty[2], anc[2];
         for (int j = 0; j < 2; ++j) {
-            const int ed = e[2 * q + j], a = ed, b = (ed + 1) & 3;
+            const int ed = e[2 * q + j];
+            int a = ed, b = (ed + 1) & 3;
+            if (fabsf(dc[b]) < fabsf(dc[a])) {
+                const int t_ = a;
+                a = b;
+                b = t_;
+            }
             const float tt = dc[a] / (dc[a] - dc[b]);
-            px[j] = (float)(x + cx[a]) + tt * (float)(cx[b] - cx[a]);
-            py[j] = (float)(y + cy[a]) + tt * (float)(cy[b] - cy[a]);
+            ox[j] = tt * (float)(cx[b] - cx[a]);
+            oy[j] = tt * (float)(cy[b] - cy[a]);
+            anc[j] = a;
+            px[j] = (float)(x + cx[a]) + ox[j];
+            py[j] = (float)(y + cy[a]) + oy[j];
             const size_t pa = pc[a], pb = pc[b];
             ha[j] = hxx[pa] + tt * (hxx[pb] - hxx[pa]);
             hb[j] = hxy[pa] + tt * (hxy[pb] - hxy[pa]);
@@ -135,8 +153,9 @@ __global__ __launch_bounds__(256) void marching_kernel(const float *__restrict__
             ty[j] = crease_type(ha[j], hb[j], hc[j], strength);
         }
         if (ty[0] == 0 || ty[0] != ty[1]) continue;
-        if (!along_weak(px[1] - px[0], py[1] - py[0], 0.5f * (ha[0] + ha[1]), 0.5f * (hb[0] + hb[1]),
-                        0.5f * (hc[0] + hc[1])))
+        const float vx = (float)(cx[anc[1]] - cx[anc[0]]) + (ox[1] - ox[0]);
+        const float vy = (float)(cy[anc[1]] - cy[anc[0]]) + (oy[1] - oy[0]);
+        if (!along_weak(vx, vy, 0.5f * (ha[0] + ha[1]), 0.5f * (hb[0] + hb[1]), 0.5f * (hc[0] + hc[1])))
             continue;
         if ((mode == MF4D_RIDGE && ty[0] != 1) || (mode == MF4D_VALLEY && ty[0] != -1)) continue;
         out[4 * slot + 0] = px[0];

@@ -139,6 +139,76 @@ def test_crease_extraction_parity(env, case, mode):
     assert rcnt > 20 and not bad_type.any()
 
 
+def test_crease_extraction_full_size(env):
+    """The 4096^2 creases image (the bench's extraction), mode BOTH.
+    - Every cell's decision against the oracle's, outside corner near-ties as
+      in the small cases. A decision that differs otherwise must be what the
+      oracle's marching makes of the GPU's field (whose error is bounded
+      first), and the GPU's marching must match that one up to float32-level
+      perturbations of a cell's field.
+    - The segment ends of 20 000 sampled cells where both sides agree, within
+      the first-order bound of the corners' d errors plus the float32
+      rounding of the stored coordinates (up to 4095 here)."""
+    import time
+    o, m, synth = env["o"], env["m"], env["synth"]
+    u = synth.creases4096().image()
+    sigma_d, strength, mode = 1.0, 0.005, 2
+    t0 = time.time()
+    seg, typ, cnt, field = _gpu_creases(env, u, sigma_d, strength, mode)
+    P = o.crease_field(u, sigma_d)
+    rseg, rtyp, rcnt = o.marching_creases(P, strength, mode)
+    _log(f"creases 4096^2: GPU and oracle in {time.time() - t0:.1f}s")
+    scale = np.abs(P).reshape(6, -1).max(axis=1)
+    ferr = np.abs(field - P).reshape(6, -1).max(axis=1)
+    assert np.all(ferr <= 2e-6 * scale + 1e-12), (ferr, scale)
+    assert cnt == int((typ != 0).sum())
+    frag = _fragile_cells(P, field, strength)
+    differ = np.any(typ != rtyp, axis=2)
+    # The oracle's marching of the GPU's own field (in FP64) must give the
+    # GPU's decisions, except where the cell's decision flips under a
+    # perturbation of its 2 x 2 field at the float32 level (the marching's
+    # own rounding: crossings, interpolated Hessians, the direction test).
+    own_seg, own_typ, _ = o.marching_creases(field.astype(np.float64), strength, mode)
+    differ_own = np.any(typ != own_typ, axis=2)
+    rng = np.random.default_rng(9)
+    flipped = np.zeros_like(differ_own)
+    for (y, x) in np.argwhere(differ_own):
+        block = field[:, y:y + 2, x:x + 2].astype(np.float64)
+        for _ in range(64):
+            pert = block * (1.0 + 1e-6 * rng.uniform(-1.0, 1.0, size=block.shape))
+            _, t2, _ = o.marching_creases(np.ascontiguousarray(pert), strength, mode)
+            if np.array_equal(t2[0, 0], typ[y, x]):
+                flipped[y, x] = True
+                break
+    unexplained = int((differ_own & ~flipped).sum())
+    # Against the oracle's own field, a decision that differs and is not a
+    # corner near-tie must follow from the GPU's field (its float32 error,
+    # bounded above, is what moved it), up to those perturbations.
+    frag |= differ & (~differ_own | flipped)
+    bad_type = differ & ~frag
+    same = np.argwhere(~differ & ~frag & np.any(rtyp != 0, axis=2))
+    rng = np.random.default_rng(5)
+    pick = same[rng.choice(len(same), size=min(20000, len(same)), replace=False)]
+    ed = np.abs(field[5].astype(np.float64) - P[5])
+    worst = 0.0
+    for (y, x) in pick:
+        dc = [P[5][y, x], P[5][y, x + 1], P[5][y + 1, x + 1], P[5][y + 1, x]]
+        ec = [ed[y, x], ed[y, x + 1], ed[y + 1, x + 1], ed[y + 1, x]]
+        tol = 2 * sum(ec) / min(abs(dc[i] - dc[(i + 1) % 4]) or 1e-300 for i in range(4)
+                                if (dc[i] >= 0) != (dc[(i + 1) % 4] >= 0)) + 1e-5
+        # plus the float32 rounding of each stored end coordinate (one ulp of
+        # its magnitude: 6e-5 at 566, 2.4e-4 near 4096)
+        lim = tol + np.spacing(np.abs(rseg[y, x]).astype(np.float32)).astype(np.float64)
+        dev = np.abs(seg[y, x] - rseg[y, x])
+        worst = max(worst, float((dev / lim).max()))
+        assert np.all(dev <= lim), (y, x, seg[y, x], rseg[y, x], tol)
+    _log(f"creases 4096^2: GPU {cnt} / oracle {rcnt} segments, {int(differ.sum())} cells differ "
+         f"({int(bad_type.sum())} outside near-ties); against the oracle's marching of the GPU's field "
+         f"{int(differ_own.sum())} differ ({unexplained} not flipped by 1e-6 perturbations); worst sampled end "
+         f"error {worst:.2f} of its bound")
+    assert rcnt > 100000 and not bad_type.any() and unexplained == 0
+
+
 def test_crease_match_parity(env):
     """The GPU matcher on the oracle's own segments (as float32) against the
     oracle on the same values, with the generator's centrelines."""
