@@ -248,6 +248,41 @@ def test_crease_match_parity(env):
     assert abs(E - Er) <= 1e-4 and abs(p - pr) <= 2.0 / len(gts)
 
 
+def test_crease_match_full_size(env):
+    """The matcher at the bench's size: the 555k centreline segments of the
+    4096^2 image against the GPU's 6.3M extracted segments (as float32, the
+    same values on both sides), GPU against oracle. A pick that differs must
+    be a near-tie at the float32 resolution of coordinates up to 4096."""
+    o, m, torch = env["o"], env["m"], env["torch"]
+    w = env["synth"].creases4096()
+    u, clean, lines = w.ground_truth()
+    seg, typ = m.mf4d_creases(_to(env, u), 1.0, 0.005, 2)
+    gts, gtt = o.gt_segments(lines)
+    gts32 = gts.astype(np.float32)
+    dist, match = m.mf4d_crease_match(seg, typ, _to(env, gts32), _to(env, gtt.astype(np.int32)), 6.0)
+    torch.cuda.synchronize()
+    seg32, typ8 = seg.cpu().numpy(), typ.cpu().numpy()
+    dist, match = dist.cpu().numpy(), match.cpu().numpy()
+    dist_ref, match_ref = o.crease_match(seg32.astype(np.float64), typ8, gts32.astype(np.float64), gtt, 6.0)
+    tol = 8 * np.finfo(np.float32).eps * max(u.shape)
+    flat = seg32.reshape(-1, 4).astype(np.float64)
+    diff = np.argwhere(match != match_ref).ravel()
+    for i in diff:
+        G = gts32[i].astype(np.float64)
+        if match[i] < 0 or match_ref[i] < 0:   # at the edge of the neighbourhood
+            k = match[i] if match[i] >= 0 else match_ref[i]
+            assert abs(o.segment_hausdorff(G, flat[k]) - 6.0) <= tol
+            continue
+        assert abs(o.segment_hausdorff(G, flat[match[i]]) - o.segment_hausdorff(G, flat[match_ref[i]])) <= tol
+    ok = (match == match_ref) & (match >= 0)
+    assert np.allclose(dist[ok], dist_ref[ok], atol=tol)
+    E, p = o.crease_scores(dist)
+    Er, pr = o.crease_scores(dist_ref)
+    _log(f"match 4096^2: {len(gts)} ground-truth segments, {len(diff)} near-tie picks; E {E:.4f} / {Er:.4f}, "
+         f"p {p:.4f} / {pr:.4f}")
+    assert len(gts) > 500000 and abs(E - Er) <= 1e-4 and abs(p - pr) <= 2.0 / len(gts) + len(diff) / len(gts)
+
+
 def test_crease_pipeline_on_filtered_image(env):
     """End to end on ridges128: the filter, the extraction and the matching
     all on the GPU, against the oracle's three steps; E and p agree to the
