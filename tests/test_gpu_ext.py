@@ -191,6 +191,78 @@ def test_postprocess_select_parity(env, mode, theta):
     assert changed > 0 and not bad
 
 
+def _sign_tie(o, u, sig, g, y, x):
+    """Is the sign test at scale g a near-tie at (y, x): |trace| of sigma^2 H
+    within 1e-5 of its norm? H from a crop that holds the pixel's whole
+    support (the blur's radius plus the derivative stencil), so its values
+    are those of the whole image."""
+    s = float(np.float32(sig[g]))
+    r = int(math.ceil(3 * s)) + 3
+    H, W = u.shape
+    y0, y1, x0, x1 = max(0, y - r), min(H, y + r + 1), max(0, x - r), min(W, x + r + 1)
+    crop = np.ascontiguousarray(u[y0:y1, x0:x1].astype(np.float64))
+    hxx, hxy, hyy = o.derivatives(o.blur(crop, s))[2:]
+    a, b, c = hxx[y - y0, x - x0], hxy[y - y0, x - x0], hyy[y - y0, x - x0]
+    return abs(a + c) <= 1e-5 * math.sqrt(a * a + c * c + 2 * b * b)
+
+
+def test_postprocess_select_full_size(env):
+    """Postprocessed scale indices on the 4096^2 image of the bench (8 scales
+    1..16, both modes, theta = 0.13), in two parts.
+    - The raw indices (postprocess = 0) against the oracle's: a difference
+      only at a stated near-tie (V gap, or the sign test at the GPU's scale).
+    - The postprocessed indices against the oracle's postprocessing of the
+      GPU's own raw indices, vmax and the cross directions at them: a
+      difference only at a near-tie of the march (vesselness at theta, the
+      direction turned by 1e-4 rad, a sample's argmax, the mean sigma at a
+      midpoint).
+    Differences against the oracle's whole pipeline follow from the two."""
+    import time
+    m, o, torch, synth = env["m"], env["o"], env["torch"], env["synth"]
+    w = synth.creases4096()
+    u = w.image()
+    theta = 0.13
+    H, W = u.shape
+
+    def select(pp):
+        p = m.Params.from_workload(w, postprocess=pp, theta=theta)
+        idx = torch.empty((H, W), dtype=torch.uint8, device=env["dev"])
+        vmax = torch.empty((H, W), dtype=torch.float32, device=env["dev"])
+        m.mf4d_scale_select(_to(env, u), p, idx, vmax)
+        torch.cuda.synchronize()
+        return idx.cpu().numpy(), vmax.cpu().numpy()
+    gi_pp, gv = select(1)
+    gi_raw, _ = select(0)
+    t0 = time.time()
+    sel = o.scale_select_postprocessed(u, w.sigmas, w.mode, theta)
+    _log(f"postprocess 4096^2: oracle in {time.time() - t0:.1f}s")
+    tmax = int(math.ceil(3 * float(np.float32(w.sigmas[-1]))))
+    assert np.abs(gv - sel["vmax"]).max() <= 1e-5
+    # raw indices
+    V = sel["V"]
+    raw_diff = np.argwhere(gi_raw != sel["idx_raw"])
+    raw_bad = 0
+    for y, x in raw_diff:
+        g = int(gi_raw[y, x])
+        vm = V[:, y, x].max()
+        if V[g, y, x] >= vm - (1e-5 + 1e-4 * vm) or _sign_tie(o, u, w.sigmas, g, y, x):
+            continue
+        raw_bad += 1
+    # the postprocessing of the GPU's raw data
+    ex, ey = o.cross_direction(u, gi_raw, w.sigmas)
+    own = o.postprocess(gi_raw, gv.astype(np.float64), ex, ey, w.sigmas, theta)
+    own_sel = dict(V=V, vmax=gv.astype(np.float64), idx_raw=gi_raw, ex=ex, ey=ey)
+    own_diff = np.argwhere(gi_pp != own)
+    own_bad = [(y, x) for y, x in own_diff if not _fragile(own_sel, w.sigmas, theta, y, x, tmax)]
+    nvessel = int((sel["vmax"] >= theta).sum())
+    changed = int((sel["idx"] != sel["idx_raw"]).sum())
+    total = int((gi_pp != sel["idx"]).sum())
+    _log(f"postprocess 4096^2: {nvessel} vessel px, {changed} re-assigned; raw indices: {len(raw_diff)} differ, "
+         f"{raw_bad} not near-ties; against the postprocessing of the GPU's raw data: {len(own_diff)} differ, "
+         f"{len(own_bad)} not near-ties; against the oracle's pipeline: {total} differ")
+    assert changed > 1000 and raw_bad == 0 and not own_bad
+
+
 def test_postprocess_filter_parity(env):
     """The whole filter with postprocessing on ridges128 (5 x 10)."""
     m, o = env["m"], env["o"]
