@@ -309,6 +309,58 @@ def test_l2stop_parity(env):
             np.array_equal(uo.cpu().numpy(), u)
 
 
+def test_l2stop_full_size(env):
+    """l2-optimal stopping on the 4096^2 image of the bench against its
+    noise-free version, 2 cycles of 20 substeps: the distances, the chosen
+    cycle and the returned state against the oracle (max-abs outside the
+    reach of stated near-tie picks of the scale, as in the one-cycle test of
+    the plain filter at this size)."""
+    import time
+    m, o, torch = env["m"], env["o"], env["torch"]
+    w = env["synth"].creases4096()
+    u, gt, _ = w.ground_truth()
+    cycles = 2
+    p = m.Params.from_workload(w, cycles=cycles)
+    ui, gi = _to(env, u), _to(env, gt)
+    uo = torch.empty_like(ui)
+    l2 = torch.empty(cycles + 1, dtype=torch.float64, device=env["dev"])
+    best = torch.empty(1, dtype=torch.int32, device=env["dev"])
+    m.mf4d_filter_l2stop(ui, uo, p, gi, l2, best)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    ub, e_ref, k_ref = o.filter_l2stop(u, gt, w.sigmas, w.mode, cycles, lam=w.lam, rho=w.rho, beta=w.beta,
+                                       substeps=w.substeps, tau_max=w.tau_max)
+    e, k = l2.cpu().numpy(), int(best.item())
+    _log(f"l2 stop 4096^2: oracle in {time.time() - t0:.1f}s, k* {k_ref} e {e_ref.round(4).tolist()}, GPU k* {k}")
+    assert np.allclose(e, e_ref, rtol=2e-5, atol=0)
+    assert e_ref[k] <= e_ref[k_ref] * (1 + 2e-5)
+    assert k == k_ref == 1
+    # The state after one cycle: where the first selection picked another
+    # scale at a stated near-tie, N and H_rho change within the rho radius
+    # and each substep reaches 2 px further; the max-abs bound holds outside
+    # that reach, the relative L2 bound everywhere.
+    from scipy import ndimage
+    H, W = u.shape
+    gidx = torch.empty((H, W), dtype=torch.uint8, device=env["dev"])
+    m.mf4d_scale_select(ui, p, gidx)
+    torch.cuda.synchronize()
+    gidx = gidx.cpu().numpy()
+    sel = o.scale_select(u, w.sigmas, w.mode)
+    flips = np.argwhere(gidx != sel["idx"])
+    V = sel["V"]
+    for y, x in flips:
+        g, vm = int(gidx[y, x]), V[:, y, x].max()
+        assert V[g, y, x] >= vm - (1e-5 + 1e-4 * vm) or _sign_tie(o, u, w.sigmas, g, y, x), (y, x)
+    reach = 2 + 2 * w.substeps
+    near = ndimage.maximum_filter((gidx != sel["idx"]).astype(np.uint8), size=2 * reach + 1) > 0
+    d = np.abs(uo.cpu().numpy().astype(np.float64) - ub)
+    e_far = float(d[~near].max())
+    _, rr = _err(uo.cpu().numpy(), ub)
+    _log(f"l2 stop 4096^2: state at k*: {len(flips)} near-tie picks, max-abs {d.max():.3e} "
+         f"({e_far:.3e} outside their reach), rel-l2 {rr:.3e}")
+    assert e_far <= MAXABS and rr <= RELL2
+
+
 def test_l2stop_identities_gpu(env):
     """Ground truth = input: stop at cycle 0 with distance 0, output = input."""
     m, torch = env["m"], env["torch"]
