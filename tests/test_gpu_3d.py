@@ -263,6 +263,61 @@ def test_filter3_parity(env, mode):
     assert np.array_equal(ui.cpu().numpy(), u)   # the input is left alone
 
 
+def test_filter3_full_size_block(env):
+    """One cycle of the bench's volume filter (256^3, 24 tubes, 4 scales
+    1..3.375, both modes, 10 substeps) against the oracle on a 96^3 block of
+    it, given the GPU's image-wide c: the selection within 12 voxels of the
+    block's faces and the output within 34 (the derivative support 11 + 1,
+    the integration radius 2 and 2 per substep) depend only on the block, so
+    there the oracle's values are those of the whole volume. Indices exact
+    up to stated near-ties; the output within the image tolerances outside
+    the reach of such picks."""
+    import time
+    from scipy import ndimage
+    m, o, torch = env["m"], env["o"], env["torch"]
+    D = H = W = 256
+    v = env["synth"].tubes3d(D, H, W, 24, seed=0, signs="mixed", width_range=(1.0, 3.0))
+    sig = [1.5 ** k for k in range(4)]
+    p = m.Params(sig, mode=2, cycles=1, substeps=10, tau_max=TAU3)
+    vi = _to(env, v)
+    vo = torch.empty_like(vi)
+    m.mf4d3d_filter(vi, vo, p)
+    idx = torch.empty(v.shape, dtype=torch.uint8, device=env["dev"])
+    c = torch.empty(1, dtype=torch.float32, device=env["dev"])
+    m.mf4d3d_scale_select(vi, p, idx, None, c)
+    torch.cuda.synchronize()
+    gc = float(c.item())
+    z0 = y0 = x0 = 96
+    n = 96
+    blk = np.ascontiguousarray(v[z0:z0 + n, y0:y0 + n, x0:x0 + n])
+    t0 = time.time()
+    sel = o.scale_select3(blk, sig, 2, c=gc)
+    ref = o.filter3(blk, sig, 2, c=gc, cycles=1, substeps=10)
+    _log(f"[3d block] oracle on 96^3 in {time.time() - t0:.1f}s, c {gc:.6g}")
+    a, b = 12, n - 12
+    gi = idx.cpu().numpy()[z0:z0 + n, y0:y0 + n, x0:x0 + n]
+    sel_in = np.zeros(gi.shape, bool)
+    sel_in[a:b, a:b, a:b] = True
+    gi_in = np.where(sel_in, gi, sel["idx"])   # the faces' zone is the block's own, not the volume's
+    ndiff, bad = _near_ties(env, blk, sig, gi_in, sel)
+    assert not bad, bad[:5]
+    flips = gi_in != sel["idx"]
+    flips_in = flips
+    got = vo.cpu().numpy()[z0:z0 + n, y0:y0 + n, x0:x0 + n].astype(np.float64)
+    r = 34
+    reach = 2 + 2 * 10
+    near = ndimage.maximum_filter(flips.astype(np.uint8), size=2 * reach + 1) > 0
+    inner = np.zeros_like(near)
+    inner[r:n - r, r:n - r, r:n - r] = True
+    d = np.abs(got - ref)
+    e_far = float(d[inner & ~near].max())
+    rel = float(np.linalg.norm((got - ref)[inner]) / np.linalg.norm(ref[inner]))
+    _log(f"[3d block] {int(flips_in.sum())} index differences in the selection interior ({int(sel_in.sum())} voxels); "
+         f"output interior {int(inner.sum())} voxels: max-abs {float(d[inner].max()):.3e} "
+         f"({e_far:.3e} outside the reach of differing picks), rel-L2 {rel:.3e}")
+    assert e_far <= MAXABS and rel <= RELL2
+
+
 def test_filter3_small_lambda(env):
     """BOTH mode at lambda = 1e-5, where |H_rho|^2 / lambda^2 lies on both
     sides of the bound that chooses between the inverse of
