@@ -203,6 +203,12 @@ __global__ __launch_bounds__(256) void crease_match_kernel(const float *__restri
     y0 = max(y0, 0);
     x1 = min(x1, W - 2);
     y1 = min(y1, H - 2);
+    // Distances are taken in coordinates relative to the segment's first end:
+    // every point compared lies within a few pixels of it, so the offsets are
+    // exact float32 differences (of values within a factor of two of each
+    // other, or small) and the distances keep float32's relative precision,
+    // instead of an absolute error of the coordinates' ulp (2.4e-4 near 4096).
+    const float l1x = g1x - g0x, l1y = g1y - g0y;
     float best = INFINITY;
     int bm = -1;
     for (int y = y0; y <= y1; ++y)
@@ -211,8 +217,8 @@ __global__ __launch_bounds__(256) void crease_match_kernel(const float *__restri
                 const size_t c = (size_t)y * (W - 1) + x;
                 if (type[2 * c + sl] != gtt) continue;
                 const float *R = seg + 8 * c + 4 * sl;
-                const float h = fmaxf(point_segment(g0x, g0y, R[0], R[1], R[2], R[3]),
-                                      point_segment(g1x, g1y, R[0], R[1], R[2], R[3]));
+                const float ax = R[0] - g0x, ay = R[1] - g0y, bx = R[2] - g0x, by = R[3] - g0y;
+                const float h = fmaxf(point_segment(0.f, 0.f, ax, ay, bx, by), point_segment(l1x, l1y, ax, ay, bx, by));
                 if (h <= radius && h < best) {
                     best = h;
                     bm = (int)(2 * c + sl);
@@ -224,7 +230,7 @@ __global__ __launch_bounds__(256) void crease_match_kernel(const float *__restri
         return;
     }
     const float *R = seg + 4 * (size_t)bm;
-    dist[i] = point_segment(0.5f * (g0x + g1x), 0.5f * (g0y + g1y), R[0], R[1], R[2], R[3]);
+    dist[i] = point_segment(0.5f * l1x, 0.5f * l1y, R[0] - g0x, R[1] - g0y, R[2] - g0x, R[3] - g0y);
 }
 
 }  // namespace

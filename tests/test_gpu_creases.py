@@ -252,7 +252,7 @@ def test_crease_match_full_size(env):
     """The matcher at the bench's size: the 555k centreline segments of the
     4096^2 image against the GPU's 6.3M extracted segments (as float32, the
     same values on both sides), GPU against oracle. A pick that differs must
-    be a near-tie at the float32 resolution of coordinates up to 4096."""
+    be a near-tie within 1e-5 px, and the distances agree to 1e-5."""
     o, m, torch = env["o"], env["m"], env["torch"]
     w = env["synth"].creases4096()
     u, clean, lines = w.ground_truth()
@@ -264,7 +264,9 @@ def test_crease_match_full_size(env):
     seg32, typ8 = seg.cpu().numpy(), typ.cpu().numpy()
     dist, match = dist.cpu().numpy(), match.cpu().numpy()
     dist_ref, match_ref = o.crease_match(seg32.astype(np.float64), typ8, gts32.astype(np.float64), gtt, 6.0)
-    tol = 8 * np.finfo(np.float32).eps * max(u.shape)
+    # distances in float32 from offsets of a few pixels (the GPU measures
+    # them from the ground-truth segment's first end)
+    tol = 1e-5
     flat = seg32.reshape(-1, 4).astype(np.float64)
     diff = np.argwhere(match != match_ref).ravel()
     for i in diff:
