@@ -5,11 +5,15 @@
 // (Eq. (21)) of the operator L^T D L with the 3-D second-difference stencils
 // and natural boundaries. Volumes are float32 [D][H][W], x fastest.
 //
-// Every kernel maps one thread to one voxel: blocks of 64 x 4 threads over
-// (x, y), one z plane per grid layer, so each wave reads and writes 64
-// consecutive floats of a row. The separable passes read their taps along
-// the pass axis straight from global memory (the rows a block touches stay
-// in L1/L2); the eigen-solves run in FP64.
+// Kernels: the sweep's z and y passes produce 8 outputs per thread along the
+// pass through register windows, the x pass stages its block's rows in LDS
+// and ends in the per-voxel tube factor and N planes; the argmax and the
+// eigen-solves map one thread to one voxel (blocks of 64 x 4 threads over
+// (x, y), one z plane per grid layer, so a wave reads and writes 64
+// consecutive floats of a row); the integration and the FED substep march
+// along z over tiles of (x, y) with LDS and register rings. The eigen-solves
+// (or, without the mode masks, the inverse that replaces them) run in FP64;
+// the tensor is stored as the six entries of P = Q diag(mu) Q^T.
 #include <cmath>
 #include <cstring>
 #include <vector>
